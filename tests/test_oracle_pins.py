@@ -1,0 +1,337 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these tests retypes an oracle formula: each compares the oracle with
+an independent construction (printed values of the paper's worked examples,
+the textbook Sylvester matrix, a library FFT or Hadamard routine, brute force,
+finite differences, torch autograd) chosen so that a dropped term, a wrong
+sign or index, a missing conjugate or a transposed operand fails at least one.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from conftest import read_golden
+from oracle import gtt_oracle as O
+from paper_2507_02420_amd.inputs import (dft_matrix, gaussian, hadamard2, haar_unitary,
+                                         int_uniform, u3)
+
+
+# --------------------------------------------------------------------------
+# Hadamard reduction (§2.6): Sylvester-Walsh-Hadamard matrix in natural order
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_hadamard_is_sylvester(n):
+    N = 1 << n
+    # the bit-count builder is itself pinned to scipy's Sylvester construction
+    assert np.array_equal(O.sylvester_hadamard(n), scipy.linalg.hadamard(N))
+    G = O.kron_power(hadamard2(True), n)
+    np.testing.assert_allclose(G, O.sylvester_hadamard(n) / np.sqrt(N), rtol=0, atol=1e-13)
+    x = gaussian(N, seed=11)
+    ref = scipy.linalg.hadamard(N) @ x / np.sqrt(N)
+    for y in (O.staged(hadamard2(True), x, n), O.fastgtt_rec(x, hadamard2(True), n),
+              O.dense(hadamard2(True), x, n)):
+        np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.linalg.norm(ref))
+
+
+# --------------------------------------------------------------------------
+# §2.2 recursive basis functions sampled at midpoints (§2.6) == Def. 2.4
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b,n,seed", [(2, 3, 1), (3, 2, 2), (4, 2, 3), (2, 4, 4)])
+def test_basis_function_discretization_equals_kron(b, n, seed):
+    W = haar_unitary(b, seed)
+    G1 = O.gtt_matrix_from_basis(W, n)
+    G2 = O.kron_power(W, n)
+    np.testing.assert_allclose(G1, G2, rtol=0, atol=1e-14)
+    # Theorem 2.2: the sampled matrix is unitary
+    np.testing.assert_allclose(G1.conj().T @ G1, np.eye(b ** n), atol=1e-13)
+
+
+def test_basis_function_values_u3_walsh():
+    # theta = pi/2, phi = 0, lambda = pi gives the normalized Hadamard (§2.3.1),
+    # whose basis functions are Walsh functions: +-1/sqrt(N) piecewise constant.
+    W = u3(np.pi / 2, 0.0, np.pi)
+    np.testing.assert_allclose(W, hadamard2(True), atol=1e-15)
+    n = 3
+    for j in range(8):
+        for p in range(8):
+            v = O.basis_function(j, (2 * p + 1) / 16, W, n)
+            assert abs(v - ((-1) ** bin(p & j).count("1")) / np.sqrt(8)) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Printed G_8 for W = U3(pi/4, pi/3, pi/6) (§4.1.5)
+# --------------------------------------------------------------------------
+def test_printed_g8_all_constructions():
+    G_print = np.array(read_golden("g8_u3.txt")["_rows"], dtype=np.complex128)
+    assert G_print.shape == (8, 8)
+    W = u3(np.pi / 4, np.pi / 3, np.pi / 6)
+    # printed W (§4.1.5): [[0.924, -0.331-0.191i], [0.191+0.331i, 0.924i]]
+    # 3-decimal rounding of re and im: |error| <= 5e-4 * sqrt(2)
+    np.testing.assert_allclose(W, [[0.924, -0.331 - 0.191j], [0.191 + 0.331j, 0.924j]], atol=7.1e-4)
+    I8 = np.eye(8)
+    cands = {
+        "kron": O.kron_power(W, 3),
+        "basis": O.gtt_matrix_from_basis(W, 3),
+        "staged": O.staged(W, I8, 3).T,           # column q = G e_q
+        "rec": np.stack([O.fastgtt_rec(I8[q], W, 3) for q in range(8)], axis=1),
+        "rows": np.stack([O.row(W, p, 3) for p in range(8)], axis=0),
+        "entry": np.array([[O.entry(W, p, q, 3) for q in range(8)] for p in range(8)]),
+    }
+    for name, G in cands.items():
+        err = np.max(np.abs(G - G_print))
+        assert err < 7.1e-4, (name, err)
+    # the printed matrix is not symmetric under transposition: a transposed
+    # operand anywhere would fail
+    assert np.max(np.abs(G_print - G_print.T)) > 0.1
+
+
+# --------------------------------------------------------------------------
+# State S1 example (§4.1.5): forward, reconstruction, Hadamard comparison
+# --------------------------------------------------------------------------
+def test_s1_compression_example():
+    d = read_golden("s1_compression.txt")
+    W = u3(np.pi / 4, np.pi / 3, np.pi / 6)
+    psi = np.array(d["psi"])
+    y = O.staged(W, psi, 3)
+    np.testing.assert_allclose(y, np.array(d["gtt"]), rtol=0, atol=1.5e-3)
+    # inverse with G^dagger of the printed sparse state returns psi
+    x = O.adjoint(W, np.array(d["gtt"]), 3)
+    np.testing.assert_allclose(x, np.array(d["recon"]), rtol=0, atol=1.5e-3)
+    h = O.staged(hadamard2(True), psi, 3)
+    np.testing.assert_allclose(h, np.array(d["hadamard"]), rtol=0, atol=1.5e-3)
+
+
+def test_table1_hadamard_column_and_topk():
+    d = read_golden("table1_hadamard.txt")
+    H = hadamard2(True)
+    for lab in ("S1", "S2", "S3"):
+        vals = d[lab]
+        psi = np.array(vals[:8])
+        F_print = vals[8].real
+        keep, kept, recon = O.topk_compress(H, psi, 3, 2)
+        coeffs = O.staged(H, psi, 3)
+        F = O.kept_energy(kept, coeffs)
+        assert abs(F - F_print) < 1.5e-3, (lab, F, F_print)
+        # the fidelity of the reconstruction equals the kept energy (unitary G)
+        assert abs(O.fidelity(psi, recon) - F) < 1e-12
+    # GTT compression of S1 keeps indices 0 and 3 (§4.1.5, item 4)
+    W = u3(np.pi / 4, np.pi / 3, np.pi / 6)
+    keep, kept, recon = O.topk_compress(W, np.array(d["S1"][:8]), 3, 2)
+    assert list(keep) == [0, 3]
+    assert O.fidelity(np.array(d["S1"][:8]), recon) > 0.999
+
+
+# --------------------------------------------------------------------------
+# Filtering example (§4.3.2): spectrum, low-pass and high-pass outputs
+# --------------------------------------------------------------------------
+def test_filter_example():
+    d = read_golden("filter_example.txt")
+    W = u3(np.pi / 4, 0.0, np.pi)
+    np.testing.assert_allclose(W.imag, 0, atol=1e-15)
+    W = W.real
+    psi = np.array(d["psi"])
+    psi = psi / np.linalg.norm(psi)
+    spec = O.staged(W, psi, 4)
+    np.testing.assert_allclose(spec, d["spectrum"], rtol=0, atol=6e-5)
+    lo, hi = O.natural_filter(W, psi, 4, 4)
+    np.testing.assert_allclose(lo, d["low"], rtol=0, atol=6e-5)
+    np.testing.assert_allclose(hi, d["high"], rtol=0, atol=6e-5)
+    # the two channels add back to the signal
+    np.testing.assert_allclose(lo + hi, psi, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# GTT-Fourier example (§2.5.1): exact complex adjoint
+# --------------------------------------------------------------------------
+def test_fourier_example_adjoint():
+    W = np.array([[1, 1j], [1, -1j]]) / np.sqrt(2)
+    g = np.array([1.0, 0.0])
+    C = O.adjoint(W, g, 1) / np.sqrt(2)
+    np.testing.assert_allclose(C, [0.5, -0.5j], rtol=0, atol=1e-15)
+    # a transpose instead of the conjugate transpose would give (1/2, +i/2)
+    C_wrong = O.staged(W.T, g, 1) / np.sqrt(2)
+    assert abs(C_wrong[1] - (-0.5j)) > 0.5
+
+
+# --------------------------------------------------------------------------
+# Unitarity (Theorems 2.1, 2.2): norm preservation and G^H G = I
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b,n", [(2, 11), (3, 7), (4, 5), (5, 4), (8, 4), (7, 3)])
+def test_unitary_invariants(b, n):
+    W = haar_unitary(b, seed=100 + b)
+    x = gaussian((3, b ** n), seed=200 + b, complex_=True)
+    y = O.staged(W, x, n)
+    np.testing.assert_allclose(np.linalg.norm(y, axis=1), np.linalg.norm(x, axis=1), rtol=1e-13)
+    np.testing.assert_allclose(O.adjoint(W, y, n), x, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Entrywise product formula (§2.6) against the dense matrix and at size
+# --------------------------------------------------------------------------
+def test_entry_formula_matches_kron():
+    W = haar_unitary(3, seed=5)
+    G = O.kron_power(W, 3)
+    for p in range(27):
+        for q in range(27):
+            assert abs(O.entry(W, p, q, 3) - G[p, q]) < 1e-15
+
+
+def test_sampled_rows_at_size():
+    b, n = 4, 8
+    W = haar_unitary(b, seed=7)
+    x = gaussian(b ** n, seed=8, complex_=True)
+    y = O.staged(W, x, n)
+    ps = [0, 1, 5, 4 ** 8 - 1, 12345, 54321]
+    np.testing.assert_allclose(O.rows(W, x, n, ps), y[ps], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# DFT base matrix: the GTT is the multidimensional DFT (library routine)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b,n", [(2, 8), (3, 5), (4, 4), (5, 3), (3, 13)])
+def test_dft_base_matrix_is_fftn(b, n):
+    x = gaussian(b ** n, seed=9, complex_=True)
+    y = O.staged(dft_matrix(b), x, n)
+    ref = np.fft.fftn(x.reshape([b] * n), norm="ortho").reshape(-1)
+    np.testing.assert_allclose(y, ref, atol=1e-12 * np.linalg.norm(ref) / np.sqrt(x.size) * 10)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 literal recursion == dense Kronecker == staged passes
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b,n", [(2, 10), (3, 6), (4, 5), (8, 3), (16, 2)])
+def test_rec_dense_staged_agree(b, n):
+    W = haar_unitary(b, seed=10 + b)
+    x = gaussian(b ** n, seed=20 + b, complex_=True)
+    y1 = O.fastgtt_rec(x, W, n)
+    y2 = O.dense(W, x, n)
+    y3 = O.staged(W, x, n)
+    np.testing.assert_allclose(y1, y2, atol=1e-13)
+    np.testing.assert_allclose(y3, y2, atol=1e-13)
+
+
+def test_identity_cases():
+    W = haar_unitary(3, seed=1)
+    x = gaussian(1, seed=2, complex_=True)
+    # n = 0: N = 1, the transform is the identity (base case of §2.2)
+    np.testing.assert_allclose(O.staged(W, x, 0), x)
+    np.testing.assert_allclose(O.fastgtt_rec(x, W, 0), x)
+    # W = I gives the identity at any size
+    x = gaussian(3 ** 6, seed=3)
+    np.testing.assert_allclose(O.staged(np.eye(3), x, 6), x)
+
+
+# --------------------------------------------------------------------------
+# Gradients: finite differences, torch autograd, and the unitary identity
+# --------------------------------------------------------------------------
+def test_grad_vs_finite_differences():
+    b, n = 8, 3
+    W = haar_unitary(b, seed=44)
+    x = gaussian(b ** n, seed=45, complex_=True)
+    g = gaussian(b ** n, seed=46, complex_=True)
+    gx, gW = O.grad(W, x, g, n)
+    fx, fW = O.fd_grad(W, x, g, n)
+    assert np.linalg.norm(gx - fx) / np.linalg.norm(fx) < 1e-6
+    assert np.linalg.norm(gW - fW) / np.linalg.norm(fW) < 1e-6
+
+
+def test_grad_vs_finite_differences_nonunitary_real():
+    b, n = 3, 3
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((b, b))          # not orthogonal
+    x = rng.standard_normal(b ** n)
+    g = rng.standard_normal(b ** n)
+    gx, gW = O.grad(W, x, g, n)
+    fx, fW = O.fd_grad(W, x, g, n)
+    np.testing.assert_allclose(gx, fx.real, atol=1e-7)
+    np.testing.assert_allclose(gW, fW.real, atol=1e-7)
+
+
+def test_grad_vs_torch_autograd():
+    torch = pytest.importorskip("torch")
+    b, n = 4, 3
+    W = haar_unitary(b, seed=61)
+    x = gaussian((2, b ** n), seed=62, complex_=True)
+    g = gaussian((2, b ** n), seed=63, complex_=True)
+    Wt = torch.tensor(W, dtype=torch.complex128, requires_grad=True)
+    xt = torch.tensor(x, dtype=torch.complex128, requires_grad=True)
+    G = Wt
+    for _ in range(n - 1):
+        G = torch.kron(G, Wt)
+    y = xt @ G.transpose(0, 1)
+    L = torch.real(torch.sum(torch.conj(torch.tensor(g)) * y))
+    L.backward()
+    gx, gW = O.grad(W, x, g, n)
+    np.testing.assert_allclose(xt.grad.numpy(), gx, atol=1e-12)
+    np.testing.assert_allclose(Wt.grad.numpy(), gW, atol=1e-12)
+
+
+def test_grad_unitary_identity():
+    # for unitary W: gW = W sum_s U_s X_s^H, with u = G^H g and U_s, X_s the
+    # (b x N/b) matrices of u and x with digit s as the row index
+    b, n = 5, 4
+    W = haar_unitary(b, seed=71)
+    x = gaussian(b ** n, seed=72, complex_=True)
+    g = gaussian(b ** n, seed=73, complex_=True)
+    gx, gW = O.grad(W, x, g, n)
+    u = O.adjoint(W, g, n)
+    np.testing.assert_allclose(gx, u, atol=1e-12)
+    S = np.zeros((b, b), dtype=complex)
+    for s in range(n):
+        U = np.moveaxis(u.reshape([b] * n), n - 1 - s, 0).reshape(b, -1)
+        X = np.moveaxis(x.reshape([b] * n), n - 1 - s, 0).reshape(b, -1)
+        S += U @ X.conj().T
+    np.testing.assert_allclose(gW, W @ S, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Integer +-1 Hadamard: exact arithmetic
+# --------------------------------------------------------------------------
+def test_int32_hadamard_exact():
+    n = 10
+    H = hadamard2(False).astype(np.int64)
+    x = int_uniform((2, 1 << n), seed=33, lo=-100, hi=100)
+    y = O.staged_int32(H, x, n)
+    ref = x @ O.sylvester_hadamard(n).T
+    assert np.array_equal(y.astype(np.int64), ref)
+    # H H = 2 I, so the adjoint of the forward is 2^n x exactly
+    back = O.adjoint_int32(H, y, n)
+    assert np.array_equal(back.astype(np.int64), x * (1 << n))
+
+
+def test_int32_wraparound_matches_bigint():
+    # values large enough to overflow int32: result is the exact value mod 2^32
+    n, b = 4, 3
+    rng = np.random.default_rng(5)
+    W = rng.integers(-50000, 50000, size=(b, b))
+    x = rng.integers(-2 ** 31, 2 ** 31, size=b ** n)
+    y = O.staged_int32(W, x, n)
+    Wl = [[int(v) for v in r] for r in W]
+    for p in range(b ** n):
+        acc = 0
+        for q in range(b ** n):
+            e = 1
+            pd, qd = O.digits(p, b, n), O.digits(q, b, n)
+            for j in range(n):
+                e *= Wl[pd[j]][qd[j]]
+            acc += e * int(x[q])
+        acc %= 2 ** 32
+        if acc >= 2 ** 31:
+            acc -= 2 ** 32
+        assert int(y[p]) == acc
+
+
+# --------------------------------------------------------------------------
+# Heterogeneous factors (§2.6, remark on distinct factors)
+# --------------------------------------------------------------------------
+def test_mixed_radix_matches_kron_of_distinct_factors():
+    Ws = [haar_unitary(2, 1), haar_unitary(3, 2), haar_unitary(4, 3), haar_unitary(3, 4)]
+    N = 2 * 3 * 4 * 3
+    x = gaussian((2, N), seed=5, complex_=True)
+    y = O.staged_mixed(Ws, x)
+    np.testing.assert_allclose(y, x @ O.kron_list(Ws).T, atol=1e-13)
+    # identical factors reduce to the uniform transform
+    W = haar_unitary(3, 9)
+    x81 = gaussian((2, 81), seed=6, complex_=True)
+    np.testing.assert_allclose(O.staged_mixed([W] * 4, x81), O.staged(W, x81, 4), atol=1e-13)
