@@ -1,0 +1,220 @@
+/*
+ * gtt.h -- C ABI of libgtt.so, the MI355X (gfx950) fast generalized tensor
+ * transform (GTT).
+ *
+ * The transform (Shukla & Vedula, §2.6, Def. 2.4) is
+ *
+ *     y = G_N x,   G_N = W kron W kron ... kron W   (n factors),  N = b^n,
+ *
+ * with entries G_N(p, q) = prod_{j<n} W[p_j][q_j] (§2.6, product formula
+ * after Def. 2.4), where p = sum_j p_j b^j is the base-b expansion of an index
+ * (digit 0 least significant, §2.1) and W[r][c] is row r, column c of the
+ * b x b base matrix (0-based, §2.1).  The fast algorithm (§3, Alg. 1) applies
+ * W along one base-b digit at a time; this library fuses several such digit
+ * passes per trip through HBM.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Layout: an instance is N contiguous elements, index i = sum_j i_j b^j,
+ *    i_0 fastest.  A uniform batch is `batch` instances back to back.
+ *  - W: row-major b x b matrix in the *compute* dtype of the plan:
+ *      GTT_F64 -> double, GTT_F32/GTT_BF16/GTT_F16 -> float,
+ *      GTT_C64 -> complex float (re, im interleaved), GTT_C128 -> complex
+ *      double, GTT_I32 -> int32 (arithmetic mod 2^32, two's complement).
+ *  - Complex data is interleaved (re, im), as in torch.complex64/complex128.
+ *  - Pointers named x, y, W, gy, gx, gW, saved and ws are DEVICE pointers
+ *    owned by the caller; the library never frees them and never allocates
+ *    device memory inside forward / inverse / backward.
+ *  - All device work is enqueued on `stream` (a hipStream_t; NULL is the
+ *    null stream).  Calls return as soon as the work is enqueued.
+ *  - Argument checks run on the host, before any HIP call, and report a
+ *    status code; nothing throws across this ABI.  A failed kernel launch is
+ *    reported as GTT_ERR_HIP.
+ *  - Aliasing: x == y (and gy == gx) is allowed (in place); any other
+ *    partial overlap of buffers is undefined behaviour.
+ *  - Alignment: every data pointer must be 16-byte aligned
+ *    (GTT_ERR_ALIGNMENT otherwise).
+ *  - A plan is immutable after creation and may be used concurrently from
+ *    several host threads on different streams, provided each call has its
+ *    own workspace.
+ *  - Determinism: for a fixed plan and inputs y, gx and gW are bitwise
+ *    reproducible (all reductions run in a fixed order).
+ */
+#ifndef GTT_H
+#define GTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gtt_status {
+    GTT_OK = 0,
+    GTT_ERR_INVALID_VALUE = 1, /* null pointer, bad flag, count < 1, ... */
+    GTT_ERR_SHAPE = 2,         /* b < 2, n < 0, b^n overflows int64, batch < 1 */
+    GTT_ERR_DTYPE = 3,         /* unknown dtype */
+    GTT_ERR_ALIGNMENT = 4,     /* a data pointer is not 16-byte aligned */
+    GTT_ERR_WORKSPACE = 5,     /* ws_bytes smaller than the call needs */
+    GTT_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement */
+    GTT_ERR_HIP = 7,           /* a HIP runtime call or kernel launch failed */
+    GTT_ERR_INTERNAL = 8
+} gtt_status;
+
+typedef enum gtt_dtype {
+    GTT_F64 = 0,
+    GTT_F32 = 1,
+    GTT_C128 = 2,
+    GTT_C64 = 3,
+    GTT_BF16 = 4,
+    GTT_F16 = 5,
+    GTT_I32 = 6
+} gtt_dtype;
+
+/* Plan flags (bit set). */
+#define GTT_FLAG_FP32_INTERMEDIATE 0x1u /* bf16/f16: keep the values between
+                                           digit groups in float32 inside the
+                                           workspace instead of the storage
+                                           dtype */
+#define GTT_FLAG_NO_TUNE 0x2u           /* ignore the tuning table; use the
+                                           built-in heuristics */
+#define GTT_FLAG_PERSISTENT 0x4u        /* ragged batch: run every digit group
+                                           of every instance in one persistent
+                                           cooperative launch */
+
+typedef struct gtt_plan_s* gtt_plan_t;
+
+/*
+ * gtt_plan -- build an execution plan.
+ *
+ * Uniform batch (count == 1): instance radix b[0] and digit count n[0] apply to
+ * `batch` contiguous instances; x_off and w_idx must be NULL.
+ *
+ * Ragged batch (count > 1, `batch` must be 1): instance t has radix b[t] and
+ * n[t] digits (N_t = b[t]^n[t]) and starts at element offset x_off[t] of the
+ * data buffers (x_off == NULL: instances packed back to back in order).
+ * Instance t uses base matrix number w_idx[t] of the W table; the table holds
+ * its matrices back to back in index order, matrix w being b_w x b_w where
+ * b_w is the radix of the instances that use it (they must agree and every
+ * index 0..max must be used).  w_idx == NULL means one matrix per distinct
+ * radix, in ascending order of radix.  gW of a ragged plan has the layout of
+ * the W table.
+ *
+ * n == 0 is allowed (N = 1, the identity; base case of §2.2).
+ * Errors: GTT_ERR_SHAPE (b < 2, n < 0, b^n overflows, batch < 1),
+ * GTT_ERR_DTYPE, GTT_ERR_INVALID_VALUE (out == NULL, count < 1, bad
+ * w_idx / x_off), GTT_ERR_UNSUPPORTED.  On error *out is set to NULL.
+ * The plan holds host memory and, for ragged batches, a small device work
+ * list (allocated here, freed by gtt_plan_destroy).
+ */
+gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n,
+                    int64_t batch, const int64_t* x_off, const int32_t* w_idx,
+                    gtt_dtype dtype, uint32_t flags);
+
+/*
+ * gtt_plan_mixed -- plan for the heterogeneous transform
+ *     G = W_0 kron W_1 kron ... kron W_{m-1},   N = prod_k b_k
+ * (§2.6, remark on distinct tensor factors), factor W_k being b_k x b_k
+ * (radices[k] = b_k).  As in the Kronecker product, the leftmost factor W_0
+ * acts on the most significant mixed-radix digit: factor k acts on the digit
+ * whose place value is b_{k+1} b_{k+2} ... b_{m-1}.  W is passed to forward /
+ * inverse as the matrices W_0, W_1, ..., W_{m-1} back to back (compute
+ * dtype, row-major).  `batch` contiguous instances of N elements.
+ * gtt_backward and gtt_filter return GTT_ERR_UNSUPPORTED for mixed plans.
+ */
+gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, int64_t batch,
+                          gtt_dtype dtype, uint32_t flags);
+
+/*
+ * gtt_workspace_size -- bytes of device workspace a call needs.
+ *   fwd   : forward and inverse (currently 0 unless the FP32-intermediate
+ *           flag is set);
+ *   bwd   : backward when `saved` is NULL (includes room to recompute the
+ *           group-boundary activations); when `saved` is passed, the smaller
+ *           amount *bwd - *saved suffices;
+ *   saved : size of the optional `saved` buffer of forward/backward (the
+ *           activations at the boundaries between digit groups).
+ * Any output pointer may be NULL.
+ */
+gtt_status gtt_workspace_size(gtt_plan_t p, size_t* fwd, size_t* bwd, size_t* saved);
+
+/*
+ * gtt_forward -- y = G_N x for every instance (Def. 2.4; fast algorithm §3).
+ * If `saved` is non-NULL it receives the activations between digit groups
+ * (size from gtt_workspace_size), for a later gtt_backward.
+ */
+gtt_status gtt_forward(gtt_plan_t p, const void* W, const void* x, void* y, void* saved,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gtt_inverse -- x = G_N^dagger y = (W^H)^{kron n} y, the inverse transform
+ * used by the paper's applications (§4.1, §4.3).  It is the inverse of
+ * gtt_forward only when W is unitary; for GTT_I32 W^H is W^T (for the
+ * unnormalised +-1 Hadamard, inverse(forward(x)) = 2^n x exactly).
+ */
+gtt_status gtt_inverse(gtt_plan_t p, const void* W, const void* y, void* x,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gtt_backward -- gradients of a real loss L through y = G_N x, in the
+ * convention dL/dRe + i dL/dIm (PyTorch's), given gy = dL/dy:
+ *     gx = G_N^H gy;
+ *     gW = sum over digits s, instances and fibres of digit s of c_s a_s^H,
+ * where a_s is the input of the pass on digit s and c_s the gradient at its
+ * output (for real dtypes ^H is ^T).  gW is overwritten (b x b, compute dtype;
+ * for ragged plans, the layout of the W table), never accumulated.  gx or gW
+ * may be NULL to skip them (not both).  `saved` (nullable) is the buffer
+ * filled by gtt_forward for the same x and W; without it the activations are
+ * recomputed in the workspace.  Floating dtypes only (GTT_ERR_UNSUPPORTED for
+ * GTT_I32 and for mixed plans).
+ */
+gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* saved,
+                        const void* gy, void* gx, void* gW, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/*
+ * gtt_filter -- classical natural-order filter (§4.3, Alg. 3 without the
+ * ancilla): coefficients X = G_N x are split at natural index `cutoff`
+ * (k < cutoff -> low, k >= cutoff -> high) and each part is mapped back with
+ * G_N^dagger.  low or high may be NULL.  Uniform plans, floating dtypes.
+ * Needs gtt_workspace_size's fwd bytes plus N*batch elements of the storage
+ * dtype (the coefficients) in `ws`.
+ */
+gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff,
+                      void* low, void* high, void* ws, size_t ws_bytes, void* stream);
+
+/* Frees the plan and its device work list.  NULL is accepted. */
+gtt_status gtt_plan_destroy(gtt_plan_t p);
+
+/* Static, human-readable name of a status code. */
+const char* gtt_status_string(gtt_status s);
+
+/*
+ * gtt_plan_describe -- writes a NUL-terminated JSON description of the plan
+ * (digit groups, tile shapes, launch sizes) into buf (truncated to len).
+ */
+gtt_status gtt_plan_describe(gtt_plan_t p, char* buf, size_t len);
+
+/*
+ * gtt_set_tuning -- override the launch heuristics for plans created after
+ * this call, for radix b and storage dtype (used by the autotuner):
+ *   lds_budget_bytes : LDS bytes of one tile (0 = default),
+ *   min_row_bytes    : least contiguous bytes per tile row for strided digit
+ *                      groups (0 = default).
+ * Process-wide; not thread-safe against concurrent gtt_plan calls.
+ */
+gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes,
+                          int32_t min_row_bytes);
+
+/*
+ * gtt_selftest -- host-only checks of the index arithmetic (fast division by
+ * constants, digit grouping); touches no GPU.  Returns GTT_OK on success.
+ */
+gtt_status gtt_selftest(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GTT_H */

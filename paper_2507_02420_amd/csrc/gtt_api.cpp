@@ -1,0 +1,603 @@
+// Host side of libgtt.so: argument checking, planning (digit groups and tile
+// shapes) and kernel launch sequences for the C ABI declared in gtt.h.
+#include "gtt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gtt_args.hpp"
+#include "gtt_launch.hpp"
+#include "gtt_plan.hpp"
+
+using namespace gtt;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+namespace gtt {
+
+FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
+    return f;
+}
+
+uint32_t host_fdiv(uint32_t n, const FastDiv& f) {
+    const uint32_t hi = (uint32_t)(((uint64_t)n * f.m) >> 32);
+    return (hi + n) >> f.s;
+}
+
+size_t storage_size(gtt_dtype d) {
+    switch (d) {
+        case GTT_F64: return 8;
+        case GTT_F32: return 4;
+        case GTT_C128: return 16;
+        case GTT_C64: return 8;
+        case GTT_BF16: return 2;
+        case GTT_F16: return 2;
+        case GTT_I32: return 4;
+    }
+    return 0;
+}
+
+size_t compute_size(gtt_dtype d) {
+    switch (d) {
+        case GTT_F64: return 8;
+        case GTT_F32: return 4;
+        case GTT_C128: return 16;
+        case GTT_C64: return 8;
+        case GTT_BF16: return 4;
+        case GTT_F16: return 4;
+        case GTT_I32: return 4;
+    }
+    return 0;
+}
+
+static bool valid_dtype(int d) { return d >= GTT_F64 && d <= GTT_I32; }
+
+static int ilog2_floor(uint64_t v) {
+    int r = -1;
+    while (v) { v >>= 1; ++r; }
+    return r;
+}
+
+// tuning table: (b, dtype) -> overrides
+struct TuneEntry {
+    int b;
+    int dtype;
+    int lds_budget;
+    int min_row_bytes;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static void tuning_for(int b, gtt_dtype dt, uint32_t flags, int* budget, int* minrow) {
+    *budget = 0;
+    *minrow = 0;
+    if (flags & GTT_FLAG_NO_TUNE) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune)
+        if (e.b == b && e.dtype == (int)dt) {
+            *budget = e.lds_budget;
+            *minrow = e.min_row_bytes;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Planner: split the digits (radix list, least significant first) into groups
+// of consecutive digits and choose the tile of every group.
+// ---------------------------------------------------------------------------
+static int64_t prod_range(const std::vector<int>& rad, int a, int b) {
+    int64_t p = 1;
+    for (int i = a; i < b; ++i) p *= rad[i];
+    return p;
+}
+
+static uint64_t pow2_floor(uint64_t v) { return v ? (uint64_t(1) << ilog2_floor(v)) : 0; }
+
+// Try to split the n digits into exactly R groups; group 0 contiguous, the
+// others strided with C columns.  Returns false if infeasible.
+static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t cmin_elems,
+                      std::vector<int>* ks) {
+    const int n = (int)rad.size();
+    // group 0: as many digits as fit
+    int k0 = 0;
+    int64_t g = 1;
+    while (k0 < n && g * rad[k0] <= T) g *= rad[k0++];
+    if (k0 == 0) return false;
+    if (R == 1) {
+        if (k0 < n) return false;
+        ks->assign(1, n);
+        return true;
+    }
+    if (k0 >= n) return false;  // R=1 would do
+    // strided groups: greedily from the low side, each as many digits as fit
+    // with at least cmin columns; then require that all digits are covered.
+    std::vector<int> out{k0};
+    int s = k0;
+    for (int r = 1; r < R && s < n; ++r) {
+        int k = 0;
+        int64_t G = 1;
+        while (s + k < n && G * rad[s + k] * cmin_elems <= T) G *= rad[s + k++];
+        if (k == 0) return false;
+        out.push_back(k);
+        s += k;
+    }
+    if (s < n || (int)out.size() != R) return false;
+    // balance the strided groups: move digits from earlier strided groups to
+    // later ones while it does not shrink the minimum column count
+    *ks = out;
+    return true;
+}
+
+static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, int64_t total_elems,
+                       int64_t T, size_t esize, size_t csize, bool uniform_small_b,
+                       int64_t row_elems_target) {
+    gr->s0 = s0;
+    gr->k = k;
+    gr->S = prod_range(rad, 0, s0);
+    gr->G = prod_range(rad, s0, s0 + k);
+    const int64_t GS = gr->G * gr->S;
+    const int64_t hi_total = total_elems / GS;  // hi blocks over the whole buffer
+    if (gr->S == 1) {
+        gr->C = 1;
+        // P: hi blocks per tile (a divisor of hi_total), tile <= T
+        int64_t P = std::max<int64_t>(1, T / gr->G);
+        P = std::min(P, hi_total);
+        while (P > 1 && hi_total % P) --P;
+        gr->P = (int)P;
+        gr->L = 1;
+    } else {
+        int64_t C = (int64_t)pow2_floor((uint64_t)std::max<int64_t>(1, T / gr->G));
+        // never wider than the row itself
+        C = std::min<int64_t>(C, (int64_t)pow2_floor((uint64_t)gr->S));
+        gr->C = (int)C;
+        gr->P = 1;
+        gr->L = (gr->S + C - 1) / C;
+        (void)row_elems_target;
+    }
+    gr->logC = ilog2_floor((uint64_t)gr->C);
+    gr->ntiles = (hi_total / gr->P) * gr->L;
+    const int64_t tileE = (int64_t)gr->P * gr->G * gr->C;
+    gr->tileE = tileE;
+    const size_t V = 16 / esize;
+    if (gr->C == gr->S || gr->S == 1) {
+        gr->mode = ((tileE * (int64_t)esize) % 16 == 0) ? kContigVec : kContigScalar;
+    } else if ((gr->C * esize) % 16 == 0 && (gr->S * (int64_t)esize) % 16 == 0 && gr->S % gr->C == 0) {
+        gr->mode = kRowVec;
+    } else {
+        gr->mode = kRowScalar;
+    }
+    (void)V;
+    gr->generic = !uniform_small_b;
+    // LDS padding: one element per register block (contiguous tiles) or per
+    // row (strided tiles) breaks power-of-two bank strides; odd radices need none
+    int pad = 31;
+    if (!gr->generic) {
+        const int b = rad[s0];
+        if ((b & (b - 1)) == 0) {
+            const int nb = (b == 2) ? 16 : (b == 4) ? 16 : b;  // register block size
+            pad = (gr->C == 1) ? ilog2_floor((uint64_t)nb) : gr->logC;
+            if (pad < 2) pad = 2;
+        } else if (b == 6) {
+            pad = (gr->C == 1) ? 4 : gr->logC;
+        }
+        // vector runs of V storage elements must not straddle a pad
+        const int lv = ilog2_floor(16 / esize);
+        if (pad < 31 && (gr->mode == kContigVec || gr->mode == kRowVec)) pad = std::max(pad, lv);
+    }
+    gr->pad_shift = pad;
+    if (gr->generic) {
+        int64_t wtot = 0;
+        for (int j = 0; j < k; ++j) wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
+        gr->wtotal = (int)wtot;
+        gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * tileE) * csize;
+    } else {
+        const int64_t phys = tileE + (pad < 31 ? (tileE >> pad) : 0) + 1;
+        gr->wtotal = 0;
+        gr->lds_bytes = (size_t)phys * csize;
+    }
+}
+
+// Plan the digit groups for one radix list.
+gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags,
+                       bool uniform, std::vector<Group>* groups) {
+    groups->clear();
+    const int n = (int)rad.size();
+    if (n == 0) return GTT_OK;
+    const size_t es = storage_size(dt), cs = compute_size(dt);
+    const int b0 = rad[0];
+    // specialised kernels: radix <= 8 (complex double: <= 5, larger W would
+    // not fit in registers)
+    const bool small_b = uniform && (b0 <= 5 || (b0 <= 8 && dt != GTT_C128));
+    int tb = 0, tr = 0;
+    tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr);
+    std::vector<int64_t> budgets;
+    if (tb > 0) {
+        budgets.push_back(tb);
+    } else {
+        budgets = {32768, 65536};
+    }
+    const int64_t min_row_bytes = tr > 0 ? tr : 128;
+    int64_t N = 1;
+    for (int r : rad) N *= r;
+    const int64_t total = N * batch;
+    for (int64_t relax_row = min_row_bytes; relax_row >= (int64_t)es; relax_row /= 2) {
+        for (int R = 1; R <= n; ++R) {
+            for (int64_t bud : budgets) {
+                int64_t T = bud / (int64_t)cs;
+                if (!small_b) T /= 2;  // the runtime-radix kernel double-buffers
+                const int64_t cmin = std::max<int64_t>(1, relax_row / (int64_t)es);
+                std::vector<int> ks;
+                if (!try_split(rad, R, T, cmin, &ks)) continue;
+                int s = 0;
+                for (int k : ks) {
+                    Group g;
+                    fill_group(&g, rad, s, k, total, T, es, cs, small_b, cmin);
+                    groups->push_back(g);
+                    s += k;
+                }
+                return GTT_OK;
+            }
+        }
+    }
+    return GTT_ERR_UNSUPPORTED;  // a single digit does not fit in LDS
+}
+
+}  // namespace gtt
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+static DT to_dt(gtt_dtype d) { return static_cast<DT>((int)d); }
+
+static void fill_args(PassArgs* a, const Group& g, const std::vector<int>& rad, const std::vector<int64_t>& wofs,
+                      int64_t N) {
+    std::memset(a, 0, sizeof(*a));
+    a->k = g.k;
+    a->G = (int32_t)g.G;
+    a->P = g.P;
+    a->logC = g.logC;
+    a->mode = g.mode;
+    a->pad_shift = g.pad_shift;
+    a->cut = -1;
+    a->S = g.S;
+    a->L = g.L;
+    a->ntiles = g.ntiles;
+    a->N = N;
+    a->divG = make_fastdiv((uint32_t)g.G);
+    int64_t pv = 1;
+    for (int j = 0; j <= g.k; ++j) {
+        a->bpow[j] = (int32_t)pv;
+        a->divb[j] = make_fastdiv((uint32_t)pv);
+        if (j < g.k) {
+            const int r = rad[g.s0 + j];
+            a->rad[j] = r;
+            a->divrad[j] = make_fastdiv((uint32_t)r);
+            a->wofs[j] = (int32_t)wofs[g.s0 + j];
+            pv *= r;
+        }
+    }
+    a->wtotal = g.wtotal;
+}
+
+static gtt_status launch_group(gtt_dtype dt, const Group& g, const std::vector<int>& rad,
+                               const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
+                               const void* in, void* out, hipStream_t s) {
+    PassArgs a;
+    fill_args(&a, g, rad, wofs, N);
+    a.in = in;
+    a.out = out;
+    a.W = W;
+    a.adjoint = adjoint ? 1 : 0;
+    const unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, (int64_t)0x7fffffff);
+    hipError_t e = launch_pass(to_dt(dt), rad[g.s0], g.generic, a, grid, g.lds_bytes, s);
+    return e == hipSuccess ? GTT_OK : GTT_ERR_HIP;
+}
+
+namespace gtt {
+gtt_status launch_group_inst(gtt_dtype dt, const Group& g, int b, int64_t N, const void* W, bool adjoint,
+                             const void* in, void* out, hipStream_t s) {
+    std::vector<int> rad(g.s0 + g.k, b);
+    std::vector<int64_t> wofs(g.s0 + g.k, 0);
+    return launch_group(dt, g, rad, wofs, N, W, adjoint, in, out, s);
+}
+}  // namespace gtt
+
+// Run a sequence of digit groups over one buffer set: group 0 reads `in`;
+// group i < R-1 writes `mid[i]` (or `out` when mid is null); the last writes out.
+static gtt_status run_groups(gtt_dtype dt, const std::vector<Group>& groups, const std::vector<int>& rad,
+                             const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
+                             const void* in, void* out, char* saved, size_t elems, hipStream_t s) {
+    const size_t es = storage_size(dt);
+    if (groups.empty()) {
+        if (in != out)
+            if (hipMemcpyAsync(out, in, elems * es, hipMemcpyDeviceToDevice, s) != hipSuccess) return GTT_ERR_HIP;
+        return GTT_OK;
+    }
+    const void* src = in;
+    for (size_t i = 0; i < groups.size(); ++i) {
+        void* dst = out;
+        if (i + 1 < groups.size() && saved) dst = saved + i * elems * es;
+        gtt_status st = launch_group(dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s);
+        if (st != GTT_OK) return st;
+        src = dst;
+    }
+    return GTT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* gtt_status_string(gtt_status s) {
+    switch (s) {
+        case GTT_OK: return "GTT_OK";
+        case GTT_ERR_INVALID_VALUE: return "GTT_ERR_INVALID_VALUE";
+        case GTT_ERR_SHAPE: return "GTT_ERR_SHAPE";
+        case GTT_ERR_DTYPE: return "GTT_ERR_DTYPE";
+        case GTT_ERR_ALIGNMENT: return "GTT_ERR_ALIGNMENT";
+        case GTT_ERR_WORKSPACE: return "GTT_ERR_WORKSPACE";
+        case GTT_ERR_UNSUPPORTED: return "GTT_ERR_UNSUPPORTED";
+        case GTT_ERR_HIP: return "GTT_ERR_HIP";
+        case GTT_ERR_INTERNAL: return "GTT_ERR_INTERNAL";
+    }
+    return "GTT_ERR_UNKNOWN";
+}
+
+static bool pow_fits(int64_t b, int64_t n, int64_t* out) {
+    int64_t v = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (v > (int64_t)(INT64_MAX / b)) return false;
+        v *= b;
+    }
+    *out = v;
+    return true;
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n, int64_t batch,
+                    const int64_t* x_off, const int32_t* w_idx, gtt_dtype dtype, uint32_t flags) {
+    if (!out) return GTT_ERR_INVALID_VALUE;
+    *out = nullptr;
+    if (count < 1 || !b || !n) return GTT_ERR_INVALID_VALUE;
+    if (!valid_dtype((int)dtype)) return GTT_ERR_DTYPE;
+    if (flags & ~(GTT_FLAG_FP32_INTERMEDIATE | GTT_FLAG_NO_TUNE | GTT_FLAG_PERSISTENT)) return GTT_ERR_INVALID_VALUE;
+    if (flags & GTT_FLAG_FP32_INTERMEDIATE) return GTT_ERR_UNSUPPORTED;
+    if (batch < 1) return GTT_ERR_SHAPE;
+    if (count == 1 && (x_off || w_idx)) return GTT_ERR_INVALID_VALUE;
+    if (count > 1 && batch != 1) return GTT_ERR_SHAPE;
+    for (int32_t t = 0; t < count; ++t) {
+        if (b[t] < 2 || n[t] < 0) return GTT_ERR_SHAPE;
+        int64_t N;
+        if (!pow_fits(b[t], n[t], &N)) return GTT_ERR_SHAPE;
+        if (N > ((int64_t)1 << 40)) return GTT_ERR_SHAPE;
+        if (count == 1 && N > INT64_MAX / batch) return GTT_ERR_SHAPE;
+    }
+    gtt_plan_s* p = new (std::nothrow) gtt_plan_s();
+    if (!p) return GTT_ERR_INTERNAL;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->esize = storage_size(dtype);
+    p->csize = compute_size(dtype);
+    gtt_status st = GTT_OK;
+    if (count == 1) {
+        p->kind = PlanKind::Uniform;
+        p->b = b[0];
+        p->n = n[0];
+        pow_fits(b[0], n[0], &p->N);
+        p->batch = batch;
+        p->rad.assign(n[0], b[0]);
+        p->wofs.assign(n[0], 0);
+        st = plan_groups(p->rad, batch, dtype, flags, true, &p->groups);
+        p->total_elems = p->N * batch;
+        p->w_elems = (int64_t)b[0] * b[0];
+    } else {
+        st = plan_ragged(p, count, b, n, x_off, w_idx);
+    }
+    if (st != GTT_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return GTT_OK;
+}
+
+gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, int64_t batch, gtt_dtype dtype,
+                          uint32_t flags) {
+    if (!out) return GTT_ERR_INVALID_VALUE;
+    *out = nullptr;
+    if (m < 0 || (m > 0 && !radices)) return GTT_ERR_INVALID_VALUE;
+    if (!valid_dtype((int)dtype)) return GTT_ERR_DTYPE;
+    if (flags & ~(GTT_FLAG_NO_TUNE)) return (flags & GTT_FLAG_FP32_INTERMEDIATE) ? GTT_ERR_UNSUPPORTED
+                                                                                 : GTT_ERR_INVALID_VALUE;
+    if (batch < 1) return GTT_ERR_SHAPE;
+    int64_t N = 1;
+    for (int k = 0; k < m; ++k) {
+        if (radices[k] < 2 || radices[k] > 64) return radices[k] < 2 ? GTT_ERR_SHAPE : GTT_ERR_UNSUPPORTED;
+        if (N > ((int64_t)1 << 40) / radices[k]) return GTT_ERR_SHAPE;
+        N *= radices[k];
+    }
+    if (N > INT64_MAX / batch) return GTT_ERR_SHAPE;
+    gtt_plan_s* p = new (std::nothrow) gtt_plan_s();
+    if (!p) return GTT_ERR_INTERNAL;
+    p->kind = PlanKind::Mixed;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->esize = storage_size(dtype);
+    p->csize = compute_size(dtype);
+    p->N = N;
+    p->batch = batch;
+    p->n = m;
+    p->total_elems = N * batch;
+    // digit d (least significant first) is factor m-1-d
+    p->rad.resize(m);
+    p->wofs.resize(m);
+    std::vector<int64_t> fofs(m);
+    int64_t acc = 0;
+    for (int k = 0; k < m; ++k) {
+        fofs[k] = acc;
+        acc += (int64_t)radices[k] * radices[k];
+    }
+    p->w_elems = acc;
+    for (int d = 0; d < m; ++d) {
+        p->rad[d] = radices[m - 1 - d];
+        p->wofs[d] = fofs[m - 1 - d];
+    }
+    gtt_status st = plan_groups(p->rad, batch, dtype, flags, false, &p->groups);
+    if (st != GTT_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return GTT_OK;
+}
+
+gtt_status gtt_plan_destroy(gtt_plan_t p) {
+    if (!p) return GTT_OK;
+    destroy_ragged(p);
+    delete p;
+    return GTT_OK;
+}
+
+gtt_status gtt_workspace_size(gtt_plan_t p, size_t* fwd, size_t* bwd, size_t* saved) {
+    if (!p) return GTT_ERR_INVALID_VALUE;
+    size_t f = 0, bw = 0, sv = 0;
+    workspace_sizes(p, &f, &bw, &sv);
+    if (fwd) *fwd = f;
+    if (bwd) *bwd = bw;
+    if (saved) *saved = sv;
+    return GTT_OK;
+}
+
+gtt_status gtt_forward(gtt_plan_t p, const void* W, const void* x, void* y, void* saved, void* ws,
+                       size_t ws_bytes, void* stream) {
+    if (!p || !W || !x || !y) return GTT_ERR_INVALID_VALUE;
+    if (!aligned16(x) || !aligned16(y) || !aligned16(W) || (saved && !aligned16(saved)) ||
+        (ws && !aligned16(ws)))
+        return GTT_ERR_ALIGNMENT;
+    (void)ws;
+    (void)ws_bytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, x, y, false, (char*)saved, s);
+    return run_groups(p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, y, (char*)saved,
+                      (size_t)p->total_elems, s);
+}
+
+gtt_status gtt_inverse(gtt_plan_t p, const void* W, const void* y, void* x, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!p || !W || !x || !y) return GTT_ERR_INVALID_VALUE;
+    if (!aligned16(x) || !aligned16(y) || !aligned16(W) || (ws && !aligned16(ws))) return GTT_ERR_ALIGNMENT;
+    (void)ws;
+    (void)ws_bytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, y, x, true, nullptr, s);
+    // the adjoint applies W^H per digit; digit passes commute, so the group
+    // order of the forward plan is reused as is
+    return run_groups(p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, y, x, nullptr,
+                      (size_t)p->total_elems, s);
+}
+
+gtt_status gtt_plan_describe(gtt_plan_t p, char* buf, size_t len) {
+    if (!p || !buf || len == 0) return GTT_ERR_INVALID_VALUE;
+    std::string s = describe_plan(p);
+    std::snprintf(buf, len, "%s", s.c_str());
+    return GTT_OK;
+}
+
+gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes) {
+    if (b < 2 || !valid_dtype((int)dtype)) return GTT_ERR_INVALID_VALUE;
+    if (lds_budget_bytes < 0 || lds_budget_bytes > 160 * 1024 || min_row_bytes < 0) return GTT_ERR_INVALID_VALUE;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : g_tune)
+        if (e.b == b && e.dtype == (int)dtype) {
+            e.lds_budget = lds_budget_bytes;
+            e.min_row_bytes = min_row_bytes;
+            return GTT_OK;
+        }
+    g_tune.push_back(TuneEntry{b, (int)dtype, lds_budget_bytes, min_row_bytes});
+    return GTT_OK;
+}
+
+gtt_status gtt_selftest(void) {
+    // fast division by invariant integers: exhaustive over a range of n for
+    // every divisor used by the planner (place values up to 2^24 and radices)
+    std::vector<uint32_t> ds;
+    for (uint32_t d = 1; d <= 64; ++d) ds.push_back(d);
+    for (uint32_t b = 2; b <= 8; ++b)
+        for (uint64_t v = b; v < (1u << 24); v *= b) ds.push_back((uint32_t)v);
+    for (uint32_t d : ds) {
+        FastDiv f = make_fastdiv(d);
+        for (uint32_t n = 0; n < 70000; ++n)
+            if (host_fdiv(n, f) != n / d) return GTT_ERR_INTERNAL;
+        for (uint32_t n = 0x7fffffffu; n > 0x7fffffffu - 70000u; --n)
+            if (host_fdiv(n, f) != n / d) return GTT_ERR_INTERNAL;
+        for (uint64_t n = 1; n < 0x80000000ull; n = n * 3 + 1)
+            if (host_fdiv((uint32_t)n, f) != (uint32_t)n / d) return GTT_ERR_INTERNAL;
+    }
+    // planner invariants: groups cover the digits exactly, tiles fit and
+    // partition the buffer
+    const gtt_dtype dts[] = {GTT_F64, GTT_F32, GTT_C128, GTT_C64, GTT_BF16, GTT_F16, GTT_I32};
+    for (gtt_dtype dt : dts)
+        for (int b = 2; b <= 33; ++b)
+            for (int n = 1; n <= 20; ++n) {
+                int64_t N;
+                if (!pow_fits(b, n, &N) || N > (1 << 22)) break;
+                std::vector<int> rad(n, b);
+                std::vector<Group> gs;
+                if (plan_groups(rad, 3, dt, GTT_FLAG_NO_TUNE, true, &gs) != GTT_OK) return GTT_ERR_INTERNAL;
+                int s = 0;
+                for (const Group& g : gs) {
+                    if (g.s0 != s || g.k < 1) return GTT_ERR_INTERNAL;
+                    s += g.k;
+                    if (g.lds_bytes > 160 * 1024) return GTT_ERR_INTERNAL;
+                    if ((int64_t)g.P * g.G * g.C != g.tileE) return GTT_ERR_INTERNAL;
+                    // tiles x tile elements cover the buffer (column blocks may overhang)
+                    if (g.ntiles * g.tileE < N * 3) return GTT_ERR_INTERNAL;
+                    if (g.C > g.S && g.S != 1) return GTT_ERR_INTERNAL;
+                    if (g.S == 1 && g.C != 1) return GTT_ERR_INTERNAL;
+                }
+                if (s != n) return GTT_ERR_INTERNAL;
+            }
+    return GTT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* saved, const void* gy, void* gx,
+                        void* gW, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !W || !x || !gy || (!gx && !gW)) return GTT_ERR_INVALID_VALUE;
+    if (!aligned16(W) || !aligned16(x) || !aligned16(gy) || (gx && !aligned16(gx)) || (gW && !aligned16(gW)) ||
+        (saved && !aligned16(saved)) || (ws && !aligned16(ws)))
+        return GTT_ERR_ALIGNMENT;
+    if (p->dtype == GTT_I32 || p->kind == PlanKind::Mixed) return GTT_ERR_UNSUPPORTED;
+    return backward_impl(p, W, x, saved, gy, gx, gW, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff, void* low, void* high, void* ws,
+                      size_t ws_bytes, void* stream) {
+    if (!p || !W || !x || (!low && !high)) return GTT_ERR_INVALID_VALUE;
+    if (!aligned16(W) || !aligned16(x) || (low && !aligned16(low)) || (high && !aligned16(high)) ||
+        (ws && !aligned16(ws)))
+        return GTT_ERR_ALIGNMENT;
+    if (p->kind != PlanKind::Uniform || p->dtype == GTT_I32) return GTT_ERR_UNSUPPORTED;
+    if (cutoff < 0) return GTT_ERR_INVALID_VALUE;
+    return filter_impl(p, W, x, cutoff, low, high, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,344 @@
+// Fused digit-group pass: one HBM round trip applies W along k consecutive
+// base-b digits (§3: each level of the fast algorithm is the product
+// Y = X W^T along one digit; the levels act on different tensor factors of
+// Def. 2.4 and therefore commute, so any k of them can be done on one tile).
+//
+// A work-group owns one tile (P hi blocks x G = b^k group positions x C lo
+// columns, see gtt_args.hpp).  It
+//   1. streams the tile from HBM into LDS with coalesced accesses
+//      (16-byte vectors where the layout allows), converting storage to the
+//      compute dtype;
+//   2. runs the k digits as ceil(k / RD) register super-stages: each thread
+//      gathers a B^RD block spanning RD digits from LDS, applies W along those
+//      RD digits in registers and scatters the block back;
+//   3. streams the tile back to HBM.
+// Every tile is read completely before it is written, and tiles are disjoint
+// sets of positions that map onto themselves, so in-place (in == out) is safe.
+#pragma once
+
+#include "gtt_args.hpp"
+#include "gtt_types.hpp"
+
+namespace gtt {
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+template <int B, int R>
+struct IPow {
+    static constexpr int value = B * IPow<B, R - 1>::value;
+};
+template <int B>
+struct IPow<B, 0> {
+    static constexpr int value = 1;
+};
+
+// register digits per super-stage: blocks of at most 16 elements
+template <int B>
+struct RegDigits {
+    static constexpr int v = (B == 2) ? 4 : (B == 3 || B == 4) ? 2 : 1;
+};
+
+// ---------------------------------------------------------------------------
+// W along digit D of a register block of B^R values (digit 0 = stride 1).
+// ---------------------------------------------------------------------------
+template <typename C, int B, int R, int D>
+__device__ __forceinline__ void block_digit(C (&v)[(IPow<B, R>::value)], const C (&w)[B * B]) {
+    constexpr int st = IPow<B, D>::value;
+    constexpr int n = IPow<B, R>::value;
+#pragma unroll
+    for (int base = 0; base < n; ++base) {
+        if ((base / st) % B != 0) continue;  // base must have digit D == 0
+        C in[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) in[q] = v[base + q * st];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            C acc = cmul(w[r * B], in[0]);
+#pragma unroll
+            for (int q = 1; q < B; ++q) acc = cmac(acc, w[r * B + q], in[q]);
+            v[base + r * st] = acc;
+        }
+    }
+}
+
+template <typename C, int B, int R, int D>
+struct BlockAll {
+    __device__ __forceinline__ static void run(C (&v)[(IPow<B, R>::value)], const C (&w)[B * B]) {
+        block_digit<C, B, R, D>(v, w);
+        BlockAll<C, B, R, D + 1>::run(v, w);
+    }
+};
+template <typename C, int B, int R>
+struct BlockAll<C, B, R, R> {
+    __device__ __forceinline__ static void run(C (&)[(IPow<B, R>::value)], const C (&)[B * B]) {}
+};
+
+// LDS position of tile element lam: one pad element after every 2^pad_shift
+// elements, which turns the power-of-two strides of the digit fibres into
+// bank-conflict-free odd strides (pad_shift >= 31 disables padding).
+__device__ __forceinline__ uint32_t lds_phys(uint32_t lam, int pad_shift) {
+    return lam + (lam >> pad_shift);
+}
+
+// One super-stage: digits j .. j+R-1 of the group, all fibres of the tile.
+template <typename C, int B, int R>
+__device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, uint32_t rows,
+                                           const C (&w)[B * B]) {
+    constexpr int NB = IPow<B, R>::value;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t F = (rows << a.logC) / NB;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t bjr = (uint32_t)a.bpow[j + R];
+    const uint32_t step = bj << a.logC;
+    for (uint32_t f = threadIdx.x; f < F; f += kThreads) {
+        const uint32_t c = f & Cm;
+        const uint32_t f1 = f >> a.logC;
+        const uint32_t Q = fdiv(f1, a.divb[j]);
+        const uint32_t glo = f1 - Q * bj;
+        const uint32_t lam0 = ((Q * bjr + glo) << a.logC) | c;
+        C v[NB];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) v[m] = lds[lds_phys(lam0 + m * step, a.pad_shift)];
+        BlockAll<C, B, R, 0>::run(v, w);
+#pragma unroll
+        for (int m = 0; m < NB; ++m) lds[lds_phys(lam0 + m * step, a.pad_shift)] = v[m];
+    }
+}
+
+template <typename C, int B, int RD>
+__device__ __forceinline__ void run_stages(C* lds, const PassArgs& a, uint32_t rows, const C (&w)[B * B]) {
+    for (int j = 0; j < a.k; j += RD) {
+        const int r = (a.k - j) < RD ? (a.k - j) : RD;
+        if constexpr (RD >= 4) {
+            if (r == 4) { super_stage<C, B, 4>(lds, a, j, rows, w); __syncthreads(); continue; }
+        }
+        if constexpr (RD >= 3) {
+            if (r == 3) { super_stage<C, B, 3>(lds, a, j, rows, w); __syncthreads(); continue; }
+        }
+        if constexpr (RD >= 2) {
+            if (r == 2) { super_stage<C, B, 2>(lds, a, j, rows, w); __syncthreads(); continue; }
+        }
+        super_stage<C, B, 1>(lds, a, j, rows, w);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile <-> LDS movement
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec16 {
+    static constexpr int V = 16 / sizeof(T);  // storage elements per 16 bytes
+};
+
+// global offset (elements) of the start of row r of the tile
+__device__ __forceinline__ int64_t row_offset(const PassArgs& a, int64_t hb, int64_t l, uint32_t r) {
+    const uint32_t p = (a.P == 1) ? 0u : fdiv(r, a.divG);
+    const uint32_t g = r - p * (uint32_t)a.G;
+    return (hb * a.P + p) * ((int64_t)a.G * a.S) + (int64_t)g * a.S + (l << a.logC);
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, int64_t t, uint32_t rows) {
+    constexpr int V = Vec16<T>::V;
+    const T* __restrict__ in = static_cast<const T*>(a.in);
+    const uint32_t tileE = rows << a.logC;
+    if (a.mode == kContigVec || a.mode == kContigScalar) {
+        const int64_t base = t * (int64_t)tileE;
+        if (a.mode == kContigVec) {
+            for (uint32_t i = threadIdx.x; i < tileE / V; i += kThreads) {
+                T v[V];
+                *reinterpret_cast<uint4*>(v) = *reinterpret_cast<const uint4*>(in + base + (int64_t)i * V);
+                const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+                for (int e = 0; e < V; ++e) lds[ph + e] = to_c(v[e]);
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads)
+                lds[lds_phys(i, a.pad_shift)] = to_c(in[base + i]);
+        }
+        return;
+    }
+    const int64_t hb = (a.L == 1) ? t : t / a.L;
+    const int64_t l = t - hb * a.L;
+    if (a.mode == kRowVec) {
+        const int lcv = a.logC - __builtin_ctz(V);  // log2(vectors per row)
+        const uint32_t n = tileE / V;
+        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
+            const uint32_t r = i >> lcv;
+            const uint32_t cc = i & ((1u << lcv) - 1u);
+            T v[V];
+            *reinterpret_cast<uint4*>(v) =
+                *reinterpret_cast<const uint4*>(in + row_offset(a, hb, l, r) + (int64_t)cc * V);
+            const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+            for (int e = 0; e < V; ++e) lds[ph + e] = to_c(v[e]);
+        }
+    } else {  // kRowScalar
+        const int64_t cvalid = a.S - (l << a.logC);  // > 0
+        const uint32_t Cm = (1u << a.logC) - 1u;
+        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+            const uint32_t r = i >> a.logC;
+            const uint32_t c = i & Cm;
+            C v = czero<C>();
+            if ((int64_t)c < cvalid) v = to_c(in[row_offset(a, hb, l, r) + c]);
+            lds[lds_phys(i, a.pad_shift)] = v;
+        }
+    }
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, int64_t t, uint32_t rows) {
+    constexpr int V = Vec16<T>::V;
+    T* __restrict__ out = static_cast<T*>(a.out);
+    const uint32_t tileE = rows << a.logC;
+    if (a.mode == kContigVec || a.mode == kContigScalar) {
+        const int64_t base = t * (int64_t)tileE;
+        if (a.mode == kContigVec) {
+            for (uint32_t i = threadIdx.x; i < tileE / V; i += kThreads) {
+                T v[V];
+                const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = from_c<T>(lds[ph + e]);
+                *reinterpret_cast<uint4*>(out + base + (int64_t)i * V) = *reinterpret_cast<const uint4*>(v);
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads)
+                out[base + i] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
+        }
+        return;
+    }
+    const int64_t hb = (a.L == 1) ? t : t / a.L;
+    const int64_t l = t - hb * a.L;
+    if (a.mode == kRowVec) {
+        const int lcv = a.logC - __builtin_ctz(V);
+        const uint32_t n = tileE / V;
+        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
+            const uint32_t r = i >> lcv;
+            const uint32_t cc = i & ((1u << lcv) - 1u);
+            T v[V];
+            const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+            for (int e = 0; e < V; ++e) v[e] = from_c<T>(lds[ph + e]);
+            *reinterpret_cast<uint4*>(out + row_offset(a, hb, l, r) + (int64_t)cc * V) =
+                *reinterpret_cast<const uint4*>(v);
+        }
+    } else {
+        const int64_t cvalid = a.S - (l << a.logC);
+        const uint32_t Cm = (1u << a.logC) - 1u;
+        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+            const uint32_t r = i >> a.logC;
+            const uint32_t c = i & Cm;
+            if ((int64_t)c < cvalid) out[row_offset(a, hb, l, r) + c] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
+        }
+    }
+}
+
+// W in registers.  Small matrices (<= 64 dwords) are read with uniform
+// addresses, which the compiler keeps in SGPRs (a VALU instruction may take one
+// SGPR operand).  Larger ones (complex radix 5..8) would spill SGPRs, so they
+// are staged through LDS, which places them in VGPRs.
+template <typename C, int B>
+__device__ __forceinline__ void load_w(C (&w)[B * B], const PassArgs& a) {
+    const C* __restrict__ Wg = static_cast<const C*>(a.W);
+    if constexpr (B * B * sizeof(C) <= 128) {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int q = 0; q < B; ++q) w[r * B + q] = a.adjoint ? cconj(Wg[q * B + r]) : Wg[r * B + q];
+    } else {
+        __shared__ C wl[B * B];
+        for (int e = threadIdx.x; e < B * B; e += kThreads) {
+            const int r = e / B, q = e % B;
+            wl[e] = a.adjoint ? cconj(Wg[q * B + r]) : Wg[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < B * B; ++e) w[e] = wl[e];
+    }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
+    using C = typename Tr<T>::C;
+    constexpr int RD = RegDigits<B>::v;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* lds = reinterpret_cast<C*>(smem_raw);
+    C w[B * B];
+    load_w<C, B>(w, a);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, C>(lds, a, t, rows);
+        __syncthreads();
+        run_stages<C, B, RD>(lds, a, rows, w);
+        tile_store<T, C>(lds, a, t, rows);
+        __syncthreads();
+    }
+}
+
+}  // namespace gtt
+
+namespace gtt {
+
+// ---------------------------------------------------------------------------
+// Runtime-radix group pass (any radix up to 64, mixed radices allowed): used
+// for radices without a specialised kernel and for heterogeneous transforms
+// (§2.6, remark on distinct factors).  One digit per LDS sweep, out of place
+// between two LDS buffers; W matrices are staged in LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) {
+    using C = typename Tr<T>::C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* Wl = reinterpret_cast<C*>(smem_raw);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t wpad = ((uint32_t)a.wtotal + 15u) & ~15u;
+    C* buf0 = Wl + wpad;
+    C* buf1 = buf0 + tileE;
+    {
+        const C* __restrict__ Wg = static_cast<const C*>(a.W);
+        for (int j = 0, done = 0; j < a.k; ++j) {
+            // each group digit gets its own copy (offset = running sum)
+            const int bj = a.rad[j];
+            for (int e = threadIdx.x; e < bj * bj; e += kThreads) {
+                const int r = e / bj, q = e - r * bj;
+                Wl[done + e] = a.adjoint ? cconj(Wg[a.wofs[j] + q * bj + r]) : Wg[a.wofs[j] + e];
+            }
+            done += bj * bj;
+        }
+    }
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, C>(buf0, a, t, rows);
+        __syncthreads();
+        C* src = buf0;
+        C* dst = buf1;
+        int woff = 0;
+        for (int j = 0; j < a.k; ++j) {
+            const uint32_t bj = (uint32_t)a.rad[j];
+            const uint32_t pv = (uint32_t)a.bpow[j];
+            const C* Wj = Wl + woff;
+            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+                const uint32_t c = i & Cm;
+                const uint32_t r = i >> a.logC;
+                const uint32_t hi = fdiv(r, a.divb[j]);      // r / pv
+                const uint32_t d = hi - fdiv(hi, a.divrad[j]) * bj;  // digit j of r
+                const uint32_t r0 = r - d * pv;
+                C acc = czero<C>();
+                for (uint32_t q = 0; q < bj; ++q)
+                    acc = cmac(acc, Wj[d * bj + q], src[((r0 + q * pv) << a.logC) | c]);
+                dst[i] = acc;
+            }
+            __syncthreads();
+            C* tmp = src; src = dst; dst = tmp;
+            woff += (int)(bj * bj);
+        }
+        tile_store<T, C>(src, a, t, rows);
+        __syncthreads();
+    }
+}
+
+}  // namespace gtt

@@ -1,0 +1,126 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+passes its host self-test, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+torch = pytest.importorskip("torch")
+from paper_2507_02420_amd import gtt as G  # noqa: E402
+
+
+def header_symbols():
+    with open(os.path.join(ROOT, "include", "gtt.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:gtt_status|const char\*)\s+(gtt_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_match_header():
+    L = G.lib()
+    syms = header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(G.EXPORTS) == syms
+
+
+def test_selftest():
+    assert G.selftest() == 0
+
+
+def test_status_strings():
+    L = G.lib()
+    for code, name in G.STATUS_NAMES.items():
+        assert L.gtt_status_string(code).decode() == name
+
+
+def _plan(count, b, n, batch=1, dtype=G.F32, flags=0, x_off=None, w_idx=None):
+    L = G.lib()
+    h = ctypes.c_void_p()
+    arr = lambda t, v: None if v is None else (t * len(v))(*v)
+    st = L.gtt_plan(ctypes.byref(h), count, arr(ctypes.c_int32, b), arr(ctypes.c_int32, n), batch,
+                    arr(ctypes.c_int64, x_off), arr(ctypes.c_int32, w_idx), dtype, flags)
+    return st, h
+
+
+def test_plan_validation():
+    L = G.lib()
+    assert _plan(1, [1], [3])[0] == 2          # b < 2
+    assert _plan(1, [2], [-1])[0] == 2         # n < 0
+    assert _plan(1, [2], [80])[0] == 2         # b^n overflows
+    assert _plan(1, [2], [4], batch=0)[0] == 2
+    assert _plan(1, [2], [4], dtype=9)[0] == 3
+    assert _plan(1, [2], [4], flags=0x100)[0] == 1
+    assert _plan(0, [2], [4])[0] == 1
+    assert _plan(2, [2, 4], [4, 2], batch=2)[0] == 2
+    assert _plan(2, [2, 4], [4, 2], w_idx=[0, 0])[0] == 1   # W index used with two radices
+    assert _plan(2, [2, 4], [4, 2], w_idx=[0, 2])[0] == 1   # W index 1 unused
+    h = ctypes.c_void_p()
+    assert L.gtt_plan(None, 1, (ctypes.c_int32 * 1)(2), (ctypes.c_int32 * 1)(3), 1, None, None, 1, 0) == 1
+    st, h = _plan(1, [3], [0])
+    assert st == 0
+    assert L.gtt_plan_destroy(h) == 0
+    assert L.gtt_plan_destroy(None) == 0
+
+
+def test_call_validation_before_any_hip_call():
+    L = G.lib()
+    st, h = _plan(1, [2], [10])
+    assert st == 0
+    a, m = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x10004)
+    S = ctypes.c_void_p()
+    assert L.gtt_forward(h, a, a, None, None, None, 0, S) == 1
+    assert L.gtt_forward(None, a, a, a, None, None, 0, S) == 1
+    assert L.gtt_forward(h, a, m, a, None, None, 0, S) == 4
+    assert L.gtt_forward(h, a, a, m, None, None, 0, S) == 4
+    assert L.gtt_inverse(h, m, a, a, None, 0, S) == 4
+    assert L.gtt_backward(h, a, a, None, a, None, None, None, 0, S) == 1
+    assert L.gtt_backward(h, a, a, m, a, a, a, None, 0, S) == 4
+    assert L.gtt_filter(h, a, a, -1, a, None, None, 0, S) == 1
+    L.gtt_plan_destroy(h)
+    st, h = _plan(1, [2], [10], dtype=G.I32)
+    assert L.gtt_backward(h, a, a, None, a, a, a, None, 0, S) == 6
+    L.gtt_plan_destroy(h)
+
+
+def test_tuning_validation():
+    L = G.lib()
+    assert L.gtt_set_tuning(1, G.F32, 0, 0) == 1
+    assert L.gtt_set_tuning(2, G.F32, 200 * 1024, 0) == 1
+
+
+def _describe(b, n, batch, dtype):
+    p = G.Plan(b, n, batch, dtype)
+    return p.describe()
+
+
+@pytest.mark.parametrize("b,n,batch,dtype,R", [
+    (2, 10, 1, torch.float64, 1),          # single FP64 vector, N = 1024
+    (4, 10, 64, torch.complex64, 2),       # 64 x 4^10 complex64
+    (3, 13, 16, torch.float32, 2),         # 16 x 3^13 float32
+    (2, 20, 16, torch.int32, 2),           # 16 x 2^20 int32
+    (8, 6, 256, torch.complex64, 2),       # 256 x 8^6 complex64
+])
+def test_plan_groups_for_workloads(b, n, batch, dtype, R):
+    d = _describe(b, n, batch, dtype)
+    gs = d["groups"]
+    assert len(gs) == R
+    assert sum(g["k"] for g in gs) == n
+    assert gs[0]["S"] == 1 and gs[0]["C"] == 1
+    for g in gs:
+        assert g["lds_bytes"] <= 160 * 1024
+        assert g["tiles"] * g["tile_elems"] >= (b ** n) * batch
+        if g["S"] > 1:
+            # strided groups read rows of at least 64 contiguous bytes
+            assert g["C"] * {torch.float64: 8, torch.complex64: 8, torch.float32: 4,
+                             torch.int32: 4}[dtype] >= 64
+
+
+def test_mixed_plan_and_describe():
+    p = G.Plan.mixed([2, 3, 4, 5], batch=3, dtype=torch.complex64)
+    d = p.describe()
+    assert d["kind"] == "mixed"
+    assert sum(g["k"] for g in d["groups"]) == 4

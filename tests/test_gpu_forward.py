@@ -1,0 +1,150 @@
+"""GPU parity of forward and inverse against the FP64 oracle, element by
+element, over radices, digit counts, batch sizes, dtypes and edge cases
+(sizes span several tiles and more than one digit group, ragged column
+blocks for odd radices, n = 0 and n = 1)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import COMPLEX, TOL, host64, make_inputs, rel_err, say
+from oracle import gtt_oracle as O
+from paper_2507_02420_amd import gtt as G
+
+pytestmark = pytest.mark.gpu
+
+FLOAT_DTYPES = [torch.float64, torch.float32, torch.complex64, torch.complex128, torch.bfloat16, torch.float16]
+
+# (b, n): small, multi-tile single group, and multi-group shapes
+SHAPES = [(2, 1), (2, 5), (2, 12), (2, 17), (3, 1), (3, 7), (3, 11), (4, 3), (4, 7), (4, 9),
+          (5, 4), (5, 7), (6, 3), (6, 6), (7, 3), (7, 6), (8, 2), (8, 4), (8, 6),
+          (9, 3), (11, 3), (16, 3), (32, 2), (16, 4)]
+
+
+def _skip_big(b, n, batch, dtype):
+    return (b ** n) * batch > (1 << 20) and dtype in (torch.complex128,)
+
+
+@pytest.mark.parametrize("dtype", FLOAT_DTYPES, ids=str)
+@pytest.mark.parametrize("b,n", SHAPES)
+def test_forward_matches_oracle(b, n, dtype):
+    batch = 3
+    if _skip_big(b, n, batch, dtype):
+        pytest.skip("size")
+    say(f"forward b={b} n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=1000 + 17 * b + n)
+    plan = G.Plan(b, n, batch, dtype)
+    y = plan.forward(W, x)
+    torch.cuda.synchronize()
+    ref = O.staged(W64, x64, n)
+    err = rel_err(host64(y), ref)
+    assert err < TOL[dtype], (b, n, dtype, err, plan.describe())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64, torch.bfloat16], ids=str)
+@pytest.mark.parametrize("b,n", [(2, 14), (3, 9), (4, 8), (5, 5), (8, 5), (16, 3)])
+def test_inverse_matches_oracle_and_roundtrip(b, n, dtype):
+    batch = 2
+    say(f"inverse b={b} n={n} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=2000 + 13 * b + n)
+    plan = G.Plan(b, n, batch, dtype)
+    xi = plan.inverse(W, x)
+    torch.cuda.synchronize()
+    assert rel_err(host64(xi), O.adjoint(W64, x64, n)) < TOL[dtype]
+    # forward then inverse recovers x (W unitary)
+    y = plan.forward(W, x)
+    back = plan.inverse(W, y)
+    torch.cuda.synchronize()
+    assert rel_err(host64(back), x64) < 3 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.bfloat16], ids=str)
+@pytest.mark.parametrize("b,n", [(2, 16), (3, 10), (4, 8), (8, 5)])
+def test_in_place(b, n, dtype):
+    say(f"in-place b={b} n={n} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, 2, dtype, seed=3000 + b + n)
+    plan = G.Plan(b, n, 2, dtype)
+    plan.forward(W, x, y=x)
+    torch.cuda.synchronize()
+    assert rel_err(host64(x), O.staged(W64, x64, n)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", FLOAT_DTYPES + [torch.int32], ids=str)
+def test_n_zero_is_identity(dtype):
+    say(f"n=0 dtype={dtype}")
+    x = torch.arange(5, dtype=torch.float64).to(dtype).cuda().reshape(5, 1)
+    W = torch.eye(3, dtype=G.W_DTYPE[dtype]).cuda()
+    plan = G.Plan(3, 0, 5, dtype)
+    y = plan.forward(W, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y.cpu(), x.cpu())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64, torch.bfloat16, torch.int32],
+                         ids=str)
+def test_signed_permutation_w_is_exact(dtype):
+    # products with 0 and +-1 and sums with exact zeros are exact in every dtype
+    b, n, batch = 4, 7, 2
+    say(f"signed permutation dtype={dtype}")
+    perm = np.array([2, 0, 3, 1])
+    sign = np.array([1, -1, -1, 1])
+    Wn = np.zeros((4, 4))
+    Wn[np.arange(4), perm] = sign
+    rng = np.random.default_rng(7)
+    if dtype == torch.int32:
+        xn = rng.integers(-1000, 1000, size=(batch, b ** n))
+    else:
+        xn = rng.standard_normal((batch, b ** n))
+    xt = torch.from_numpy(xn).to(dtype).cuda()
+    Wt = torch.from_numpy(Wn).to(G.W_DTYPE[dtype]).cuda()
+    y = G.Plan(b, n, batch, dtype).forward(Wt, xt)
+    torch.cuda.synchronize()
+    x64 = xt.cpu().to(torch.float64).numpy()
+    ref = O.staged(Wn, x64, n)
+    got = y.cpu().to(torch.float64).numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_dft_base_matrix_is_fftn_on_gpu():
+    # W = DFT_3: the transform is the 13-dimensional DFT of the 3 x ... x 3 array
+    from paper_2507_02420_amd.inputs import dft_matrix
+    b, n, batch = 3, 13, 2
+    say("dft3 n=13")
+    x, W, x64, W64 = make_inputs(b, n, batch, torch.complex64, seed=31, W=dft_matrix(3))
+    y = G.Plan(b, n, batch, torch.complex64).forward(W, x)
+    torch.cuda.synchronize()
+    ref = np.fft.fftn(x64.reshape([batch] + [b] * n), axes=tuple(range(1, n + 1)), norm="ortho").reshape(batch, -1)
+    assert rel_err(host64(y), ref) < 1e-5
+
+
+def test_determinism_bitwise():
+    b, n, batch = 4, 9, 3
+    x, W, _, _ = make_inputs(b, n, batch, torch.complex64, seed=41)
+    plan = G.Plan(b, n, batch, torch.complex64)
+    y1 = plan.forward(W, x).clone()
+    y2 = plan.forward(W, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64], ids=str)
+def test_mixed_radix_matches_kron(dtype):
+    radices = [2, 3, 4, 5, 3]     # W_0 acts on the most significant digit
+    Ns = int(np.prod(radices))
+    batch = 3
+    say(f"mixed radix {radices} dtype={dtype}")
+    cplx = dtype in COMPLEX
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+    Ws = [haar_unitary(r, 50 + i, complex_=cplx) for i, r in enumerate(radices)]
+    x = gaussian((batch, Ns), seed=60, complex_=cplx)
+    wdt = G.W_DTYPE[dtype]
+    Wt = torch.cat([torch.from_numpy(w).to(wdt).reshape(-1) for w in Ws]).cuda()
+    xt = torch.from_numpy(x).to(dtype).cuda()
+    plan = G.Plan.mixed(radices, batch, dtype)
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    Ws64 = [torch.from_numpy(w).to(wdt).to(torch.complex128).numpy() for w in Ws]
+    x64 = host64(xt)
+    ref = O.staged_mixed(Ws64, x64)
+    assert rel_err(host64(y), ref) < TOL[dtype]
+    assert rel_err(host64(xi), x64) < 3 * TOL[dtype]
