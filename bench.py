@@ -1,0 +1,336 @@
+"""Benchmark of the fast generalized tensor transform on one MI355X.
+
+Headline: forward + backward (dL/dx and dL/dW) of 256 complex64 vectors,
+b = 8, n = 6 (N = 262,144; 67,108,864 elements), W a random 8 x 8 unitary,
+loss L = Re <g, y>.  One step = gtt_forward (keeping the activations between
+digit groups) + gtt_backward, inputs resident in HBM.  value = elements per
+second of that step.
+
+The JSON line also carries:
+  roofline     -- the kernel with the largest share of the timed region, its
+                  algorithmic HBM bytes per launch over its HIP-event duration,
+                  against the 8 TB/s HBM peak;
+  cpu_baseline -- the FP64 oracle (numpy, one core) on a bounded sample of the
+                  same workload, and the GPU error against it on that sample;
+  workloads    -- the other configurations (single FP64 vector, complex64
+                  round trip, odd radix, int32 Hadamard, ragged bf16 batch vs
+                  the plain FP32 path), a few timed calls each.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTT fwd+bwd elements/s and % of HBM roofline vs plain FP32 at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_calls(fn, iters, flush=None):
+    """Median milliseconds of fn() over iters calls, timed with HIP events on
+    the current stream (the stream every call is enqueued on)."""
+    ts = []
+    for _ in range(iters):
+        if flush is not None:
+            flush()
+        s, e = _events()
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e))
+    ts.sort()
+    return ts[len(ts) // 2], ts
+
+
+def dominant(timing: dict):
+    name = max(timing, key=lambda k: timing[k]["total_ms"])
+    t = timing[name]
+    achieved = t["bytes_per_launch"] / (t["avg_ms"] * 1e-3) / 1e9
+    return name, t, achieved
+
+
+def load_traffic(kernel_name: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    for this kernel (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel factor)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = d.get("kernels", {}).get(kernel_name)
+    if not ent or ent.get("stale"):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# headline workload
+# ---------------------------------------------------------------------------
+def headline(steps, warmup):
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+
+    b, n, batch = 8, 6, 256
+    N = b ** n
+    E = N * batch
+    dev = torch.device("cuda:0")
+    # seeded inputs: x (seed 41), W (seed 42), g (seed 43), generated per
+    # instance block to bound host memory
+    x = torch.empty(batch, N, dtype=torch.complex64, device=dev)
+    g = torch.empty(batch, N, dtype=torch.complex64, device=dev)
+    for i0 in range(0, batch, 32):
+        x[i0:i0 + 32] = torch.from_numpy(gaussian((32, N), seed=41 * 1000 + i0, complex_=True).astype(np.complex64))
+        g[i0:i0 + 32] = torch.from_numpy(gaussian((32, N), seed=43 * 1000 + i0, complex_=True).astype(np.complex64))
+    W = torch.from_numpy(haar_unitary(b, 42).astype(np.complex64)).to(dev)
+    plan = G.Plan(b, n, batch, torch.complex64)
+    _, bwd_ws, sv = plan.workspace_size()
+    saved = torch.empty(sv, dtype=torch.uint8, device=dev)
+    y = torch.empty_like(x)
+    gx = torch.empty_like(x)
+    gW = torch.empty_like(W)
+
+    def step():
+        plan.forward(W, x, y, saved=saved)
+        plan.backward(W, x, g, saved=saved, gx=gx, gW=gW)
+
+    for _ in range(warmup):
+        step()
+    _sync()
+    plan.timing(True)
+    _sync()
+    s, e = _events()
+    t0 = time.perf_counter()
+    s.record()
+    for _ in range(steps):
+        step()
+    e.record()
+    _sync()
+    wall = time.perf_counter() - t0
+    plan.timing(False)
+    ms = s.elapsed_time(e) / steps
+    timing = plan.timing_read()
+    name, t, achieved = dominant(timing)
+    out = {
+        "E": E, "ms_per_step": ms, "wall_s": wall, "timing": timing, "plan": plan.describe(),
+        "dominant": name, "achieved_GBs": achieved, "bytes_per_launch": t["bytes_per_launch"],
+        "tensors": (x, g, W, y, gx, gW),
+    }
+    return out
+
+
+def cpu_baseline_headline(tensors, budget_s=20.0):
+    """FP64 oracle (numpy, single core) on a bounded sample of the headline
+    workload: forward + gradient of whole instances, timed; also the GPU
+    error on those instances."""
+    from oracle import gtt_oracle as O
+    x, g, W, y, gx, gW = tensors
+    b, n = 8, 6
+    W64 = W.cpu().to(__import__("torch").complex128).numpy()
+    try:
+        prev = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(prev)})
+    except (AttributeError, OSError):
+        prev = None
+    done = 0
+    errs_y, errs_gx = [], []
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    for i in (0, 97, 200, 255, 31, 64, 128, 150, 180, 220):
+        xi = x[i].cpu().numpy().astype(np.complex128)
+        gi = g[i].cpu().numpy().astype(np.complex128)
+        ts = time.perf_counter()
+        yi = O.staged(W64, xi, n)
+        gxi, _ = O.grad(W64, xi, gi, n)
+        elapsed += time.perf_counter() - ts
+        done += 1
+        errs_y.append(float(np.linalg.norm(y[i].cpu().numpy() - yi) / np.linalg.norm(yi)))
+        errs_gx.append(float(np.linalg.norm(gx[i].cpu().numpy() - gxi) / np.linalg.norm(gxi)))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    cores = 1
+    if prev is not None:
+        os.sched_setaffinity(0, prev)
+    elems = done * b ** n
+    return {
+        "value": elems / elapsed, "unit": "elements/s", "cores": cores, "kind": "oracle",
+        "sample": f"{done} of 256 instances (N=262144 c64 upcast to complex128): numpy staged forward + "
+                  f"stage-wise gradient, {elapsed:.2f} s on one pinned host core",
+        "gpu_rel_err_y_max": max(errs_y), "gpu_rel_err_gx_max": max(errs_gx),
+    }
+
+
+# ---------------------------------------------------------------------------
+# secondary workloads (GPU-only checks: round trips, bit exactness, the plain
+# FP32 path as reference for the bf16 ragged batch)
+# ---------------------------------------------------------------------------
+def secondary(iters=10):
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import (gaussian, hadamard2, haar_unitary, int_uniform, ragged_shapes,
+                                             uniform)
+    dev = torch.device("cuda:0")
+    res = {}
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    flush = lambda: scratch.zero_()  # evicts the 256 MB Infinity Cache
+
+    # single FP64 vector, b=2, n=10: Hadamard and random orthogonal W
+    x = torch.from_numpy(gaussian(1024, seed=11)).to(dev)
+    p = G.Plan(2, 10, 1, torch.float64)
+    for nm, W in (("hadamard", hadamard2(True)), ("orthogonal", haar_unitary(2, 12, complex_=False))):
+        Wt = torch.from_numpy(W).to(dev)
+        y = torch.empty_like(x)
+        ms, _ = time_calls(lambda: p.forward(Wt, x, y), iters * 5)
+        res[f"f64_b2_n10_{nm}"] = {"us_per_call": ms * 1e3, "elements_per_s": 1024 / (ms * 1e-3)}
+
+    # 64 x complex64, b=4, n=10: forward then inverse
+    b, n, batch = 4, 10, 64
+    x = torch.from_numpy(gaussian((batch, b ** n), seed=21, complex_=True).astype(np.complex64)).to(dev)
+    W = torch.from_numpy(haar_unitary(4, 22).astype(np.complex64)).to(dev)
+    p = G.Plan(b, n, batch, torch.complex64)
+    y = torch.empty_like(x)
+    xr = torch.empty_like(x)
+    p.timing(True)
+    ms, _ = time_calls(lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
+    tm = p.timing_read()
+    p.timing(False)
+    E = batch * b ** n
+    nm_, t_, ach = dominant(tm)
+    err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
+    res["c64_b4_n10_x64_fwd_inv"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err,
+                                     "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+
+    # 16 x float32, b=3, n=13 (odd strides), MALL flushed
+    b, n, batch = 3, 13, 16
+    x = torch.from_numpy(uniform((batch, b ** n), seed=31).astype(np.float32)).to(dev)
+    W = torch.from_numpy(haar_unitary(3, 32, complex_=False).astype(np.float32)).to(dev)
+    p = G.Plan(b, n, batch, torch.float32)
+    y = torch.empty_like(x)
+    p.timing(True)
+    ms, _ = time_calls(lambda: p.forward(W, x, y), iters, flush=flush)
+    tm = p.timing_read()
+    p.timing(False)
+    xr = p.inverse(W, y)
+    err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
+    E = batch * b ** n
+    nm_, t_, ach = dominant(tm)
+    res["f32_b3_n13_x16_fwd"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err,
+                                 "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+
+    # 16 x int32, b=2, n=20, unnormalised Hadamard, MALL flushed; bit-exact
+    b, n, batch = 2, 20, 16
+    xi = torch.from_numpy(int_uniform((batch, b ** n), seed=33, lo=-100, hi=100)).to(torch.int32).to(dev)
+    H = torch.from_numpy(hadamard2(False)).to(torch.int32).to(dev)
+    p = G.Plan(b, n, batch, torch.int32)
+    y = torch.empty_like(xi)
+    p.timing(True)
+    ms, _ = time_calls(lambda: p.forward(H, xi, y), iters, flush=flush)
+    tm = p.timing_read()
+    p.timing(False)
+    back = p.inverse(H, y)
+    exact = bool(torch.equal(back, xi * (1 << n)))
+    E = batch * b ** n
+    nm_, t_, ach = dominant(tm)
+    res["i32_hadamard_b2_n20_x16_fwd"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
+                                          "inverse_of_forward_is_2^n_x_exactly": exact,
+                                          "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+
+    # ragged bf16 batch: 1024 instances, b in {2,4,16,32}, N in [2^10, 2^20]
+    shapes = ragged_shapes(1024, seed=52)
+    bs = [s_[0] for s_ in shapes]
+    ns = [s_[1] for s_ in shapes]
+    Ntot = sum(b_ ** n_ for b_, n_ in shapes)
+    rng = np.random.default_rng(53)
+    x32 = torch.from_numpy(rng.standard_normal(Ntot, dtype=np.float32)).to(dev)
+    xb = x32.to(torch.bfloat16)
+    xf = xb.to(torch.float32)     # the same values, plain FP32 storage
+    Ws = [haar_unitary(r, 54 + i, complex_=False).astype(np.float32) for i, r in enumerate((2, 4, 16, 32))]
+    Wt = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).to(dev)
+    pb = G.Plan(bs, ns, 1, torch.bfloat16)
+    pf = G.Plan(bs, ns, 1, torch.float32)
+    yb = torch.empty_like(xb)
+    yf = torch.empty_like(xf)
+    msb, _ = time_calls(lambda: pb.forward(Wt, xb, yb), 3)
+    msf, _ = time_calls(lambda: pf.forward(Wt, xf, yf), 3)
+    # per-instance error of the bf16 path against the plain FP32 path
+    offs = np.cumsum([0] + [b_ ** n_ for b_, n_ in shapes])
+    yb32 = yb.to(torch.float32)
+    errs = []
+    for t in range(0, 1024, 8):
+        a, c = int(offs[t]), int(offs[t + 1])
+        errs.append(float((torch.linalg.vector_norm(yb32[a:c] - yf[a:c]) / torch.linalg.vector_norm(yf[a:c])).item()))
+    res["ragged_bf16_1024"] = {"elements": Ntot, "ms_bf16": msb, "elements_per_s_bf16": Ntot / (msb * 1e-3),
+                               "ms_plain_fp32": msf, "elements_per_s_plain_fp32": Ntot / (msf * 1e-3),
+                               "rel_err_vs_fp32_max": max(errs), "rel_err_vs_fp32_median": float(np.median(errs)),
+                               "instances_checked": len(errs)}
+    del scratch
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    print("bench: headline fwd+bwd 256 x 8^6 c64", file=sys.stderr, flush=True)
+    h = headline(args.steps, args.warmup)
+    E = h["E"]
+    value = E / (h["ms_per_step"] * 1e-3)
+    roof = {"bound": "hbm", "achieved": h["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": h["achieved_GBs"] / HBM_PEAK_GBS, "traffic": load_traffic(h["dominant"], "c64_b8_n6_x256"),
+            "kernel": h["dominant"], "algorithmic_bytes_per_launch": h["bytes_per_launch"]}
+    cpu = None
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_headline(h["tensors"])
+    extra = None
+    if not args.no_extra:
+        print("bench: secondary workloads", file=sys.stderr, flush=True)
+        extra = secondary()
+    line = {
+        "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "fwd+bwd: 256 x complex64, b=8, n=6 (N=262144), W 8x8 unitary, L=Re<g,y>",
+                   "b": 8, "n": 6, "batch": 256, "elements": E, "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu,
+        "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                    for k, v in h["timing"].items()},
+        "workloads": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,8 +80,12 @@ typedef enum gtt_dtype {
 #define GTT_FLAG_NO_TUNE 0x2u           /* ignore the tuning table; use the
                                            built-in heuristics */
 #define GTT_FLAG_PERSISTENT 0x4u        /* ragged batch: run every digit group
-                                           of every instance in one persistent
-                                           cooperative launch */
+                                           of every instance in ONE persistent
+                                           launch, grid barrier between digit
+                                           groups (default: one launch per
+                                           digit-group phase) */
+#define GTT_FLAG_PER_INSTANCE 0x8u      /* ragged batch: one launch per digit
+                                           group per instance (the plain path) */
 
 typedef struct gtt_plan_s* gtt_plan_t;
 
@@ -105,8 +109,12 @@ typedef struct gtt_plan_s* gtt_plan_t;
  * Errors: GTT_ERR_SHAPE (b < 2, n < 0, b^n overflows, batch < 1),
  * GTT_ERR_DTYPE, GTT_ERR_INVALID_VALUE (out == NULL, count < 1, bad
  * w_idx / x_off), GTT_ERR_UNSUPPORTED.  On error *out is set to NULL.
- * The plan holds host memory and, for ragged batches, a small device work
- * list (allocated here, freed by gtt_plan_destroy).
+ * The plan holds host memory and, for ragged batches, a device work list
+ * (one descriptor per instance and digit group, one entry per tile) and the
+ * grid-barrier words, allocated and uploaded by the first forward / inverse
+ * call (synchronously: do not make that first call inside a graph capture)
+ * and freed by gtt_plan_destroy.  Calls with GTT_FLAG_PERSISTENT share the
+ * plan's barrier words: do not run one such plan on two streams at once.
  */
 gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n,
                     int64_t batch, const int64_t* x_off, const int32_t* w_idx,
@@ -130,9 +138,10 @@ gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, in
  * gtt_workspace_size -- bytes of device workspace a call needs.
  *   fwd   : forward and inverse (currently 0 unless the FP32-intermediate
  *           flag is set);
- *   bwd   : backward when `saved` is NULL (includes room to recompute the
- *           group-boundary activations); when `saved` is passed, the smaller
- *           amount *bwd - *saved suffices;
+ *   bwd   : backward in the worst case (`saved` NULL, so the activations
+ *           between digit groups are recomputed, and gx NULL or equal to
+ *           gy, so the gradient between groups needs its own buffer); when
+ *           `saved` is passed, *bwd - *saved bytes suffice;
  *   saved : size of the optional `saved` buffer of forward/backward (the
  *           activations at the boundaries between digit groups).
  * Any output pointer may be NULL.
@@ -195,6 +204,19 @@ const char* gtt_status_string(gtt_status s);
  * (digit groups, tile shapes, launch sizes) into buf (truncated to len).
  */
 gtt_status gtt_plan_describe(gtt_plan_t p, char* buf, size_t len);
+
+/*
+ * gtt_plan_timing -- instrumentation: when enable != 0, every kernel launch
+ * made through this plan is bracketed by HIP events recorded on the call's
+ * stream.  gtt_plan_timing_read waits for the recorded events and writes a
+ * JSON object {name: {launches, total_ms, avg_ms, bytes_per_launch}} (one
+ * entry per kernel kind and digit group; bytes_per_launch is the algorithmic
+ * HBM traffic of one launch: 2 E s for a forward/inverse pass, 3 E s for a
+ * backward group), then forgets the recorded launches.  Timing mutates the
+ * plan: do not time a plan used concurrently by several threads.
+ */
+gtt_status gtt_plan_timing(gtt_plan_t p, int32_t enable);
+gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len);
 
 /*
  * gtt_set_tuning -- override the launch heuristics for plans created after

@@ -1,0 +1,29 @@
+// Instantiations of the backward and reduction kernels for storage type double.
+#include "gtt_bwd.hpp"
+#include "gtt_launch.hpp"
+
+namespace gtt {
+
+hipError_t launch_bwd_f64(const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    using T = double;
+    const void* k = a.b <= 8 ? reinterpret_cast<const void*>(gtt_bwd_kernel<T, 8>)
+                             : reinterpret_cast<const void*>(gtt_bwd_kernel<T, 16>);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (a.b <= 8)
+        hipLaunchKernelGGL((gtt_bwd_kernel<T, 8>), dim3(grid), dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((gtt_bwd_kernel<T, 16>), dim3(grid), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_f64(const void* partials, int64_t nparts, int bb, void* out, hipStream_t s) {
+    using C = typename Tr<double>::C;
+    hipLaunchKernelGGL(gtt_reduce_kernel<C>, dim3(1), dim3(kThreads), 0, s, static_cast<const C*>(partials),
+                       nparts, bb, static_cast<C*>(out));
+    return hipGetLastError();
+}
+
+}  // namespace gtt

@@ -108,13 +108,13 @@ static uint64_t pow2_floor(uint64_t v) { return v ? (uint64_t(1) << ilog2_floor(
 
 // Try to split the n digits into exactly R groups; group 0 contiguous, the
 // others strided with C columns.  Returns false if infeasible.
-static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t cmin_elems,
+static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t Gmax, int64_t cmin_elems,
                       std::vector<int>* ks) {
     const int n = (int)rad.size();
     // group 0: as many digits as fit
     int k0 = 0;
     int64_t g = 1;
-    while (k0 < n && g * rad[k0] <= T) g *= rad[k0++];
+    while (k0 < n && g * rad[k0] <= std::min(T, Gmax)) g *= rad[k0++];
     if (k0 == 0) return false;
     if (R == 1) {
         if (k0 < n) return false;
@@ -129,7 +129,7 @@ static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t cmi
     for (int r = 1; r < R && s < n; ++r) {
         int k = 0;
         int64_t G = 1;
-        while (s + k < n && G * rad[s + k] * cmin_elems <= T) G *= rad[s + k++];
+        while (s + k < n && G * rad[s + k] * cmin_elems <= T && G * rad[s + k] <= Gmax) G *= rad[s + k++];
         if (k == 0) return false;
         out.push_back(k);
         s += k;
@@ -142,10 +142,10 @@ static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t cmi
 }
 
 static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, int64_t total_elems,
-                       int64_t T, size_t esize, size_t csize, bool uniform_small_b,
-                       int64_t row_elems_target) {
+                       int64_t T, size_t esize, size_t csize, int kind, int64_t row_elems_target) {
     gr->s0 = s0;
     gr->k = k;
+    gr->elems = total_elems;
     gr->S = prod_range(rad, 0, s0);
     gr->G = prod_range(rad, s0, s0 + k);
     const int64_t GS = gr->G * gr->S;
@@ -180,11 +180,11 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         gr->mode = kRowScalar;
     }
     (void)V;
-    gr->generic = !uniform_small_b;
+    gr->kind = kind;
     // LDS padding: one element per register block (contiguous tiles) or per
     // row (strided tiles) breaks power-of-two bank strides; odd radices need none
     int pad = 31;
-    if (!gr->generic) {
+    if (gr->kind != kKindGeneric) {
         const int b = rad[s0];
         if ((b & (b - 1)) == 0) {
             const int nb = (b == 2) ? 16 : (b == 4) ? 16 : b;  // register block size
@@ -198,7 +198,7 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         if (pad < 31 && (gr->mode == kContigVec || gr->mode == kRowVec)) pad = std::max(pad, lv);
     }
     gr->pad_shift = pad;
-    if (gr->generic) {
+    if (gr->kind == kKindGeneric) {
         int64_t wtot = 0;
         for (int j = 0; j < k; ++j) wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
         gr->wtotal = (int)wtot;
@@ -212,15 +212,21 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
 
 // Plan the digit groups for one radix list.
 gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags,
-                       bool uniform, std::vector<Group>* groups) {
+                       bool uniform, std::vector<Group>* groups, std::vector<Group>* bwd_groups, bool ragged) {
     groups->clear();
+    if (bwd_groups) bwd_groups->clear();
     const int n = (int)rad.size();
     if (n == 0) return GTT_OK;
     const size_t es = storage_size(dt), cs = compute_size(dt);
     const int b0 = rad[0];
-    // specialised kernels: radix <= 8 (complex double: <= 5, larger W would
-    // not fit in registers)
-    const bool small_b = uniform && (b0 <= 5 || (b0 <= 8 && dt != GTT_C128));
+    // specialised kernels: radix <= 8 on the VALU (complex double: <= 5,
+    // larger W would not fit in registers); radix 16 / 32 with 16-bit storage
+    // on the matrix cores; everything else on the runtime-radix kernel
+    int kind = kKindGeneric;
+    // (the one-launch ragged kernel carries the VALU code for radix <= 5 only)
+    if (uniform && (b0 <= 5 || (b0 <= 8 && dt != GTT_C128 && !ragged))) kind = kKindValu;
+    if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16)) kind = kKindMfma;
+    const bool small_b = kind != kKindGeneric;
     int tb = 0, tr = 0;
     tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr);
     std::vector<int64_t> budgets;
@@ -240,13 +246,25 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                 if (!small_b) T /= 2;  // the runtime-radix kernel double-buffers
                 const int64_t cmin = std::max<int64_t>(1, relax_row / (int64_t)es);
                 std::vector<int> ks;
-                if (!try_split(rad, R, T, cmin, &ks)) continue;
+                // a group's positions must fit three times in LDS for backward
+                const int64_t Gmax = (int64_t)(40 * 1024) / (int64_t)cs;
+                if (!try_split(rad, R, T, Gmax, cmin, &ks)) continue;
                 int s = 0;
                 for (int k : ks) {
                     Group g;
-                    fill_group(&g, rad, s, k, total, T, es, cs, small_b, cmin);
+                    fill_group(&g, rad, s, k, total, T, es, cs, kind, cmin);
                     groups->push_back(g);
                     s += k;
+                }
+                if (bwd_groups) {
+                    // backward: same digit groups, tiles of at most 40 KiB
+                    bwd_groups->clear();
+                    const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
+                    for (const Group& fg : *groups) {
+                        Group g;
+                        fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
+                        bwd_groups->push_back(g);
+                    }
                 }
                 return GTT_OK;
             }
@@ -262,7 +280,8 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
 // ---------------------------------------------------------------------------
 static DT to_dt(gtt_dtype d) { return static_cast<DT>((int)d); }
 
-static void fill_args(PassArgs* a, const Group& g, const std::vector<int>& rad, const std::vector<int64_t>& wofs,
+namespace gtt {
+void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, const std::vector<int64_t>& wofs,
                       int64_t N) {
     std::memset(a, 0, sizeof(*a));
     a->k = g.k;
@@ -291,33 +310,47 @@ static void fill_args(PassArgs* a, const Group& g, const std::vector<int>& rad, 
     }
     a->wtotal = g.wtotal;
 }
+}  // namespace gtt
 
-static gtt_status launch_group(gtt_dtype dt, const Group& g, const std::vector<int>& rad,
+static const char* dt_name(gtt_dtype d) {
+    static const char* n[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32"};
+    return n[(int)d];
+}
+
+static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, const std::vector<int>& rad,
                                const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
                                const void* in, void* out, hipStream_t s) {
     PassArgs a;
-    fill_args(&a, g, rad, wofs, N);
+    fill_pass_args(&a, g, rad, wofs, N);
     a.in = in;
     a.out = out;
     a.W = W;
     a.adjoint = adjoint ? 1 : 0;
     const unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, (int64_t)0x7fffffff);
-    hipError_t e = launch_pass(to_dt(dt), rad[g.s0], g.generic, a, grid, g.lds_bytes, s);
+    timing_begin(tp, s);
+    hipError_t e = launch_pass(to_dt(dt), rad[g.s0], g.kind, a, grid, g.lds_bytes, s);
+    if (tp && tp->timing.enabled) {
+        char nm[128];
+        std::snprintf(nm, sizeof nm, "pass %s b=%d%s s0=%d k=%d%s", dt_name(dt), rad[g.s0],
+                      g.kind == kKindGeneric ? " generic" : g.kind == kKindMfma ? " mfma" : "",
+                      g.s0, g.k, adjoint ? " adjoint" : "");
+        timing_end(tp, s, nm, 2.0 * (double)g.elems * (double)storage_size(dt));
+    }
     return e == hipSuccess ? GTT_OK : GTT_ERR_HIP;
 }
 
 namespace gtt {
-gtt_status launch_group_inst(gtt_dtype dt, const Group& g, int b, int64_t N, const void* W, bool adjoint,
-                             const void* in, void* out, hipStream_t s) {
+gtt_status launch_group_inst(gtt_plan_s* tp, gtt_dtype dt, const Group& g, int b, int64_t N, const void* W,
+                             bool adjoint, const void* in, void* out, hipStream_t s) {
     std::vector<int> rad(g.s0 + g.k, b);
     std::vector<int64_t> wofs(g.s0 + g.k, 0);
-    return launch_group(dt, g, rad, wofs, N, W, adjoint, in, out, s);
+    return launch_group(tp, dt, g, rad, wofs, N, W, adjoint, in, out, s);
 }
 }  // namespace gtt
 
 // Run a sequence of digit groups over one buffer set: group 0 reads `in`;
 // group i < R-1 writes `mid[i]` (or `out` when mid is null); the last writes out.
-static gtt_status run_groups(gtt_dtype dt, const std::vector<Group>& groups, const std::vector<int>& rad,
+static gtt_status run_groups(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>& groups, const std::vector<int>& rad,
                              const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
                              const void* in, void* out, char* saved, size_t elems, hipStream_t s) {
     const size_t es = storage_size(dt);
@@ -330,7 +363,7 @@ static gtt_status run_groups(gtt_dtype dt, const std::vector<Group>& groups, con
     for (size_t i = 0; i < groups.size(); ++i) {
         void* dst = out;
         if (i + 1 < groups.size() && saved) dst = saved + i * elems * es;
-        gtt_status st = launch_group(dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s);
+        gtt_status st = launch_group(tp, dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s);
         if (st != GTT_OK) return st;
         src = dst;
     }
@@ -375,7 +408,8 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
     *out = nullptr;
     if (count < 1 || !b || !n) return GTT_ERR_INVALID_VALUE;
     if (!valid_dtype((int)dtype)) return GTT_ERR_DTYPE;
-    if (flags & ~(GTT_FLAG_FP32_INTERMEDIATE | GTT_FLAG_NO_TUNE | GTT_FLAG_PERSISTENT)) return GTT_ERR_INVALID_VALUE;
+    if (flags & ~(GTT_FLAG_FP32_INTERMEDIATE | GTT_FLAG_NO_TUNE | GTT_FLAG_PERSISTENT | GTT_FLAG_PER_INSTANCE))
+        return GTT_ERR_INVALID_VALUE;
     if (flags & GTT_FLAG_FP32_INTERMEDIATE) return GTT_ERR_UNSUPPORTED;
     if (batch < 1) return GTT_ERR_SHAPE;
     if (count == 1 && (x_off || w_idx)) return GTT_ERR_INVALID_VALUE;
@@ -402,7 +436,7 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
         p->batch = batch;
         p->rad.assign(n[0], b[0]);
         p->wofs.assign(n[0], 0);
-        st = plan_groups(p->rad, batch, dtype, flags, true, &p->groups);
+        st = plan_groups(p->rad, batch, dtype, flags, true, &p->groups, &p->bwd_groups);
         p->total_elems = p->N * batch;
         p->w_elems = (int64_t)b[0] * b[0];
     } else {
@@ -457,7 +491,7 @@ gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, in
         p->rad[d] = radices[m - 1 - d];
         p->wofs[d] = fofs[m - 1 - d];
     }
-    gtt_status st = plan_groups(p->rad, batch, dtype, flags, false, &p->groups);
+    gtt_status st = plan_groups(p->rad, batch, dtype, flags, false, &p->groups, nullptr);
     if (st != GTT_OK) {
         delete p;
         return st;
@@ -493,7 +527,7 @@ gtt_status gtt_forward(gtt_plan_t p, const void* W, const void* x, void* y, void
     (void)ws_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, x, y, false, (char*)saved, s);
-    return run_groups(p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, y, (char*)saved,
+    return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, y, (char*)saved,
                       (size_t)p->total_elems, s);
 }
 
@@ -507,13 +541,26 @@ gtt_status gtt_inverse(gtt_plan_t p, const void* W, const void* y, void* x, void
     if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, y, x, true, nullptr, s);
     // the adjoint applies W^H per digit; digit passes commute, so the group
     // order of the forward plan is reused as is
-    return run_groups(p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, y, x, nullptr,
+    return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, y, x, nullptr,
                       (size_t)p->total_elems, s);
 }
 
 gtt_status gtt_plan_describe(gtt_plan_t p, char* buf, size_t len) {
     if (!p || !buf || len == 0) return GTT_ERR_INVALID_VALUE;
     std::string s = describe_plan(p);
+    std::snprintf(buf, len, "%s", s.c_str());
+    return GTT_OK;
+}
+
+gtt_status gtt_plan_timing(gtt_plan_t p, int32_t enable) {
+    if (!p) return GTT_ERR_INVALID_VALUE;
+    p->timing.enabled = enable != 0;
+    return GTT_OK;
+}
+
+gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len) {
+    if (!p || !buf || len == 0) return GTT_ERR_INVALID_VALUE;
+    std::string s = timing_read(p);
     std::snprintf(buf, len, "%s", s.c_str());
     return GTT_OK;
 }
@@ -558,7 +605,12 @@ gtt_status gtt_selftest(void) {
                 if (!pow_fits(b, n, &N) || N > (1 << 22)) break;
                 std::vector<int> rad(n, b);
                 std::vector<Group> gs;
-                if (plan_groups(rad, 3, dt, GTT_FLAG_NO_TUNE, true, &gs) != GTT_OK) return GTT_ERR_INTERNAL;
+                std::vector<Group> bgs;
+                if (plan_groups(rad, 3, dt, GTT_FLAG_NO_TUNE, true, &gs, &bgs) != GTT_OK) return GTT_ERR_INTERNAL;
+                if (bgs.size() != gs.size()) return GTT_ERR_INTERNAL;
+                for (size_t i = 0; i < gs.size(); ++i)
+                    if (bgs[i].s0 != gs[i].s0 || bgs[i].k != gs[i].k || bwd_lds_bytes(bgs[i], compute_size(dt), b) > 160 * 1024)
+                        return GTT_ERR_INTERNAL;
                 int s = 0;
                 for (const Group& g : gs) {
                     if (g.s0 != s || g.k < 1) return GTT_ERR_INTERNAL;

@@ -3,23 +3,101 @@
 
 namespace gtt {
 
-hipError_t launch_pass_f64(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_f32(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_c128(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_c64(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_bf16(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_f16(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_pass_i32(int, bool, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_f64(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_f32(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_c128(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_c64(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_bf16(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_f16(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_pass_i32(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 
-hipError_t launch_pass(DT dt, int b, bool generic, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_bwd_f64(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f32(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c128(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c64(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_bf16(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f16(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_reduce_f64(const void*, int64_t, int, void*, hipStream_t);
+hipError_t launch_reduce_f32(const void*, int64_t, int, void*, hipStream_t);
+hipError_t launch_reduce_c128(const void*, int64_t, int, void*, hipStream_t);
+hipError_t launch_reduce_c64(const void*, int64_t, int, void*, hipStream_t);
+hipError_t launch_reduce_bf16(const void*, int64_t, int, void*, hipStream_t);
+hipError_t launch_reduce_f16(const void*, int64_t, int, void*, hipStream_t);
+
+hipError_t launch_bwd(DT dt, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     switch (dt) {
-        case DT::F64: return launch_pass_f64(b, generic, a, grid, lds, s);
-        case DT::F32: return launch_pass_f32(b, generic, a, grid, lds, s);
-        case DT::C128: return launch_pass_c128(b, generic, a, grid, lds, s);
-        case DT::C64: return launch_pass_c64(b, generic, a, grid, lds, s);
-        case DT::BF16: return launch_pass_bf16(b, generic, a, grid, lds, s);
-        case DT::F16: return launch_pass_f16(b, generic, a, grid, lds, s);
-        case DT::I32: return launch_pass_i32(b, generic, a, grid, lds, s);
+        case DT::F64: return launch_bwd_f64(a, grid, lds, s);
+        case DT::F32: return launch_bwd_f32(a, grid, lds, s);
+        case DT::C128: return launch_bwd_c128(a, grid, lds, s);
+        case DT::C64: return launch_bwd_c64(a, grid, lds, s);
+        case DT::BF16: return launch_bwd_bf16(a, grid, lds, s);
+        case DT::F16: return launch_bwd_f16(a, grid, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s) {
+    switch (dt) {
+        case DT::F64: return launch_reduce_f64(partials, nparts, bb, out, s);
+        case DT::F32: return launch_reduce_f32(partials, nparts, bb, out, s);
+        case DT::C128: return launch_reduce_c128(partials, nparts, bb, out, s);
+        case DT::C64: return launch_reduce_c64(partials, nparts, bb, out, s);
+        case DT::BF16: return launch_reduce_bf16(partials, nparts, bb, out, s);
+        case DT::F16: return launch_reduce_f16(partials, nparts, bb, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ragged_f64(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_f64(size_t, int*);
+hipError_t launch_ragged_f32(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_f32(size_t, int*);
+hipError_t launch_ragged_c128(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_c128(size_t, int*);
+hipError_t launch_ragged_c64(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_c64(size_t, int*);
+hipError_t launch_ragged_bf16(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_bf16(size_t, int*);
+hipError_t launch_ragged_f16(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_f16(size_t, int*);
+hipError_t launch_ragged_i32(const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t ragged_occupancy_i32(size_t, int*);
+
+hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    switch (dt) {
+        case DT::F64: return launch_ragged_f64(a, grid, lds, s);
+        case DT::F32: return launch_ragged_f32(a, grid, lds, s);
+        case DT::C128: return launch_ragged_c128(a, grid, lds, s);
+        case DT::C64: return launch_ragged_c64(a, grid, lds, s);
+        case DT::BF16: return launch_ragged_bf16(a, grid, lds, s);
+        case DT::F16: return launch_ragged_f16(a, grid, lds, s);
+        case DT::I32: return launch_ragged_i32(a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t ragged_occupancy(DT dt, size_t lds, int* b) {
+    switch (dt) {
+        case DT::F64: return ragged_occupancy_f64(lds, b);
+        case DT::F32: return ragged_occupancy_f32(lds, b);
+        case DT::C128: return ragged_occupancy_c128(lds, b);
+        case DT::C64: return ragged_occupancy_c64(lds, b);
+        case DT::BF16: return ragged_occupancy_bf16(lds, b);
+        case DT::F16: return ragged_occupancy_f16(lds, b);
+        case DT::I32: return ragged_occupancy_i32(lds, b);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(DT dt, int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    switch (dt) {
+        case DT::F64: return launch_pass_f64(b, kind, a, grid, lds, s);
+        case DT::F32: return launch_pass_f32(b, kind, a, grid, lds, s);
+        case DT::C128: return launch_pass_c128(b, kind, a, grid, lds, s);
+        case DT::C64: return launch_pass_c64(b, kind, a, grid, lds, s);
+        case DT::BF16: return launch_pass_bf16(b, kind, a, grid, lds, s);
+        case DT::F16: return launch_pass_f16(b, kind, a, grid, lds, s);
+        case DT::I32: return launch_pass_i32(b, kind, a, grid, lds, s);
     }
     return hipErrorInvalidValue;
 }

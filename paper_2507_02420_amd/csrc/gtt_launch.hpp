@@ -9,9 +9,24 @@ namespace gtt {
 
 enum class DT : int { F64 = 0, F32 = 1, C128 = 2, C64 = 3, BF16 = 4, F16 = 5, I32 = 6 };
 
-// forward / inverse digit-group pass (specialised radix 2..8, else the
-// runtime-radix kernel; `generic` forces the runtime-radix kernel)
-hipError_t launch_pass(DT dt, int b, bool generic, const PassArgs& a, unsigned grid, size_t lds,
-                       hipStream_t s);
+// kernel families of a digit-group pass
+constexpr int kKindValu = 0;     // radix 2..8, register super-stages on the VALU
+constexpr int kKindGeneric = 1;  // any radix <= 64 and mixed radices, LDS sweeps
+constexpr int kKindMfma = 2;     // radix 16 / 32, bf16 / f16 storage, matrix cores
+
+// forward / inverse digit-group pass
+hipError_t launch_pass(DT dt, int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
+
+struct BwdArgs;
+// backward of one digit group (runtime radix <= 16, floating dtypes)
+hipError_t launch_bwd(DT dt, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
+// gW = fixed-order sum of nparts partial vectors of bb compute-dtype values
+hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s);
+
+struct RaggedArgs;
+// ragged-batch launch (all phases with grid barriers, or one phase)
+hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s);
+// co-resident work-groups per compute unit of the ragged kernel
+hipError_t ragged_occupancy(DT dt, size_t lds, int* blocks_per_cu);
 
 }  // namespace gtt

@@ -1,0 +1,164 @@
+// Digit-group pass on the matrix cores for radix 16 and 32 with bf16 / f16
+// storage.  Each digit pass is the product Y = W X (§3: Y = X W^T in the
+// paper's row layout) with X the b x F matrix whose columns are the fibres of
+// that digit, a dense contraction that maps onto the 16x16x16 MFMA:
+//   A operand (W, 16 x 16 block): lane l holds W[i = l%16][4*(l/16) + 0..3];
+//   B operand (X, 16 x 16 block): lane l holds X[4*(l/16) + 0..3][fibre l%16];
+//   result: lane l holds Y[4*(l/16) + 0..3][fibre l%16].
+// Input and output fragments have the same layout, so a wave reads four
+// consecutive elements of its fibre from LDS, runs the MFMAs and writes four
+// consecutive results back in place.  Radix 32 uses the 2 x 2 blocks of W.
+// The tile stays FP32 in LDS between digits; the operand of every MFMA is
+// rounded to the 16-bit type (round to nearest even), W is split into a high
+// and a low 16-bit part (two MFMAs) so that its rounding adds no error, and
+// accumulation is FP32.
+#pragma once
+
+#include "gtt_args.hpp"
+#include "gtt_pass.hpp"
+#include "gtt_types.hpp"
+
+namespace gtt {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaOp;
+
+template <>
+struct MfmaOp<bf16> {
+    using V = s16x4;
+    using E = short;
+    __device__ static V pack(const float (&x)[4]) {
+        V r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = __builtin_bit_cast(short, (__bf16)x[i]);
+        return r;
+    }
+    __device__ static float unpack1(short v) { return __uint_as_float(((uint32_t)(uint16_t)v) << 16); }
+    __device__ static void split(float w, short* hi, short* lo) {
+        const __bf16 h = (__bf16)w;
+        *hi = __builtin_bit_cast(short, h);
+        *lo = __builtin_bit_cast(short, (__bf16)(w - (float)h));
+    }
+    __device__ static f32x4 mma(V a, V b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+};
+
+template <>
+struct MfmaOp<f16> {
+    using V = h16x4;
+    using E = _Float16;
+    __device__ static V pack(const float (&x)[4]) {
+        V r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = (_Float16)x[i];
+        return r;
+    }
+    __device__ static void split(float w, _Float16* hi, _Float16* lo) {
+        const _Float16 h = (_Float16)w;
+        *hi = h;
+        *lo = (_Float16)(w - (float)h);
+    }
+    __device__ static f32x4 mma(V a, V b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+};
+
+template <typename T, int B>
+struct WFrag {
+    static constexpr int NB = B / 16;
+    typename MfmaOp<T>::V hi[NB][NB], lo[NB][NB];
+};
+
+template <typename T, int B>
+__device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) {
+    using Op = MfmaOp<T>;
+    const float* __restrict__ Wg = static_cast<const float*>(a.W);
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int bi = 0; bi < WFrag<T, B>::NB; ++bi)
+#pragma unroll
+        for (int bk = 0; bk < WFrag<T, B>::NB; ++bk)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bi + i, c = 16 * bk + 4 * q + v;
+                const float w = a.adjoint ? Wg[c * B + r] : Wg[r * B + c];
+                typename Op::E h, l;
+                Op::split(w, &h, &l);
+                wf.hi[bi][bk][v] = h;
+                wf.lo[bi][bk][v] = l;
+            }
+}
+
+// W along digit j of every fibre of the FP32 tile, in place, on MFMA.
+template <typename T, int B>
+__device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j, uint32_t rows,
+                                           const WFrag<T, B>& wf) {
+    using Op = MfmaOp<T>;
+    constexpr int NB = B / 16;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t F = (rows << a.logC) / B;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t bj1 = (uint32_t)a.bpow[j + 1];
+    const uint32_t step = bj << a.logC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int q = lane >> 4;
+    const uint32_t ngrp = (F + 15) / 16;
+    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+        const uint32_t f = grp * 16 + (lane & 15);
+        const bool valid = f < F;
+        uint32_t lam0 = 0;
+        if (valid) {
+            const uint32_t c = f & Cm;
+            const uint32_t f1 = f >> a.logC;
+            const uint32_t Q = fdiv(f1, a.divb[j]);
+            const uint32_t glo = f1 - Q * bj;
+            lam0 = ((Q * bj1 + glo) << a.logC) | c;
+        }
+        typename Op::V xb[NB];
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            float x[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                x[v] = valid ? lds[lds_phys(lam0 + (16 * h + 4 * q + v) * step, a.pad_shift)] : 0.f;
+            xb[h] = Op::pack(x);
+        }
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) {
+                acc = Op::mma(wf.hi[bi][bk], xb[bk], acc);
+                acc = Op::mma(wf.lo[bi][bk], xb[bk], acc);
+            }
+            if (valid) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lds[lds_phys(lam0 + (16 * bi + 4 * q + v) * step, a.pad_shift)] = acc[v];
+            }
+        }
+    }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* lds = reinterpret_cast<float*>(smem_raw);
+    WFrag<T, B> wf;
+    load_w_frag<T, B>(wf, a);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, float>(lds, a, static_cast<const T*>(a.in), t, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            mfma_stage<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        tile_store<T, float>(lds, a, static_cast<T*>(a.out), t, rows);
+        __syncthreads();
+    }
+}
+
+}  // namespace gtt

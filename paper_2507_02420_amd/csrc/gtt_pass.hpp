@@ -141,9 +141,9 @@ __device__ __forceinline__ int64_t row_offset(const PassArgs& a, int64_t hb, int
 }
 
 template <typename T, typename C>
-__device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, int64_t t, uint32_t rows) {
+__device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
+                                          uint32_t rows) {
     constexpr int V = Vec16<T>::V;
-    const T* __restrict__ in = static_cast<const T*>(a.in);
     const uint32_t tileE = rows << a.logC;
     if (a.mode == kContigVec || a.mode == kContigScalar) {
         const int64_t base = t * (int64_t)tileE;
@@ -190,9 +190,9 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, int64_t t, 
 }
 
 template <typename T, typename C>
-__device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, int64_t t, uint32_t rows) {
+__device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* __restrict__ out, int64_t t,
+                                           uint32_t rows) {
     constexpr int V = Vec16<T>::V;
-    T* __restrict__ out = static_cast<T*>(a.out);
     const uint32_t tileE = rows << a.logC;
     if (a.mode == kContigVec || a.mode == kContigScalar) {
         const int64_t base = t * (int64_t)tileE;
@@ -270,10 +270,10 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     load_w<C, B>(w, a);
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(lds, a, t, rows);
+        tile_load<T, C>(lds, a, static_cast<const T*>(a.in), t, rows);
         __syncthreads();
         run_stages<C, B, RD>(lds, a, rows, w);
-        tile_store<T, C>(lds, a, t, rows);
+        tile_store<T, C>(lds, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
 }
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) 
     }
     const uint32_t Cm = (1u << a.logC) - 1u;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(buf0, a, t, rows);
+        tile_load<T, C>(buf0, a, static_cast<const T*>(a.in), t, rows);
         __syncthreads();
         C* src = buf0;
         C* dst = buf1;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) 
             C* tmp = src; src = dst; dst = tmp;
             woff += (int)(bj * bj);
         }
-        tile_store<T, C>(src, a, t, rows);
+        tile_store<T, C>(src, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
 }

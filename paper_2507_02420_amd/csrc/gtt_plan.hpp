@@ -23,9 +23,10 @@ struct Group {
     int64_t tileE = 0;
     int mode = 0;
     int pad_shift = 31;
-    bool generic = false;
+    int kind = 0;       // kKindValu / kKindGeneric / kKindMfma
     int wtotal = 0;
     size_t lds_bytes = 0;
+    int64_t elems = 0;  // elements covered by one launch of this group
 };
 
 enum class PlanKind { Uniform, Ragged, Mixed };
@@ -36,9 +37,22 @@ struct Instance {
     int64_t off = 0;   // element offset in the data buffers
     int w = 0;         // W table index
     std::vector<Group> groups;
+    std::vector<Group> bwd_groups;
 };
 
 struct RaggedState;  // device work list (persistent launch)
+
+// Optional per-launch HIP-event timing (instrumentation; see gtt_plan_timing)
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t start, stop;
+    double bytes;  // algorithmic bytes moved by this launch
+};
+struct Timing {
+    bool enabled = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> pool;
+};
 
 }  // namespace gtt
 
@@ -55,11 +69,13 @@ struct gtt_plan_s {
     std::vector<int> rad;     // radix per digit, least significant first
     std::vector<int64_t> wofs;// W offset per digit (elements)
     std::vector<gtt::Group> groups;
+    std::vector<gtt::Group> bwd_groups;  // backward tiles (same digit groups)
     // ragged
     std::vector<gtt::Instance> inst;
     std::vector<int> w_b;         // radix of W table entry
     std::vector<int64_t> w_off;   // element offset of W table entry
     gtt::RaggedState* rs = nullptr;
+    gtt::Timing timing;
 };
 
 namespace gtt {
@@ -69,7 +85,9 @@ uint32_t host_fdiv(uint32_t n, const FastDiv& f);
 size_t storage_size(gtt_dtype d);
 size_t compute_size(gtt_dtype d);
 gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags, bool uniform,
-                       std::vector<Group>* groups);
+                       std::vector<Group>* groups, std::vector<Group>* bwd_groups, bool ragged = false);
+size_t bwd_lds_bytes(const Group& g, size_t csize, int b);
+size_t bwd_partials_elems(const std::vector<Group>& bg, int b);
 
 gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int32_t* n, const int64_t* x_off,
                        const int32_t* w_idx);
@@ -77,7 +95,15 @@ void destroy_ragged(gtt_plan_s* p);
 gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out, bool adjoint, char* saved,
                         hipStream_t s);
 void workspace_sizes(const gtt_plan_s* p, size_t* fwd, size_t* bwd, size_t* saved);
+size_t bwd_partial_bytes(const gtt_plan_s* p);
 std::string describe_plan(const gtt_plan_s* p);
+// bracket a launch with events when timing is enabled (no-ops otherwise)
+void timing_begin(gtt_plan_s* p, hipStream_t s);
+void timing_end(gtt_plan_s* p, hipStream_t s, const std::string& name, double bytes);
+void timing_release(gtt_plan_s* p);
+std::string timing_read(gtt_plan_s* p);
+gtt_status launch_group_inst(gtt_plan_s* tp, gtt_dtype dt, const Group& g, int b, int64_t N, const void* W,
+                             bool adjoint, const void* in, void* out, hipStream_t s);
 gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void* saved, const void* gy, void* gx,
                          void* gW, void* ws, size_t ws_bytes, hipStream_t s);
 gtt_status filter_impl(gtt_plan_s* p, const void* W, const void* x, int64_t cutoff, void* low, void* high,

@@ -3,18 +3,115 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <cstdio>
 #include <map>
 #include <string>
 
 #include "gtt_launch.hpp"
 #include "gtt_plan.hpp"
+#include "gtt_ragged.hpp"
 
 namespace gtt {
 
+void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, const std::vector<int64_t>& wofs,
+                    int64_t N);
+
+// Device work list of a ragged plan (built on the host at plan time, uploaded
+// on the first call that needs it).
 struct RaggedState {
-    int dummy = 0;
+    std::vector<RaggedDesc> desc;
+    std::vector<RaggedItem> items;
+    std::vector<int64_t> phase_start;
+    size_t lds_max = 0;
+    bool uploaded = false;
+    RaggedDesc* d_desc = nullptr;
+    RaggedItem* d_items = nullptr;
+    unsigned* d_bar = nullptr;
+    int grid_persistent = 0;
+    int cus = 0;
 };
+
+static void build_worklist(gtt_plan_s* p) {
+    RaggedState* rs = new RaggedState();
+    p->rs = rs;
+    int maxR = 0;
+    for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
+    const int64_t E = p->total_elems;
+    struct Tmp {
+        int phase;
+        int64_t cost;
+        RaggedItem it;
+    };
+    std::vector<Tmp> tmp;
+    for (const Instance& t : p->inst) {
+        const int R = (int)t.groups.size();
+        std::vector<int> rad(t.n, t.b);
+        std::vector<int64_t> wofs(t.n, 0);
+        for (int g = 0; g < R; ++g) {
+            const Group& G = t.groups[g];
+            RaggedDesc d;
+            std::memset(&d, 0, sizeof d);
+            fill_pass_args(&d.a, G, rad, wofs, t.N);
+            d.b = t.b;
+            d.kind = G.kind;
+            d.w_off = p->w_off[t.w];
+            d.in_sel = (g == 0) ? 0 : 2;
+            d.in_off = t.off;
+            d.in_off_saved = (int64_t)(g - 1) * E + t.off;
+            d.out_sel = (g == R - 1) ? 1 : 2;
+            d.out_off = t.off;
+            d.mid_off_saved = (int64_t)g * E + t.off;
+            const int di = (int)rs->desc.size();
+            rs->desc.push_back(d);
+            const size_t extra = 64 * p->csize;
+            rs->lds_max = std::max(rs->lds_max, G.lds_bytes + extra);
+            // cost estimate of one tile: elements x digits x radix work
+            const int64_t work = (G.kind == kKindMfma) ? 8 : t.b;
+            const int64_t cost = G.tileE * G.k * work;
+            for (int64_t i = 0; i < G.ntiles; ++i) tmp.push_back(Tmp{g, cost, RaggedItem{di, 0, i}});
+        }
+    }
+    // phase-major; within a phase the costliest tiles first, so that the
+    // round-robin assignment ends with the cheap ones (longest-processing-time
+    // order)
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) {
+        if (a.phase != b.phase) return a.phase < b.phase;
+        return a.cost > b.cost;
+    });
+    rs->phase_start.assign(maxR + 1, 0);
+    for (const Tmp& t : tmp) rs->phase_start[t.phase + 1]++;
+    for (int ph = 0; ph < maxR; ++ph) rs->phase_start[ph + 1] += rs->phase_start[ph];
+    for (const Tmp& t : tmp) rs->items.push_back(t.it);
+}
+
+static gtt_status upload_worklist(gtt_plan_s* p) {
+    RaggedState* rs = p->rs;
+    if (rs->uploaded) return GTT_OK;
+    const DT dt = static_cast<DT>((int)p->dtype);
+    if (hipMalloc(&rs->d_desc, rs->desc.size() * sizeof(RaggedDesc)) != hipSuccess) return GTT_ERR_HIP;
+    if (hipMalloc(&rs->d_items, std::max<size_t>(1, rs->items.size()) * sizeof(RaggedItem)) != hipSuccess)
+        return GTT_ERR_HIP;
+    if (hipMalloc(&rs->d_bar, 4 * sizeof(unsigned)) != hipSuccess) return GTT_ERR_HIP;
+    if (hipMemcpy(rs->d_desc, rs->desc.data(), rs->desc.size() * sizeof(RaggedDesc), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return GTT_ERR_HIP;
+    if (!rs->items.empty() &&
+        hipMemcpy(rs->d_items, rs->items.data(), rs->items.size() * sizeof(RaggedItem), hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return GTT_ERR_HIP;
+    if (hipMemset(rs->d_bar, 0, 4 * sizeof(unsigned)) != hipSuccess) return GTT_ERR_HIP;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GTT_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GTT_ERR_HIP;
+    rs->cus = prop.multiProcessorCount;
+    int per_cu = 0;
+    if (ragged_occupancy(dt, rs->lds_max, &per_cu) != hipSuccess || per_cu < 1) return GTT_ERR_HIP;
+    rs->grid_persistent = per_cu * rs->cus;
+    rs->uploaded = true;
+    return GTT_OK;
+}
 
 gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int32_t* n, const int64_t* x_off,
                        const int32_t* w_idx) {
@@ -74,24 +171,82 @@ gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int
         end = std::max(end, in.off + N);
         in.w = widx[t];
         std::vector<int> rad(n[t], b[t]);
-        gtt_status st = plan_groups(rad, 1, p->dtype, p->flags, true, &in.groups);
+        gtt_status st = plan_groups(rad, 1, p->dtype, p->flags, true, &in.groups, &in.bwd_groups, true);
         if (st != GTT_OK) return st;
     }
     p->total_elems = end;
+    int maxR = 0;
+    for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
+    if (maxR > kMaxPhases) return GTT_ERR_UNSUPPORTED;
+    build_worklist(p);
     return GTT_OK;
 }
 
 void destroy_ragged(gtt_plan_s* p) {
+    timing_release(p);
+    if (p->rs) {
+        if (p->rs->d_desc) hipFree(p->rs->d_desc);
+        if (p->rs->d_items) hipFree(p->rs->d_items);
+        if (p->rs->d_bar) hipFree(p->rs->d_bar);
+    }
     delete p->rs;
     p->rs = nullptr;
 }
 
-gtt_status launch_group_inst(gtt_dtype dt, const Group& g, int b, int64_t N, const void* W, bool adjoint,
-                             const void* in, void* out, hipStream_t s);
 
-// Per-instance launches (one launch per digit group per instance).
+static gtt_status ragged_per_instance(gtt_plan_s* p, const void* W, const void* in, void* out, bool adjoint,
+                                      char* saved, hipStream_t s);
+
+// One persistent launch for all digit groups (GTT_FLAG_PERSISTENT), or one
+// launch per phase; GTT_FLAG_PER_INSTANCE selects one launch per digit group
+// per instance (the plain path).
 gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out, bool adjoint, char* saved,
                         hipStream_t s) {
+    if (p->flags & GTT_FLAG_PER_INSTANCE) return ragged_per_instance(p, W, in, out, adjoint, saved, s);
+    gtt_status st = upload_worklist(p);
+    if (st != GTT_OK) return st;
+    RaggedState* rs = p->rs;
+    const DT dt = static_cast<DT>((int)p->dtype);
+    RaggedArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.desc = rs->d_desc;
+    a.items = rs->d_items;
+    a.nphases = (int)rs->phase_start.size() - 1;
+    for (int i = 0; i <= a.nphases; ++i) a.phase_start[i] = rs->phase_start[i];
+    a.adjoint = adjoint ? 1 : 0;
+    a.x = in;
+    a.y = out;
+    a.saved = adjoint ? nullptr : saved;
+    a.W = W;
+    a.bar = rs->d_bar;
+    static const char* dn[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32"};
+    if (p->flags & GTT_FLAG_PERSISTENT) {
+        int64_t most = 0;
+        for (int i = 0; i < a.nphases; ++i) most = std::max(most, rs->phase_start[i + 1] - rs->phase_start[i]);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rs->grid_persistent, most));
+        a.persistent = 1;
+        timing_begin(p, s);
+        if (launch_ragged(dt, a, grid, rs->lds_max, s) != hipSuccess) return GTT_ERR_HIP;
+        timing_end(p, s, std::string("ragged persistent ") + dn[(int)p->dtype],
+                   2.0 * (double)p->total_elems * (double)p->esize * (double)a.nphases);
+        return GTT_OK;
+    }
+    for (int ph = 0; ph < a.nphases; ++ph) {
+        const int64_t cnt = rs->phase_start[ph + 1] - rs->phase_start[ph];
+        if (cnt == 0) continue;
+        a.persistent = 0;
+        a.phase = ph;
+        const unsigned grid = (unsigned)std::min<int64_t>(cnt, (int64_t)rs->grid_persistent * 4);
+        timing_begin(p, s);
+        if (launch_ragged(dt, a, grid, rs->lds_max, s) != hipSuccess) return GTT_ERR_HIP;
+        timing_end(p, s, std::string("ragged phase ") + std::to_string(ph) + " " + dn[(int)p->dtype], 0.0);
+    }
+    return GTT_OK;
+}
+
+// Per-instance launches (one launch per digit group per instance).
+static gtt_status ragged_per_instance(gtt_plan_s* p, const void* W, const void* in, void* out, bool adjoint,
+                                      char* saved, hipStream_t s) {
     const size_t es = p->esize, cs = p->csize;
     for (const Instance& t : p->inst) {
         const char* src = static_cast<const char*>(in) + t.off * es;
@@ -107,7 +262,7 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
             void* nxt = dst;
             if (saved && i + 1 < t.groups.size())
                 nxt = saved + ((int64_t)i * p->total_elems + t.off) * es;
-            gtt_status st = launch_group_inst(p->dtype, t.groups[i], t.b, t.N, w, adjoint, cur, nxt, s);
+            gtt_status st = launch_group_inst(p, p->dtype, t.groups[i], t.b, t.N, w, adjoint, cur, nxt, s);
             if (st != GTT_OK) return st;
             cur = nxt;
         }
@@ -122,6 +277,16 @@ static int max_groups(const gtt_plan_s* p) {
     return r;
 }
 
+size_t bwd_partial_bytes(const gtt_plan_s* p) {
+    size_t partial = 0;
+    if (p->kind == PlanKind::Ragged) {
+        for (const Instance& t : p->inst) partial += bwd_partials_elems(t.bwd_groups, t.b) * p->csize;
+    } else if (p->kind == PlanKind::Uniform) {
+        partial += bwd_partials_elems(p->bwd_groups, p->b) * p->csize;
+    }
+    return (partial + 255) & ~(size_t)255;
+}
+
 void workspace_sizes(const gtt_plan_s* p, size_t* fwd, size_t* bwd, size_t* saved) {
     const int R = max_groups(p);
     const size_t E = (size_t)p->total_elems;
@@ -129,18 +294,81 @@ void workspace_sizes(const gtt_plan_s* p, size_t* fwd, size_t* bwd, size_t* save
     *saved = (R > 1) ? (size_t)(R - 1) * E * p->esize : 0;
     // backward: per-tile partial sums of the weight gradient (compute dtype,
     // b*b per tile and group) plus room to recompute the saved activations
-    size_t partial = 0;
-    auto add_groups = [&](const std::vector<Group>& gs, int b) {
-        for (const Group& g : gs) partial += (size_t)g.ntiles * b * b * p->csize;
-    };
-    if (p->kind == PlanKind::Ragged) {
-        for (const Instance& t : p->inst) add_groups(t.groups, t.b);
-        partial += 256;
-    } else {
-        add_groups(p->groups, p->b);
+    const size_t partial = bwd_partial_bytes(p);
+    // + a cotangent buffer between digit groups (used when gx is NULL or
+    // aliases gy)
+    const size_t cbuf = (R > 1 || p->kind == PlanKind::Ragged) ? E * p->esize : 0;
+    *bwd = partial + *saved + cbuf;
+}
+
+static hipEvent_t pool_get(Timing& t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
     }
-    partial = (partial + 255) & ~(size_t)255;
-    *bwd = partial + *saved;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static thread_local hipEvent_t t_open = nullptr;
+
+void timing_begin(gtt_plan_s* p, hipStream_t s) {
+    if (!p || !p->timing.enabled) return;
+    t_open = pool_get(p->timing);
+    if (t_open) hipEventRecord(t_open, s);
+}
+
+void timing_end(gtt_plan_s* p, hipStream_t s, const std::string& name, double bytes) {
+    if (!p || !p->timing.enabled || !t_open) return;
+    hipEvent_t e = pool_get(p->timing);
+    if (!e) return;
+    hipEventRecord(e, s);
+    p->timing.pending.push_back(TimedLaunch{name, t_open, e, bytes});
+    t_open = nullptr;
+}
+
+void timing_release(gtt_plan_s* p) {
+    for (auto& tl : p->timing.pending) {
+        hipEventDestroy(tl.start);
+        hipEventDestroy(tl.stop);
+    }
+    for (auto e : p->timing.pool) hipEventDestroy(e);
+    p->timing.pending.clear();
+    p->timing.pool.clear();
+}
+
+std::string timing_read(gtt_plan_s* p) {
+    struct Agg {
+        int n = 0;
+        double ms = 0, bytes = 0;
+    };
+    std::map<std::string, Agg> agg;
+    for (auto& tl : p->timing.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(tl.stop) == hipSuccess && hipEventElapsedTime(&ms, tl.start, tl.stop) == hipSuccess) {
+            Agg& a = agg[tl.name];
+            a.n += 1;
+            a.ms += ms;
+            a.bytes += tl.bytes;
+        }
+        p->timing.pool.push_back(tl.start);
+        p->timing.pool.push_back(tl.stop);
+    }
+    p->timing.pending.clear();
+    std::string s = "{";
+    bool first = true;
+    for (auto& kv : agg) {
+        char b[512];
+        std::snprintf(b, sizeof b, "%s\"%s\":{\"launches\":%d,\"total_ms\":%.6f,\"avg_ms\":%.6f,\"bytes_per_launch\":%.1f}",
+                      first ? "" : ",", kv.first.c_str(), kv.second.n, kv.second.ms, kv.second.ms / kv.second.n,
+                      kv.second.bytes / kv.second.n);
+        s += b;
+        first = false;
+    }
+    s += "}";
+    return s;
 }
 
 std::string describe_plan(const gtt_plan_s* p) {
@@ -148,9 +376,10 @@ std::string describe_plan(const gtt_plan_s* p) {
         char b[320];
         std::snprintf(b, sizeof b,
                       "{\"s0\":%d,\"k\":%d,\"S\":%lld,\"G\":%lld,\"C\":%d,\"P\":%d,\"L\":%lld,\"tiles\":%lld,"
-                      "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"generic\":%s,\"lds_bytes\":%zu}",
+                      "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"kind\":\"%s\",\"lds_bytes\":%zu}",
                       g.s0, g.k, (long long)g.S, (long long)g.G, g.C, g.P, (long long)g.L, (long long)g.ntiles,
-                      (long long)g.tileE, g.mode, g.pad_shift, g.generic ? "true" : "false", g.lds_bytes);
+                      (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : "mfma",
+                      g.lds_bytes);
         return std::string(b);
     };
     std::string s = "{";

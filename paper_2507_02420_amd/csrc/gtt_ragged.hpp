@@ -1,0 +1,235 @@
+// Ragged batches in one launch: instances of different radix and length (each
+// its own GTT, Def. 2.4) packed in one buffer.  The host lays out a device
+// work list of (descriptor, tile) items, one descriptor per (instance, digit
+// group); phase p holds the tiles of digit group p of every instance.  A
+// work-group takes items of the current phase round-robin and dispatches on
+// the radix to the VALU, matrix-core or runtime-radix tile code.
+//
+// Persistent mode runs every phase in ONE launch and separates the phases by
+// a grid barrier (the next digit group of an instance needs all tiles of the
+// previous one).  The barrier counts arrivals with a device-scope atomic; the
+// last work-group to arrive resets the count and advances a generation word
+// the others wait on, so the state returns to zero after every barrier and the
+// launch can be replayed from a captured graph.  The grid never exceeds the
+// number of co-resident work-groups, and every wait is bounded: after the spin
+// limit a work-group raises the error word and leaves, so no wave can hang.
+#pragma once
+
+#include "gtt_args.hpp"
+#include "gtt_mfma.hpp"
+#include "gtt_pass.hpp"
+#include "gtt_types.hpp"
+
+namespace gtt {
+
+struct RaggedDesc {
+    PassArgs a;          // tile geometry of this (instance, group)
+    int64_t in_off;      // element offset of the group's input
+    int64_t out_off;     // element offset of the group's output
+    int64_t mid_off_saved;  // offset of this group's output inside `saved`
+    int64_t w_off;       // element offset of the instance's W in the W table
+    int32_t in_sel;      // 0: x, 1: y, 2: intermediate (saved if given, else y)
+    int32_t out_sel;     // 1: y, 2: intermediate
+    int32_t in_mid_saved;// 1 when in_sel == 2 (offset in saved is in_off_saved)
+    int32_t b;
+    int32_t kind;        // kKindValu / kKindGeneric / kKindMfma
+    int32_t pad0;
+    int64_t in_off_saved;
+};
+
+struct RaggedItem {
+    int32_t d;           // descriptor index
+    int32_t pad0;
+    int64_t tile;        // tile index within the descriptor's group
+};
+
+constexpr int kMaxPhases = 8;
+
+struct RaggedArgs {
+    const RaggedDesc* desc;
+    const RaggedItem* items;
+    int64_t phase_start[kMaxPhases + 1];
+    int32_t nphases;
+    int32_t persistent;  // 1: all phases in this launch, grid barriers between
+    int32_t phase;       // phase of a per-phase launch
+    int32_t adjoint;
+    const void* x;
+    void* y;
+    void* saved;
+    const void* W;
+    unsigned* bar;       // [0] arrivals, [1] generation, [2] error flag
+};
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_thread_fence(__ATOMIC_RELEASE);  // this block's tile stores
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // bounded wait: ~2^24 polls with s_sleep is several seconds
+            for (uint32_t spin = 0;; ++spin) {
+                if (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) break;
+                if (spin > (1u << 24)) {
+                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    }
+    __syncthreads();
+}
+
+template <typename C, int B>
+__device__ __forceinline__ void load_w_ptr(C (&w)[B * B], const C* __restrict__ Wg, int adjoint, C* wl) {
+    if constexpr (B * B * sizeof(C) <= 128) {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int q = 0; q < B; ++q) w[r * B + q] = adjoint ? cconj(Wg[q * B + r]) : Wg[r * B + q];
+    } else {
+        for (int e = threadIdx.x; e < B * B; e += kThreads) {
+            const int r = e / B, q = e % B;
+            wl[e] = adjoint ? cconj(Wg[q * B + r]) : Wg[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < B * B; ++e) w[e] = wl[e];
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void ragged_tile_valu(unsigned char* smem, const PassArgs& a, const T* in, T* out,
+                                              const typename Tr<T>::C* W, int adjoint, int64_t t) {
+    using C = typename Tr<T>::C;
+    constexpr int RD = RegDigits<B>::v;
+    C* wl = reinterpret_cast<C*>(smem);
+    C* lds = wl + 64;  // first 64 elements: staging for W (radix <= 8)
+    C w[B * B];
+    load_w_ptr<C, B>(w, W, adjoint, wl);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    tile_load<T, C>(lds, a, in, t, rows);
+    __syncthreads();
+    run_stages<C, B, RD>(lds, a, rows, w);
+    tile_store<T, C>(lds, a, out, t, rows);
+    __syncthreads();
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void ragged_tile_mfma(unsigned char* smem, const PassArgs& a, const T* in, T* out,
+                                              const float* W, int adjoint, int64_t t) {
+    float* lds = reinterpret_cast<float*>(smem) + 64;
+    PassArgs aw;  // only W / adjoint are read by the fragment loader
+    aw.W = W;
+    aw.adjoint = adjoint;
+    WFrag<T, B> wf;
+    load_w_frag<T, B>(wf, aw);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    tile_load<T, float>(lds, a, in, t, rows);
+    __syncthreads();
+    for (int j = 0; j < a.k; ++j) {
+        mfma_stage<T, B>(lds, a, j, rows, wf);
+        __syncthreads();
+    }
+    tile_store<T, float>(lds, a, out, t, rows);
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void ragged_tile_generic(unsigned char* smem, const PassArgs& a, const T* in, T* out,
+                                                 const typename Tr<T>::C* W, int adjoint, int64_t t) {
+    using C = typename Tr<T>::C;
+    C* Wl = reinterpret_cast<C*>(smem);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t wpad = ((uint32_t)a.wtotal + 15u) & ~15u;
+    C* buf0 = Wl + wpad;
+    C* buf1 = buf0 + tileE;
+    for (int j = 0, done = 0; j < a.k; ++j) {
+        const int bj = a.rad[j];
+        for (int e = threadIdx.x; e < bj * bj; e += kThreads) {
+            const int r = e / bj, q = e - r * bj;
+            Wl[done + e] = adjoint ? cconj(W[a.wofs[j] + q * bj + r]) : W[a.wofs[j] + e];
+        }
+        done += bj * bj;
+    }
+    tile_load<T, C>(buf0, a, in, t, rows);
+    __syncthreads();
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    C* src = buf0;
+    C* dst = buf1;
+    int woff = 0;
+    for (int j = 0; j < a.k; ++j) {
+        const uint32_t bj = (uint32_t)a.rad[j];
+        const uint32_t pv = (uint32_t)a.bpow[j];
+        const C* Wj = Wl + woff;
+        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+            const uint32_t c = i & Cm;
+            const uint32_t r = i >> a.logC;
+            const uint32_t hi = fdiv(r, a.divb[j]);
+            const uint32_t d = hi - fdiv(hi, a.divrad[j]) * bj;
+            const uint32_t r0 = r - d * pv;
+            C acc = czero<C>();
+            for (uint32_t q = 0; q < bj; ++q) acc = cmac(acc, Wj[d * bj + q], src[((r0 + q * pv) << a.logC) | c]);
+            dst[i] = acc;
+        }
+        __syncthreads();
+        C* tmp = src;
+        src = dst;
+        dst = tmp;
+        woff += (int)(bj * bj);
+    }
+    tile_store<T, C>(src, a, out, t, rows);
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gtt_ragged_kernel(RaggedArgs r) {
+    using C = typename Tr<T>::C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int p0 = r.persistent ? 0 : r.phase;
+    const int p1 = r.persistent ? r.nphases : r.phase + 1;
+    for (int p = p0; p < p1; ++p) {
+        for (int64_t i = r.phase_start[p] + blockIdx.x; i < r.phase_start[p + 1]; i += gridDim.x) {
+            const RaggedItem it = r.items[i];
+            const RaggedDesc& d = r.desc[it.d];
+            const T* in;
+            T* out;
+            if (d.in_sel == 0) in = static_cast<const T*>(r.x) + d.in_off;
+            else if (d.in_sel == 1 || !r.saved) in = static_cast<const T*>(r.y) + d.in_off;
+            else in = static_cast<const T*>(r.saved) + d.in_off_saved;
+            if (d.out_sel == 1 || !r.saved) out = static_cast<T*>(r.y) + d.out_off;
+            else out = static_cast<T*>(r.saved) + d.mid_off_saved;
+            const C* W = static_cast<const C*>(r.W) + d.w_off;
+            if (d.kind == kKindValu) {
+                switch (d.b) {
+                    case 2: ragged_tile_valu<T, 2>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
+                    case 3: ragged_tile_valu<T, 3>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
+                    case 4: ragged_tile_valu<T, 4>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
+                    case 5: ragged_tile_valu<T, 5>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
+                    default: ragged_tile_generic<T>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
+                }
+            } else if (d.kind == kKindMfma) {
+                if constexpr (sizeof(T) == 2) {
+                    if (d.b == 16)
+                        ragged_tile_mfma<T, 16>(smem_raw, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint,
+                                                it.tile);
+                    else
+                        ragged_tile_mfma<T, 32>(smem_raw, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint,
+                                                it.tile);
+                }
+            } else {
+                ragged_tile_generic<T>(smem_raw, d.a, in, out, W, r.adjoint, it.tile);
+            }
+        }
+        if (r.persistent && p + 1 < p1) grid_barrier(r.bar, gridDim.x);
+    }
+}
+
+}  // namespace gtt

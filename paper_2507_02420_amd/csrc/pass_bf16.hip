@@ -1,5 +1,6 @@
 // Instantiations of the digit-group pass kernels for storage type bf16.
 #include "gtt_launch.hpp"
+#include "gtt_mfma.hpp"
 #include "gtt_pass.hpp"
 
 namespace gtt {
@@ -11,7 +12,7 @@ static hipError_t set_lds(K kernel, size_t lds) {
     return hipSuccess;
 }
 
-hipError_t launch_pass_bf16(int b, bool generic, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_pass_bf16(int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     using T = bf16;
     hipError_t e = hipSuccess;
 #define GTT_LAUNCH(KER)                                                       \
@@ -20,8 +21,15 @@ hipError_t launch_pass_bf16(int b, bool generic, const PassArgs& a, unsigned gri
         if (e != hipSuccess) return e;                                        \
         hipLaunchKernelGGL(KER, dim3(grid), dim3(kThreads), lds, s, a);       \
     } while (0)
-    if (generic) {
+    if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
+    } else if (kind == kKindMfma) {
+        if (b == 16)
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 16>));
+        else if (b == 32)
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 32>));
+        else
+            return hipErrorInvalidValue;
     } else {
         switch (b) {
             case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;

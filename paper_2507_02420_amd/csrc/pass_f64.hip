@@ -11,7 +11,7 @@ static hipError_t set_lds(K kernel, size_t lds) {
     return hipSuccess;
 }
 
-hipError_t launch_pass_f64(int b, bool generic, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_pass_f64(int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     using T = double;
     hipError_t e = hipSuccess;
 #define GTT_LAUNCH(KER)                                                       \
@@ -20,8 +20,10 @@ hipError_t launch_pass_f64(int b, bool generic, const PassArgs& a, unsigned grid
         if (e != hipSuccess) return e;                                        \
         hipLaunchKernelGGL(KER, dim3(grid), dim3(kThreads), lds, s, a);       \
     } while (0)
-    if (generic) {
+    if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
+    } else if (kind == kKindMfma) {
+        return hipErrorInvalidValue;
     } else {
         switch (b) {
             case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;

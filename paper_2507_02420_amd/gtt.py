@@ -27,6 +27,7 @@ F64, F32, C128, C64, BF16, F16, I32 = range(7)
 FLAG_FP32_INTERMEDIATE = 0x1
 FLAG_NO_TUNE = 0x2
 FLAG_PERSISTENT = 0x4
+FLAG_PER_INSTANCE = 0x8
 
 TORCH_TO_GTT = {torch.float64: F64, torch.float32: F32, torch.complex128: C128,
                 torch.complex64: C64, torch.bfloat16: BF16, torch.float16: F16, torch.int32: I32}
@@ -38,7 +39,8 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 # every symbol declared in include/gtt.h
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
            "gtt_backward", "gtt_filter", "gtt_plan_destroy", "gtt_status_string",
-           "gtt_plan_describe", "gtt_set_tuning", "gtt_selftest"]
+           "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_set_tuning",
+           "gtt_selftest"]
 
 
 class GTTError(RuntimeError):
@@ -72,6 +74,8 @@ def lib() -> ctypes.CDLL:
     L.gtt_status_string.argtypes = [ctypes.c_int]
     L.gtt_status_string.restype = ctypes.c_char_p
     L.gtt_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.gtt_plan_timing.argtypes = [vp, i32]
+    L.gtt_plan_timing_read.argtypes = [vp, ctypes.c_char_p, sz]
     L.gtt_set_tuning.argtypes = [i32, ctypes.c_int, i32, i32]
     L.gtt_selftest.argtypes = []
     for name in EXPORTS:
@@ -159,6 +163,15 @@ class Plan:
     def describe(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().gtt_plan_describe(self._h, buf, len(buf)), "gtt_plan_describe")
+        return json.loads(buf.value.decode())
+
+    def timing(self, enable: bool = True):
+        """Bracket every kernel launch of this plan with HIP events."""
+        _check(lib().gtt_plan_timing(self._h, 1 if enable else 0), "gtt_plan_timing")
+
+    def timing_read(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().gtt_plan_timing_read(self._h, buf, len(buf)), "gtt_plan_timing_read")
         return json.loads(buf.value.decode())
 
     # -- calls ---------------------------------------------------------------

@@ -148,3 +148,23 @@ def test_mixed_radix_matches_kron(dtype):
     ref = O.staged_mixed(Ws64, x64)
     assert rel_err(host64(y), ref) < TOL[dtype]
     assert rel_err(host64(xi), x64) < 3 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=str)
+@pytest.mark.parametrize("b,n,batch", [(16, 1, 5), (16, 2, 3), (16, 3, 2), (16, 5, 1), (32, 1, 7), (32, 2, 3),
+                                       (32, 3, 1), (32, 4, 1)])
+def test_mfma_radix_16_32(b, n, batch, dtype):
+    # matrix-core path: 16-bit operands, W split in two 16-bit parts, FP32
+    # accumulation; error against FP64 on the stored inputs
+    say(f"mfma b={b} n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=7000 + b + n)
+    plan = G.Plan(b, n, batch, dtype)
+    assert all(g["kind"] == "mfma" for g in plan.describe()["groups"])
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, y)
+    torch.cuda.synchronize()
+    ref = O.staged(W64, x64, n)
+    err = rel_err(host64(y), ref)
+    say(f"  rel err {err:.3e}")
+    assert err < 1e-2
+    assert rel_err(host64(xi), x64) < 2e-2
