@@ -19,10 +19,17 @@ hipError_t launch_bwd_c128(const BwdArgs& a, unsigned grid, size_t lds, hipStrea
     return hipGetLastError();
 }
 
+static constexpr int kReduceBlocks = 64;
+
 hipError_t launch_reduce_c128(const void* partials, int64_t nparts, int bb, void* out, hipStream_t s) {
     using C = typename Tr<cd>::C;
-    hipLaunchKernelGGL(gtt_reduce_kernel<C>, dim3(1), dim3(kThreads), 0, s, static_cast<const C*>(partials),
-                       nparts, bb, static_cast<C*>(out));
+    // partials has room for kReduceBlocks more vectors after the nparts ones
+    C* mid = const_cast<C*>(static_cast<const C*>(partials)) + (size_t)nparts * bb;
+    const int g1 = (int)(nparts < kReduceBlocks ? nparts : kReduceBlocks);
+    hipLaunchKernelGGL(gtt_reduce_kernel<C>, dim3(g1), dim3(kThreads), 0, s, static_cast<const C*>(partials),
+                       nparts, bb, mid);
+    hipLaunchKernelGGL(gtt_reduce_kernel<C>, dim3(1), dim3(kThreads), 0, s, mid, (int64_t)g1, bb,
+                       static_cast<C*>(out));
     return hipGetLastError();
 }
 

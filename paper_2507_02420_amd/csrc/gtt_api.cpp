@@ -226,6 +226,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     // (the one-launch ragged kernel carries the VALU code for radix <= 5 only)
     if (uniform && (b0 <= 5 || (b0 <= 8 && dt != GTT_C128 && !ragged))) kind = kKindValu;
     if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16)) kind = kKindMfma;
+    if (uniform && b0 == 8 && dt == GTT_C64 && !ragged) kind = kKindCMfma;
     const bool small_b = kind != kKindGeneric;
     int tb = 0, tr = 0;
     tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr);
@@ -332,7 +333,8 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     if (tp && tp->timing.enabled) {
         char nm[128];
         std::snprintf(nm, sizeof nm, "pass %s b=%d%s s0=%d k=%d%s", dt_name(dt), rad[g.s0],
-                      g.kind == kKindGeneric ? " generic" : g.kind == kKindMfma ? " mfma" : "",
+                      g.kind == kKindGeneric ? " generic" : g.kind == kKindMfma ? " mfma"
+                                                   : g.kind == kKindCMfma ? " cmfma" : "",
                       g.s0, g.k, adjoint ? " adjoint" : "");
         timing_end(tp, s, nm, 2.0 * (double)g.elems * (double)storage_size(dt));
     }

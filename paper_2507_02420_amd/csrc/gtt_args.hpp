@@ -59,4 +59,11 @@ struct PassArgs {
     int32_t wtotal;                // elements of W to stage in LDS
 };
 
+// backward of one group, complex64 radix 8 on the matrix cores
+struct CBwdArgs {
+    PassArgs p;          // tile geometry; p.in = a_in, p.out = c_in, p.W = W
+    const void* c_out;   // cotangent at the group's output
+    void* partials;      // [gridDim.x][64] complex float
+};
+
 }  // namespace gtt

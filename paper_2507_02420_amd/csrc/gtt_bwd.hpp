@@ -155,25 +155,38 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
     for (int e = threadIdx.x; e < bb; e += kThreads) part[e] = acc[e];
 }
 
-// gW[e] = sum over parts p of partials[p][e] (p ascending within each of
-// four interleaved chains, then the chains in order): one work-group.
+// Fixed-order sum of partial vectors of bb values: work-group w sums the
+// parts of its contiguous range [w*n/G, (w+1)*n/G) (interleaved chains inside
+// the range, then the chains in order) into out[w].  Two launches (G blocks,
+// then one block over the G results) give a deterministic total.
 template <typename C>
 __global__ __launch_bounds__(kThreads) void gtt_reduce_kernel(const C* __restrict__ partials, int64_t nparts,
                                                               int bb, C* __restrict__ out) {
     __shared__ C red[kThreads];
     const int t = threadIdx.x;
     const int chains = kThreads / bb;
+    const int64_t lo = (int64_t)blockIdx.x * nparts / gridDim.x;
+    const int64_t hi = (int64_t)(blockIdx.x + 1) * nparts / gridDim.x;
     C s = czero<C>();
     if (t < chains * bb) {
         const int e = t % bb, ch = t / bb;
-        for (int64_t p = ch; p < nparts; p += chains) s = cadd(s, partials[p * bb + e]);
+        int64_t p = lo + ch;
+        for (; p + 3 * chains < hi; p += 4 * chains) {
+            const C v0 = partials[p * bb + e];
+            const C v1 = partials[(p + chains) * bb + e];
+            const C v2 = partials[(p + 2 * chains) * bb + e];
+            const C v3 = partials[(p + 3 * chains) * bb + e];
+            s = cadd(cadd(s, v0), v1);
+            s = cadd(cadd(s, v2), v3);
+        }
+        for (; p < hi; p += chains) s = cadd(s, partials[p * bb + e]);
     }
     red[t] = s;
     __syncthreads();
     if (t < bb) {
         C tot = czero<C>();
         for (int ch = 0; ch < chains; ++ch) tot = cadd(tot, red[ch * bb + t]);
-        out[t] = tot;
+        out[(size_t)blockIdx.x * bb + t] = tot;
     }
 }
 

@@ -20,8 +20,9 @@ static const char* kDtName[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32
 
 // LDS bytes of the backward kernel for a tile geometry
 size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
-    const int maxb = b <= 8 ? 8 : 16;
     const int64_t tileP = g.tileE + (g.pad_shift < 31 ? (g.tileE >> g.pad_shift) : 0) + 1;
+    if (g.kind == kKindCMfma) return (size_t)(3 * tileP + 1) * csize + 4 * 256 * sizeof(double);
+    const int maxb = b <= 8 ? 8 : 16;
     return (size_t)(3 * maxb * maxb + kThreads + 3 * tileP) * csize;
 }
 
@@ -33,6 +34,9 @@ size_t bwd_partials_elems(const std::vector<Group>& bg, int b) {
     for (const Group& g : bg) e += (size_t)bwd_grid(g) * b * b;
     return e;
 }
+
+// partial vectors of the reduction's first stage (after the bwd partials)
+static constexpr size_t kReduceScratchVectors = 64;
 
 // backward of one instance set (uniform batch, or one ragged instance)
 static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>& fg, const std::vector<Group>& bg, int b,
@@ -58,10 +62,20 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
         ba.b = b;
         const unsigned grid = bwd_grid(G);
         timing_begin(tp, s);
-        if (launch_bwd(to_dt(dt), ba, grid, bwd_lds_bytes(G, cs, b), s) != hipSuccess) return GTT_ERR_HIP;
+        if (G.kind == kKindCMfma) {
+            CBwdArgs ca;
+            std::memset(&ca, 0, sizeof ca);
+            ca.p = ba.p;
+            ca.c_out = ba.c_out;
+            ca.partials = ba.partials;
+            if (launch_cbwd8(ca, grid, bwd_lds_bytes(G, cs, b), s) != hipSuccess) return GTT_ERR_HIP;
+        } else if (launch_bwd(to_dt(dt), ba, grid, bwd_lds_bytes(G, cs, b), s) != hipSuccess) {
+            return GTT_ERR_HIP;
+        }
         if (tp && tp->timing.enabled) {
             char nm[96];
-            std::snprintf(nm, sizeof nm, "bwd %s b=%d s0=%d k=%d", kDtName[(int)dt], b, G.s0, G.k);
+            std::snprintf(nm, sizeof nm, "bwd %s b=%d%s s0=%d k=%d", kDtName[(int)dt], b,
+                          G.kind == kKindCMfma ? " cmfma" : "", G.s0, G.k);
             timing_end(tp, s, nm, 3.0 * (double)G.elems * (double)es);
         }
         part += (size_t)grid * b * b * cs;
@@ -144,9 +158,12 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
     char* sv_tmp = extra;
     char* cb_base = cb_in_gx ? static_cast<char*>(gx) : extra + ((maxR > 1 && !saved) ? (size_t)(maxR - 1) * E * es : 0);
     const int nw = (int)p->w_b.size();
-    std::vector<size_t> wstart(nw + 1, 0);
-    for (const Instance& t : p->inst) wstart[t.w + 1] += bwd_partials_elems(t.bwd_groups, t.b) * cs;
-    for (int w = 0; w < nw; ++w) wstart[w + 1] += wstart[w];
+    // region of W entry w: its instances' partials, then the reduction's
+    // first-stage vectors
+    std::vector<size_t> wpart(nw, 0), wstart(nw + 1, 0);
+    for (const Instance& t : p->inst) wpart[t.w] += bwd_partials_elems(t.bwd_groups, t.b) * cs;
+    for (int w = 0; w < nw; ++w)
+        wstart[w + 1] = wstart[w] + wpart[w] + kReduceScratchVectors * (size_t)p->w_b[w] * p->w_b[w] * cs;
     std::vector<size_t> wcur(wstart.begin(), wstart.end() - 1);
     for (const Instance& t : p->inst) {
         const char* xin = static_cast<const char*>(x) + t.off * es;
@@ -184,7 +201,7 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
         for (int w = 0; w < nw; ++w) {
             const int bb = p->w_b[w] * p->w_b[w];
             char* out = static_cast<char*>(gW) + p->w_off[w] * cs;
-            const int64_t nparts = (int64_t)((wstart[w + 1] - wstart[w]) / cs / bb);
+            const int64_t nparts = (int64_t)(wpart[w] / cs / bb);
             if (nparts == 0) {
                 if (hipMemsetAsync(out, 0, (size_t)bb * cs, s) != hipSuccess) return GTT_ERR_HIP;
             } else if (launch_reduce(dt, partials + wstart[w], nparts, bb, out, s) != hipSuccess) {

@@ -1,0 +1,206 @@
+// Complex radix-8 digit passes and weight gradient on the FP32 matrix cores.
+//
+// A complex 8 x 8 product y = W x is the real 16 x 16 product
+//     [Re y; Im y] = [[Re W, -Im W], [Im W, Re W]] [Re x; Im x],
+// which is one 16x16 MFMA block.  With v_mfma_f32_16x16x4_f32, K is split in
+// four slices of four; rows and columns of the real matrix are ordered so that
+// every lane sees complex values in the interleaved (re, im) memory layout:
+//   B operand, K slice kk: lane (q = l/16, fibre i = l%16) holds component
+//     kk & 1 of element 2q + (kk >> 1) of fibre i, i.e. over the four slices
+//     the lane supplies x[2q].re, x[2q].im, x[2q+1].re, x[2q+1].im;
+//   result: lane (q, i) holds y[2q].re, y[2q].im, y[2q+1].re, y[2q+1].im.
+// So one wave reads two complex elements per lane from LDS, runs four MFMAs
+// and writes two complex results back in place (16 fibres per wave step).
+//
+// The weight gradient sum_f c_f a_f^H over the fibres of a digit is the real
+// 16 x 16 product M = [c]_{16 x F} [a]^T_{F x 16} accumulated over fibres
+// (K = fibres, four per MFMA), with row index m = 2e + comp for element e:
+//   Re gW[r][q] = M[2r][2q] + M[2r+1][2q+1],  Im gW[r][q] = M[2r+1][2q] - M[2r][2q+1].
+// Every digit of every group adds into the same gradient, so one accumulator
+// per wave collects all of them: the FP32 MFMA chain covers one digit of one
+// tile (at most a few hundred terms), and is then added into an FP64
+// accumulator, which bounds the rounding error of long sums; the work-group
+// total is rounded to FP32 once.
+#pragma once
+
+#include "gtt_args.hpp"
+#include "gtt_pass.hpp"
+#include "gtt_types.hpp"
+
+namespace gtt {
+
+typedef float f32x4_c __attribute__((ext_vector_type(4)));
+
+struct CFrag8 {
+    float a[4];  // A operand of the four K slices
+};
+
+// real 16 x 16 block of W (or W^H) at (m, k) in the interleaved ordering
+__device__ __forceinline__ float creal_block(const cf* __restrict__ W, int adjoint, int m, int k) {
+    const int e_out = 2 * (m >> 2) + ((m & 3) >> 1), c_out = m & 1;
+    const int e_in = 2 * (k & 3) + (k >> 3), c_in = (k >> 2) & 1;
+    cf w = adjoint ? cconj(W[e_in * 8 + e_out]) : W[e_out * 8 + e_in];
+    if (c_out == 0) return c_in == 0 ? w.re : -w.im;
+    return c_in == 0 ? w.im : w.re;
+}
+
+__device__ __forceinline__ void load_cfrag8(CFrag8& f, const cf* __restrict__ W, int adjoint) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) f.a[kk] = creal_block(W, adjoint, lane & 15, 4 * kk + (lane >> 4));
+}
+
+__device__ __forceinline__ uint32_t fibre_base(const PassArgs& a, int j, uint32_t f) {
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t c = f & Cm;
+    const uint32_t f1 = f >> a.logC;
+    const uint32_t Q = fdiv(f1, a.divb[j]);
+    const uint32_t glo = f1 - Q * bj;
+    return ((Q * (uint32_t)a.bpow[j + 1] + glo) << a.logC) | c;
+}
+
+// W (fragments f) along digit j of every fibre of the complex tile, in place.
+__device__ __forceinline__ void cmfma_stage8(cf* lds, const PassArgs& a, int j, uint32_t rows, const CFrag8& fr) {
+    const uint32_t F = (rows << a.logC) >> 3;
+    const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int q = lane >> 4;
+    const uint32_t ngrp = (F + 15) >> 4;
+    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+        const uint32_t f = (grp << 4) + (lane & 15);
+        const bool valid = f < F;
+        uint32_t p0 = 0, p1 = 0;
+        cf x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
+        if (valid) {
+            const uint32_t lam0 = fibre_base(a, j, f);
+            p0 = lds_phys(lam0 + (2 * q) * step, a.pad_shift);
+            p1 = lds_phys(lam0 + (2 * q + 1) * step, a.pad_shift);
+            x0 = lds[p0];
+            x1 = lds[p1];
+        }
+        f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0.re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], x0.im, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1.re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1.im, acc, 0, 0, 0);
+        if (valid) {
+            lds[p0] = cf{acc[0], acc[1]};
+            lds[p1] = cf{acc[2], acc[3]};
+        }
+    }
+}
+
+// M += sum over the fibres of digit j of [c] [a]^T (see the header comment).
+__device__ __forceinline__ void cmfma_gw8(const cf* ct, const cf* at, const PassArgs& a, int j, uint32_t rows,
+                                          f32x4_c& M) {
+    const uint32_t F = (rows << a.logC) >> 3;
+    const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const int e = m >> 1;
+    const bool im = (m & 1) != 0;
+    const uint32_t ngrp = (F + 3) >> 2;
+    const float* ctf = reinterpret_cast<const float*>(ct);
+    const float* atf = reinterpret_cast<const float*>(at);
+    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+        const uint32_t f = (grp << 2) + (lane >> 4);
+        float cv = 0.f, av = 0.f;
+        if (f < F) {
+            const uint32_t ph = lds_phys(fibre_base(a, j, f) + e * step, a.pad_shift);
+            cv = ctf[2 * ph + im];
+            av = atf[2 * ph + im];
+        }
+        M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv, av, M, 0, 0, 0);
+    }
+}
+
+// complex tile copy dst = src (same padded layout)
+__device__ __forceinline__ void ctile_copy(cf* dst, const cf* src, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_pass_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cf* lds = reinterpret_cast<cf*>(smem_raw);
+    CFrag8 fr;
+    load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<cf, cf>(lds, a, static_cast<const cf*>(a.in), t, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            cmfma_stage8(lds, a, j, rows, fr);
+            __syncthreads();
+        }
+        tile_store<cf, cf>(lds, a, static_cast<cf*>(a.out), t, rows);
+        __syncthreads();
+    }
+}
+
+// Backward of one digit group, complex radix 8, on the matrix cores.  LDS:
+// the group input A, a recomputation tile T and the cotangent Ct, plus the
+// per-wave gradient blocks for the final reduction.
+__global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs ba) {
+    const PassArgs& a = ba.p;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t tileP = tileE + (a.pad_shift < 31 ? (tileE >> a.pad_shift) : 0u) + 1u;
+    cf* A = reinterpret_cast<cf*>(smem_raw);
+    cf* T = A + tileP;
+    cf* Ct = T + tileP;
+    double* red = reinterpret_cast<double*>(Ct + tileP + 1);  // 4 waves x 256
+    CFrag8 fw, fh;
+    load_cfrag8(fw, static_cast<const cf*>(a.W), 0);
+    load_cfrag8(fh, static_cast<const cf*>(a.W), 1);
+    double Md[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<cf, cf>(A, a, static_cast<const cf*>(a.in), t, rows);
+        tile_load<cf, cf>(Ct, a, static_cast<const cf*>(ba.c_out), t, rows);
+        __syncthreads();
+        for (int s = a.k - 1; s >= 0; --s) {
+            const cf* act = A;
+            if (s > 0) {
+                // input of the pass on digit s: digits 0..s-1 applied to A
+                ctile_copy(T, A, tileP);
+                __syncthreads();
+                for (int j = 0; j < s; ++j) {
+                    cmfma_stage8(T, a, j, rows, fw);
+                    __syncthreads();
+                }
+                act = T;
+            }
+            f32x4_c M = {0.f, 0.f, 0.f, 0.f};
+            cmfma_gw8(Ct, act, a, s, rows, M);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
+            __syncthreads();
+            cmfma_stage8(Ct, a, s, rows, fh);
+            __syncthreads();
+        }
+        tile_store<cf, cf>(Ct, a, static_cast<cf*>(a.out), t, rows);
+        __syncthreads();
+    }
+    // reduce the four waves' 16 x 16 blocks, then form the complex gradient
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = Md[v];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
+        auto Mv = [&](int mm, int nn) {
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += red[w * 256 + mm * 16 + nn];
+            return s;
+        };
+        cf g;
+        g.re = (float)(Mv(2 * r, 2 * q) + Mv(2 * r + 1, 2 * q + 1));
+        g.im = (float)(Mv(2 * r + 1, 2 * q) - Mv(2 * r, 2 * q + 1));
+        static_cast<cf*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
+    }
+}
+
+}  // namespace gtt

@@ -13,6 +13,7 @@ enum class DT : int { F64 = 0, F32 = 1, C128 = 2, C64 = 3, BF16 = 4, F16 = 5, I3
 constexpr int kKindValu = 0;     // radix 2..8, register super-stages on the VALU
 constexpr int kKindGeneric = 1;  // any radix <= 64 and mixed radices, LDS sweeps
 constexpr int kKindMfma = 2;     // radix 16 / 32, bf16 / f16 storage, matrix cores
+constexpr int kKindCMfma = 3;    // complex64, radix 8, FP32 matrix cores
 
 // forward / inverse digit-group pass
 hipError_t launch_pass(DT dt, int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
@@ -22,6 +23,10 @@ struct BwdArgs;
 hipError_t launch_bwd(DT dt, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 // gW = fixed-order sum of nparts partial vectors of bb compute-dtype values
 hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s);
+
+struct CBwdArgs;
+// backward of one digit group, complex64 radix 8 on the matrix cores
+hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 struct RaggedArgs;
 // ragged-batch launch (all phases with grid barriers, or one phase)

@@ -35,7 +35,7 @@ struct RaggedState {
 static void build_worklist(gtt_plan_s* p) {
     RaggedState* rs = new RaggedState();
     p->rs = rs;
-    int maxR = 0;
+    int maxR = 1;
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
     const int64_t E = p->total_elems;
     struct Tmp {
@@ -45,15 +45,35 @@ static void build_worklist(gtt_plan_s* p) {
     };
     std::vector<Tmp> tmp;
     for (const Instance& t : p->inst) {
-        const int R = (int)t.groups.size();
-        std::vector<int> rad(t.n, t.b);
-        std::vector<int64_t> wofs(t.n, 0);
+        // n == 0 (N = 1, the identity): a one-element tile with no digit
+        std::vector<Group> idg;
+        if (t.groups.empty()) {
+            Group g0;
+            g0.k = 0;
+            g0.G = 1;
+            g0.S = 1;
+            g0.C = 1;
+            g0.P = 1;
+            g0.L = 1;
+            g0.ntiles = 1;
+            g0.tileE = 1;
+            g0.elems = 1;
+            g0.mode = kContigScalar;
+            g0.pad_shift = 31;
+            g0.kind = kKindValu;
+            g0.lds_bytes = 16 * p->csize;
+            idg.push_back(g0);
+        }
+        const std::vector<Group>& groups = t.groups.empty() ? idg : t.groups;
+        const int R = (int)groups.size();
+        std::vector<int> rad(std::max(t.n, 1), t.b);
+        std::vector<int64_t> wofs(std::max(t.n, 1), 0);
         for (int g = 0; g < R; ++g) {
-            const Group& G = t.groups[g];
+            const Group& G = groups[g];
             RaggedDesc d;
             std::memset(&d, 0, sizeof d);
             fill_pass_args(&d.a, G, rad, wofs, t.N);
-            d.b = t.b;
+            d.b = t.groups.empty() ? 2 : t.b;  // identity tiles take the radix-2 path (no digit)
             d.kind = G.kind;
             d.w_off = p->w_off[t.w];
             d.in_sel = (g == 0) ? 0 : 2;
@@ -278,11 +298,15 @@ static int max_groups(const gtt_plan_s* p) {
 }
 
 size_t bwd_partial_bytes(const gtt_plan_s* p) {
+    // per-work-group partials, plus 64 first-stage reduction vectors after the
+    // partials of each W (radix <= 16: at most 256 values each)
     size_t partial = 0;
     if (p->kind == PlanKind::Ragged) {
         for (const Instance& t : p->inst) partial += bwd_partials_elems(t.bwd_groups, t.b) * p->csize;
+        partial += p->w_b.size() * 64 * 256 * p->csize;
     } else if (p->kind == PlanKind::Uniform) {
         partial += bwd_partials_elems(p->bwd_groups, p->b) * p->csize;
+        partial += 64 * (size_t)p->b * p->b * p->csize;
     }
     return (partial + 255) & ~(size_t)255;
 }
@@ -378,7 +402,7 @@ std::string describe_plan(const gtt_plan_s* p) {
                       "{\"s0\":%d,\"k\":%d,\"S\":%lld,\"G\":%lld,\"C\":%d,\"P\":%d,\"L\":%lld,\"tiles\":%lld,"
                       "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"kind\":\"%s\",\"lds_bytes\":%zu}",
                       g.s0, g.k, (long long)g.S, (long long)g.G, g.C, g.P, (long long)g.L, (long long)g.ntiles,
-                      (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : "mfma",
+                      (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : g.kind == 2 ? "mfma" : "cmfma",
                       g.lds_bytes);
         return std::string(b);
     };

@@ -1,5 +1,6 @@
 // Instantiations of the digit-group pass kernels for storage type cf.
 #include "gtt_launch.hpp"
+#include "gtt_cmfma.hpp"
 #include "gtt_pass.hpp"
 
 namespace gtt {
@@ -24,6 +25,9 @@ hipError_t launch_pass_c64(int b, int kind, const PassArgs& a, unsigned grid, si
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
         return hipErrorInvalidValue;
+    } else if (kind == kKindCMfma) {
+        if (b != 8) return hipErrorInvalidValue;
+        GTT_LAUNCH(gtt_c64_mfma8_pass_kernel);
     } else {
         switch (b) {
             case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
@@ -37,6 +41,13 @@ hipError_t launch_pass_c64(int b, int kind, const PassArgs& a, unsigned grid, si
         }
     }
 #undef GTT_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds(gtt_c64_mfma8_bwd_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gtt_c64_mfma8_bwd_kernel, dim3(grid), dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
 

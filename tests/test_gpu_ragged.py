@@ -1,0 +1,169 @@
+"""Ragged batches: instances of different radix and length in one buffer,
+run as one persistent launch (grid barrier between digit groups), as one
+launch per phase, or per instance; every instance checked against the FP64
+oracle.  Also graph capture and replay of the persistent launch."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import COMPLEX, TOL, host64, rel_err, say
+from oracle import gtt_oracle as O
+from paper_2507_02420_amd import gtt as G
+from paper_2507_02420_amd.inputs import gaussian, haar_unitary, ragged_shapes
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"phases": 0, "persistent": G.FLAG_PERSISTENT, "per_instance": G.FLAG_PER_INSTANCE}
+
+
+def _ragged_inputs(shapes, dtype, seed, x_off=None, w_idx=None):
+    cplx = dtype in COMPLEX
+    Ns = [b ** n for b, n in shapes]
+    if x_off is None:
+        offs = np.cumsum([0] + Ns[:-1]).tolist()
+        total = int(sum(Ns))
+    else:
+        offs = list(x_off)
+        total = int(max(o + N for o, N in zip(offs, Ns)))
+    total = (total + 7) // 8 * 8
+    x = gaussian(total, seed=seed, complex_=cplx)
+    if w_idx is None:
+        radices = sorted(set(b for b, _ in shapes))
+        Ws = [haar_unitary(r, seed + 1 + i, complex_=cplx) for i, r in enumerate(radices)]
+        widx = [radices.index(b) for b, _ in shapes]
+    else:
+        nw = max(w_idx) + 1
+        rad_of = {}
+        for (b, _), w in zip(shapes, w_idx):
+            rad_of[w] = b
+        Ws = [haar_unitary(rad_of[w], seed + 50 + w, complex_=cplx) for w in range(nw)]
+        widx = list(w_idx)
+    wdt = G.W_DTYPE[dtype]
+    Wt = torch.cat([torch.from_numpy(w).to(wdt).reshape(-1) for w in Ws]).cuda()
+    xt = torch.from_numpy(x).to(dtype).cuda()
+    W64 = [torch.from_numpy(w).to(wdt).to(torch.complex128 if cplx else torch.float64).numpy() for w in Ws]
+    return xt, Wt, W64, widx, offs
+
+
+SMALL = [(2, 11), (4, 3), (16, 2), (32, 2), (3, 4), (2, 0), (8, 3), (16, 3), (4, 7), (2, 15), (32, 1), (7, 2),
+         (16, 4), (2, 1), (4, 5), (5, 3), (32, 3), (2, 17), (3, 1), (6, 3)]
+
+
+@pytest.mark.parametrize("mode", list(MODES), ids=str)
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.complex64], ids=str)
+def test_ragged_forward_inverse(mode, dtype):
+    say(f"ragged {mode} {dtype}")
+    shapes = SMALL
+    xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=800)
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=MODES[mode])
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    x64, y64, xi64 = host64(xt), host64(y), host64(xi)
+    tol = TOL[dtype]
+    for t, ((b, n), o) in enumerate(zip(shapes, offs)):
+        N = b ** n
+        ref = O.staged(W64[widx[t]], x64[o:o + N], n)
+        e = rel_err(y64[o:o + N], ref)
+        assert e < tol, (t, b, n, e)
+        assert rel_err(xi64[o:o + N], x64[o:o + N]) < 3 * tol, (t, b, n)
+
+
+def test_ragged_offsets_and_shared_w():
+    # explicit offsets with gaps; two instances of radix 4 use different W
+    shapes = [(4, 5), (2, 9), (4, 3), (16, 2), (2, 4)]
+    x_off = [0, 1024 + 8, 1024 + 8 + 512 + 16, 2048, 4096]
+    w_idx = [0, 1, 2, 3, 1]
+    dtype = torch.complex64
+    xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=900, x_off=x_off, w_idx=w_idx)
+    for flags in (0, G.FLAG_PERSISTENT):
+        plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=flags, x_off=x_off,
+                      w_idx=w_idx)
+        y = torch.zeros_like(xt)
+        plan.forward(Wt, xt, y)
+        torch.cuda.synchronize()
+        x64, y64 = host64(xt), host64(y)
+        for t, ((b, n), o) in enumerate(zip(shapes, offs)):
+            N = b ** n
+            assert rel_err(y64[o:o + N], O.staged(W64[widx[t]], x64[o:o + N], n)) < 1e-5
+
+
+def test_ragged_backward_per_w():
+    shapes = [(2, 10), (4, 4), (2, 6), (8, 3), (4, 6), (3, 5)]
+    dtype = torch.complex64
+    xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=1000)
+    g = torch.from_numpy(gaussian(xt.numel(), seed=1001, complex_=True)).to(dtype).cuda()
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype)
+    _, _, sv = plan.workspace_size()
+    saved = torch.empty(sv, dtype=torch.uint8, device="cuda") if sv else None
+    plan.forward(Wt, xt, saved=saved)
+    gx, gW = plan.backward(Wt, xt, g, saved=saved)
+    torch.cuda.synchronize()
+    x64, g64, gx64, gW64 = host64(xt), host64(g), host64(gx), host64(gW)
+    ref_gW = [np.zeros_like(w) for w in W64]
+    for t, ((b, n), o) in enumerate(zip(shapes, offs)):
+        N = b ** n
+        rgx, rgW = O.grad(W64[widx[t]], x64[o:o + N], g64[o:o + N], n)
+        assert rel_err(gx64[o:o + N], rgx) < 1e-5
+        ref_gW[widx[t]] += rgW
+    pos = 0
+    for w in ref_gW:
+        got = gW64[pos:pos + w.size].reshape(w.shape)
+        assert np.linalg.norm(got - w) / np.linalg.norm(w) < 1e-5
+        pos += w.size
+
+
+def test_ragged_full_shape_list_bf16_persistent_sampled():
+    # the 1024-instance shape list (b in {2,4,16,32}, N in [2^10, 2^20],
+    # 268,417,024 elements) in bf16, one persistent launch; sampled instances
+    # against the FP64 oracle on the stored bf16 values
+    shapes = ragged_shapes(1024, seed=52)
+    say("ragged 1024 bf16 persistent")
+    Ns = [b ** n for b, n in shapes]
+    offs = np.cumsum([0] + Ns[:-1])
+    total = int(sum(Ns))
+    rng = np.random.default_rng(53)
+    xt = torch.from_numpy(rng.standard_normal(total, dtype=np.float32)).cuda().to(torch.bfloat16)
+    Ws = [haar_unitary(r, 54 + i, complex_=False).astype(np.float32) for i, r in enumerate((2, 4, 16, 32))]
+    Wt = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).cuda()
+    ridx = {2: 0, 4: 1, 16: 2, 32: 3}
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, torch.bfloat16, flags=G.FLAG_PERSISTENT)
+    y = plan.forward(Wt, xt)
+    torch.cuda.synchronize()
+    errs = {}
+    for t in list(range(0, 1024, 37)) + [int(np.argmax(Ns))]:
+        b, n = shapes[t]
+        o, N = int(offs[t]), Ns[t]
+        x64 = xt[o:o + N].float().cpu().double().numpy()
+        ref = O.staged(Ws[ridx[b]].astype(np.float64), x64, n)
+        e = rel_err(y[o:o + N].float().cpu().double().numpy(), ref)
+        errs.setdefault(b, []).append(e)
+        assert e < 1e-2, (t, b, n, e)
+    say("  max rel err per radix: " + ", ".join(f"b={b}: {max(v):.2e}" for b, v in sorted(errs.items())))
+
+
+def test_ragged_persistent_graph_replay():
+    shapes = SMALL
+    dtype = torch.bfloat16
+    xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=1100)
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=G.FLAG_PERSISTENT)
+    y_eager = plan.forward(Wt, xt)           # first call uploads the work list
+    torch.cuda.synchronize()
+    y = torch.empty_like(xt)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(Wt, xt, y)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.forward(Wt, xt, y)
+    for rep in range(3):
+        y.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_eager), rep
+        # eager work between replays
+        _ = plan.forward(Wt, xt)
+        torch.cuda.synchronize()
