@@ -147,7 +147,8 @@ def test_ragged_persistent_graph_replay():
     dtype = torch.bfloat16
     xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=1100)
     plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=G.FLAG_PERSISTENT)
-    y_eager = plan.forward(Wt, xt)           # first call uploads the work list
+    y_eager = torch.zeros_like(xt)           # the buffer tail past the last instance stays 0
+    plan.forward(Wt, xt, y_eager)            # first call uploads the work list
     torch.cuda.synchronize()
     y = torch.empty_like(xt)
     s = torch.cuda.Stream()
