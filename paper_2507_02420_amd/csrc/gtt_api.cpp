@@ -258,12 +258,18 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                     s += k;
                 }
                 if (bwd_groups) {
-                    // backward: same digit groups, tiles of at most 40 KiB
+                    // backward: same digit groups, tiles of at most 40 KiB; the
+                    // matrix-core backward handles up to 4 digits on vector
+                    // tiles of at most 8192 elements, others take the
+                    // runtime-radix backward
                     bwd_groups->clear();
                     const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
                     for (const Group& fg : *groups) {
                         Group g;
                         fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
+                        if (g.kind == kKindCMfma &&
+                            (g.k > 4 || g.tileE > 8192 || (g.mode != kContigVec && g.mode != kRowVec)))
+                            g.kind = kKindValu;
                         bwd_groups->push_back(g);
                     }
                 }
@@ -320,14 +326,21 @@ static const char* dt_name(gtt_dtype d) {
 
 static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, const std::vector<int>& rad,
                                const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
-                               const void* in, void* out, hipStream_t s) {
+                               const void* in, void* out, hipStream_t s, int64_t cut = -1, bool keep_high = false) {
     PassArgs a;
     fill_pass_args(&a, g, rad, wofs, N);
+    a.cut = cut;
+    a.cut_keep_high = keep_high ? 1 : 0;
     a.in = in;
     a.out = out;
     a.W = W;
     a.adjoint = adjoint ? 1 : 0;
-    const unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, (int64_t)0x7fffffff);
+    // one work-group per tile (the prefetching persistent variant of the
+    // tile loop measured slower on MI355X: its extra registers cost more
+    // occupancy than the overlap gains)
+    a.pf = 0;
+    const int64_t gmax = (int64_t)0x7fffffff;
+    const unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, gmax);
     timing_begin(tp, s);
     hipError_t e = launch_pass(to_dt(dt), rad[g.s0], g.kind, a, grid, g.lds_bytes, s);
     if (tp && tp->timing.enabled) {
@@ -354,7 +367,8 @@ gtt_status launch_group_inst(gtt_plan_s* tp, gtt_dtype dt, const Group& g, int b
 // group i < R-1 writes `mid[i]` (or `out` when mid is null); the last writes out.
 static gtt_status run_groups(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>& groups, const std::vector<int>& rad,
                              const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint,
-                             const void* in, void* out, char* saved, size_t elems, hipStream_t s) {
+                             const void* in, void* out, char* saved, size_t elems, hipStream_t s,
+                             int64_t cut = -1, bool keep_high = false) {
     const size_t es = storage_size(dt);
     if (groups.empty()) {
         if (in != out)
@@ -365,7 +379,8 @@ static gtt_status run_groups(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Gro
     for (size_t i = 0; i < groups.size(); ++i) {
         void* dst = out;
         if (i + 1 < groups.size() && saved) dst = saved + i * elems * es;
-        gtt_status st = launch_group(tp, dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s);
+        gtt_status st = launch_group(tp, dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s, i == 0 ? cut : -1,
+                                     keep_high);
         if (st != GTT_OK) return st;
         src = dst;
     }
@@ -655,3 +670,30 @@ gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff
 }
 
 }  // extern "C"
+
+namespace gtt {
+// Natural-order filter (§4.3, Alg. 3 classical analogue): coefficients into
+// the workspace, then two inverse transforms whose first digit group masks
+// the coefficients by natural index as it loads them.
+gtt_status filter_impl(gtt_plan_s* p, const void* W, const void* x, int64_t cutoff, void* low, void* high, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+    const size_t E = (size_t)p->total_elems;
+    size_t f = 0, bw = 0, sv = 0;
+    workspace_sizes(p, &f, &bw, &sv);
+    if (ws_bytes < f + E * p->esize || !ws) return GTT_ERR_WORKSPACE;
+    if (p->groups.empty()) return GTT_ERR_UNSUPPORTED;  // n == 0: nothing to filter
+    char* coef = static_cast<char*>(ws) + f;
+    const int64_t cut = std::min<int64_t>(cutoff, p->N);
+    gtt_status st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, coef, nullptr, E, s);
+    if (st != GTT_OK) return st;
+    if (low) {
+        st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, coef, low, nullptr, E, s, cut, false);
+        if (st != GTT_OK) return st;
+    }
+    if (high) {
+        st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, coef, high, nullptr, E, s, cut, true);
+        if (st != GTT_OK) return st;
+    }
+    return GTT_OK;
+}
+}  // namespace gtt

@@ -21,13 +21,16 @@ static const char* kDtName[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32
 // LDS bytes of the backward kernel for a tile geometry
 size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
     const int64_t tileP = g.tileE + (g.pad_shift < 31 ? (g.tileE >> g.pad_shift) : 0) + 1;
-    if (g.kind == kKindCMfma) return (size_t)(3 * tileP + 1) * csize + 4 * 256 * sizeof(double);
+    if (g.kind == kKindCMfma) return std::max<size_t>((size_t)(4 * tileP + 1) * csize, 16 * 256 * sizeof(double));
     const int maxb = b <= 8 ? 8 : 16;
     return (size_t)(3 * maxb * maxb + kThreads + 3 * tileP) * csize;
 }
 
-// work-groups of one backward launch (fixed per plan: determinism of gW)
-static unsigned bwd_grid(const Group& g) { return (unsigned)std::min<int64_t>(g.ntiles, 2048); }
+// work-groups of one backward launch (fixed per plan: determinism of gW);
+// the matrix-core kernel is one 1024-thread work-group per compute unit
+static unsigned bwd_grid(const Group& g) {
+    return (unsigned)std::min<int64_t>(g.ntiles, g.kind == kKindCMfma ? 256 : 2048);
+}
 
 size_t bwd_partials_elems(const std::vector<Group>& bg, int b) {
     size_t e = 0;
@@ -212,8 +215,5 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
     return GTT_OK;
 }
 
-gtt_status filter_impl(gtt_plan_s*, const void*, const void*, int64_t, void*, void*, void*, size_t, hipStream_t) {
-    return GTT_ERR_UNSUPPORTED;
-}
 
 }  // namespace gtt

@@ -60,15 +60,18 @@ __device__ __forceinline__ uint32_t fibre_base(const PassArgs& a, int j, uint32_
     return ((Q * (uint32_t)a.bpow[j + 1] + glo) << a.logC) | c;
 }
 
-// W (fragments f) along digit j of every fibre of the complex tile, in place.
-__device__ __forceinline__ void cmfma_stage8(cf* lds, const PassArgs& a, int j, uint32_t rows, const CFrag8& fr) {
+// W (fragments f) along digit j of every fibre of the complex tile: reads
+// src, writes dst (in place when they are equal).  NT threads per work-group.
+template <int NT = kThreads>
+__device__ __forceinline__ void cmfma_stage8(const cf* src, cf* dst, const PassArgs& a, int j, uint32_t rows,
+                                             const CFrag8& fr) {
     const uint32_t F = (rows << a.logC) >> 3;
     const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int q = lane >> 4;
     const uint32_t ngrp = (F + 15) >> 4;
-    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+    for (uint32_t grp = wave; grp < ngrp; grp += NT / 64) {
         const uint32_t f = (grp << 4) + (lane & 15);
         const bool valid = f < F;
         uint32_t p0 = 0, p1 = 0;
@@ -77,8 +80,8 @@ __device__ __forceinline__ void cmfma_stage8(cf* lds, const PassArgs& a, int j, 
             const uint32_t lam0 = fibre_base(a, j, f);
             p0 = lds_phys(lam0 + (2 * q) * step, a.pad_shift);
             p1 = lds_phys(lam0 + (2 * q + 1) * step, a.pad_shift);
-            x0 = lds[p0];
-            x1 = lds[p1];
+            x0 = src[p0];
+            x1 = src[p1];
         }
         f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0.re, acc, 0, 0, 0);
@@ -86,13 +89,14 @@ __device__ __forceinline__ void cmfma_stage8(cf* lds, const PassArgs& a, int j, 
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1.re, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1.im, acc, 0, 0, 0);
         if (valid) {
-            lds[p0] = cf{acc[0], acc[1]};
-            lds[p1] = cf{acc[2], acc[3]};
+            dst[p0] = cf{acc[0], acc[1]};
+            dst[p1] = cf{acc[2], acc[3]};
         }
     }
 }
 
 // M += sum over the fibres of digit j of [c] [a]^T (see the header comment).
+template <int NT = kThreads>
 __device__ __forceinline__ void cmfma_gw8(const cf* ct, const cf* at, const PassArgs& a, int j, uint32_t rows,
                                           f32x4_c& M) {
     const uint32_t F = (rows << a.logC) >> 3;
@@ -105,7 +109,7 @@ __device__ __forceinline__ void cmfma_gw8(const cf* ct, const cf* at, const Pass
     const uint32_t ngrp = (F + 3) >> 2;
     const float* ctf = reinterpret_cast<const float*>(ct);
     const float* atf = reinterpret_cast<const float*>(at);
-    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+    for (uint32_t grp = wave; grp < ngrp; grp += NT / 64) {
         const uint32_t f = (grp << 2) + (lane >> 4);
         float cv = 0.f, av = 0.f;
         if (f < F) {
@@ -117,74 +121,154 @@ __device__ __forceinline__ void cmfma_gw8(const cf* ct, const cf* at, const Pass
     }
 }
 
-// complex tile copy dst = src (same padded layout)
-__device__ __forceinline__ void ctile_copy(cf* dst, const cf* src, uint32_t n) {
-    for (uint32_t i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
-}
 
+template <bool PF>
 __global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cf* lds = reinterpret_cast<cf*>(smem_raw);
     CFrag8 fr;
     load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
-    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<cf, cf>(lds, a, static_cast<const cf*>(a.in), t, rows);
-        __syncthreads();
+    tile_loop<cf, cf, PF>(lds, a, [&](cf* t, uint32_t rows) {
         for (int j = 0; j < a.k; ++j) {
-            cmfma_stage8(lds, a, j, rows, fr);
+            cmfma_stage8(t, t, a, j, rows, fr);
             __syncthreads();
         }
-        tile_store<cf, cf>(lds, a, static_cast<cf*>(a.out), t, rows);
-        __syncthreads();
+    });
+}
+
+// Backward of one digit group (k <= 4 digits), complex radix 8, on the
+// matrix cores, kBwdThreads threads (the LDS of one group tile allows one
+// work-group per compute unit; 16 waves keep the MFMA and LDS pipes busy).
+// LDS holds the group input A, two activation slots T1, T2 and the
+// cotangent Ct.  With a_s the input of the pass on digit s:
+//   T1 = a_1; T2 = a_2 (then a_3 = W T2 in place when k = 4);
+//   for s = k-1 .. 0: accumulate the c a_s^H sums, then Ct <- W^H Ct along s,
+//   recomputing a_2 from T1 once when k = 4.
+// The next tile's A and Ct are fetched into registers while the current tile
+// is processed.
+constexpr int kBwdThreads = 1024;
+constexpr int kBwdVec = 4;  // 16-byte vectors per thread and buffer (tile <= 8192 c64)
+
+__device__ __forceinline__ void bwd_fetch(uint4 (&buf)[kBwdVec], const PassArgs& a, const cf* __restrict__ in,
+                                          int64_t t, uint32_t tileE) {
+    const bool contig = a.mode == kContigVec;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    const uint32_t nvec = tileE / 2;
+#pragma unroll
+    for (int v = 0; v < kBwdVec; ++v) {
+        const uint32_t i = threadIdx.x + v * kBwdThreads;
+        if (i < nvec) buf[v] = *reinterpret_cast<const uint4*>(in + vec_offset<cf>(a, t, i, hb, l, tileE));
     }
 }
 
-// Backward of one digit group, complex radix 8, on the matrix cores.  LDS:
-// the group input A, a recomputation tile T and the cotangent Ct, plus the
-// per-wave gradient blocks for the final reduction.
-__global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs ba) {
+__device__ __forceinline__ void bwd_commit(cf* lds, const uint4 (&buf)[kBwdVec], const PassArgs& a,
+                                           uint32_t tileE) {
+    const uint32_t nvec = tileE / 2;
+#pragma unroll
+    for (int v = 0; v < kBwdVec; ++v) {
+        const uint32_t i = threadIdx.x + v * kBwdThreads;
+        if (i < nvec) {
+            cf vals[2];
+            *reinterpret_cast<uint4*>(vals) = buf[v];
+            const uint32_t ph = lds_phys(i * 2, a.pad_shift);
+            lds[ph] = vals[0];
+            lds[ph + 1] = vals[1];
+        }
+    }
+}
+
+__device__ __forceinline__ void bwd_store(const cf* lds, const PassArgs& a, cf* __restrict__ out, int64_t t,
+                                          uint32_t tileE) {
+    const bool contig = a.mode == kContigVec;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    const uint32_t nvec = tileE / 2;
+    for (uint32_t i = threadIdx.x; i < nvec; i += kBwdThreads) {
+        cf vals[2];
+        const uint32_t ph = lds_phys(i * 2, a.pad_shift);
+        vals[0] = lds[ph];
+        vals[1] = lds[ph + 1];
+        *reinterpret_cast<uint4*>(out + vec_offset<cf>(a, t, i, hb, l, tileE)) = *reinterpret_cast<const uint4*>(vals);
+    }
+}
+
+__global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs ba) {
     const PassArgs& a = ba.p;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
     const uint32_t tileE = rows << a.logC;
     const uint32_t tileP = tileE + (a.pad_shift < 31 ? (tileE >> a.pad_shift) : 0u) + 1u;
     cf* A = reinterpret_cast<cf*>(smem_raw);
-    cf* T = A + tileP;
-    cf* Ct = T + tileP;
-    double* red = reinterpret_cast<double*>(Ct + tileP + 1);  // 4 waves x 256
+    cf* T1 = A + tileP;
+    cf* T2 = T1 + tileP;
+    cf* Ct = T2 + tileP;
+    // 16 waves x 256 doubles for the final reduction, reusing the tiles' LDS
+    double* red = reinterpret_cast<double*>(smem_raw);
     CFrag8 fw, fh;
     load_cfrag8(fw, static_cast<const cf*>(a.W), 0);
     load_cfrag8(fh, static_cast<const cf*>(a.W), 1);
     double Md[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<cf, cf>(A, a, static_cast<const cf*>(a.in), t, rows);
-        tile_load<cf, cf>(Ct, a, static_cast<const cf*>(ba.c_out), t, rows);
-        __syncthreads();
-        for (int s = a.k - 1; s >= 0; --s) {
-            const cf* act = A;
-            if (s > 0) {
-                // input of the pass on digit s: digits 0..s-1 applied to A
-                ctile_copy(T, A, tileP);
-                __syncthreads();
-                for (int j = 0; j < s; ++j) {
-                    cmfma_stage8(T, a, j, rows, fw);
-                    __syncthreads();
-                }
-                act = T;
-            }
-            f32x4_c M = {0.f, 0.f, 0.f, 0.f};
-            cmfma_gw8(Ct, act, a, s, rows, M);
+    const cf* xin = static_cast<const cf*>(a.in);
+    const cf* cin = static_cast<const cf*>(ba.c_out);
+    uint4 pa[kBwdVec], pc[kBwdVec];
+    int64_t t = blockIdx.x;
+    if (t < a.ntiles) {
+        bwd_fetch(pa, a, xin, t, tileE);
+        bwd_fetch(pc, a, cin, t, tileE);
+    }
+    auto gw = [&](const cf* act, int s) {
+        f32x4_c M = {0.f, 0.f, 0.f, 0.f};
+        cmfma_gw8<kBwdThreads>(Ct, act, a, s, rows, M);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
-            __syncthreads();
-            cmfma_stage8(Ct, a, s, rows, fh);
+        for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
+        __syncthreads();  // every wave has read Ct before the pass on s rewrites it
+    };
+    auto adj = [&](int s) {
+        cmfma_stage8<kBwdThreads>(Ct, Ct, a, s, rows, fh);
+        __syncthreads();
+    };
+    for (; t < a.ntiles; t += gridDim.x) {
+        bwd_commit(A, pa, a, tileE);
+        bwd_commit(Ct, pc, a, tileE);
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        if (tn < a.ntiles) {  // in flight while this tile is processed
+            bwd_fetch(pa, a, xin, tn, tileE);
+            bwd_fetch(pc, a, cin, tn, tileE);
+        }
+        const int k = a.k;
+        if (k >= 2) {
+            cmfma_stage8<kBwdThreads>(A, T1, a, 0, rows, fw);  // a_1
             __syncthreads();
         }
-        tile_store<cf, cf>(Ct, a, static_cast<cf*>(a.out), t, rows);
+        if (k >= 3) {
+            cmfma_stage8<kBwdThreads>(T1, T2, a, 1, rows, fw);  // a_2
+            __syncthreads();
+        }
+        if (k == 4) {
+            cmfma_stage8<kBwdThreads>(T2, T2, a, 2, rows, fw);  // a_3
+            __syncthreads();
+            gw(T2, 3);
+            adj(3);
+            cmfma_stage8<kBwdThreads>(T1, T2, a, 1, rows, fw);  // a_2 again
+            __syncthreads();
+        }
+        if (k >= 3) {
+            gw(T2, 2);
+            adj(2);
+        }
+        if (k >= 2) {
+            gw(T1, 1);
+            adj(1);
+        }
+        gw(A, 0);
+        adj(0);
+        bwd_store(Ct, a, static_cast<cf*>(a.out), t, tileE);
         __syncthreads();
     }
-    // reduce the four waves' 16 x 16 blocks, then form the complex gradient
+    // reduce the waves' 16 x 16 blocks in a fixed order, then form the
+    // complex gradient
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = Md[v];
@@ -193,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs ba
         const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
         auto Mv = [&](int mm, int nn) {
             double s = 0.0;
-            for (int w = 0; w < 4; ++w) s += red[w * 256 + mm * 16 + nn];
+            for (int w = 0; w < kBwdThreads / 64; ++w) s += red[w * 256 + mm * 16 + nn];
             return s;
         };
         cf g;

@@ -142,23 +142,18 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     }
 }
 
-template <typename T, int B>
+template <typename T, int B, bool PF>
 __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* lds = reinterpret_cast<float*>(smem_raw);
     WFrag<T, B> wf;
     load_w_frag<T, B>(wf, a);
-    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, float>(lds, a, static_cast<const T*>(a.in), t, rows);
-        __syncthreads();
+    tile_loop<T, float, PF>(lds, a, [&](float* t, uint32_t rows) {
         for (int j = 0; j < a.k; ++j) {
-            mfma_stage<T, B>(lds, a, j, rows, wf);
+            mfma_stage<T, B>(t, a, j, rows, wf);
             __syncthreads();
         }
-        tile_store<T, float>(lds, a, static_cast<T*>(a.out), t, rows);
-        __syncthreads();
-    }
+    });
 }
 
 }  // namespace gtt

@@ -140,51 +140,90 @@ __device__ __forceinline__ int64_t row_offset(const PassArgs& a, int64_t hb, int
     return (hb * a.P + p) * ((int64_t)a.G * a.S) + (int64_t)g * a.S + (l << a.logC);
 }
 
+// All global loads of a thread are issued before the first LDS write, so a
+// thread has up to kLoadBatch accesses in flight instead of one.
+constexpr int kLoadBatch = 8;
+
+// global element offset of 16-byte vector i of tile t (vector modes)
+template <typename T>
+__device__ __forceinline__ int64_t vec_offset(const PassArgs& a, int64_t t, uint32_t i, int64_t hb, int64_t l,
+                                              uint32_t tileE) {
+    constexpr int V = Vec16<T>::V;
+    if (a.mode == kContigVec) return t * (int64_t)tileE + (int64_t)i * V;
+    const int lcv = a.logC - __builtin_ctz(V);  // log2(vectors per row)
+    const uint32_t r = i >> lcv;
+    const uint32_t cc = i & ((1u << lcv) - 1u);
+    return row_offset(a, hb, l, r) + (int64_t)cc * V;
+}
+
+// global element offset of element i of tile t (scalar modes); -1 when the
+// element lies past the last valid column of a partial column block
+__device__ __forceinline__ int64_t elem_offset(const PassArgs& a, int64_t t, uint32_t i, int64_t hb, int64_t l,
+                                               uint32_t tileE) {
+    if (a.mode == kContigScalar) return t * (int64_t)tileE + i;
+    const uint32_t r = i >> a.logC;
+    const uint32_t c = i & ((1u << a.logC) - 1u);
+    if ((int64_t)c >= a.S - (l << a.logC)) return -1;
+    return row_offset(a, hb, l, r) + c;
+}
+
 template <typename T, typename C>
 __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
                                           uint32_t rows) {
     constexpr int V = Vec16<T>::V;
     const uint32_t tileE = rows << a.logC;
-    if (a.mode == kContigVec || a.mode == kContigScalar) {
-        const int64_t base = t * (int64_t)tileE;
-        if (a.mode == kContigVec) {
-            for (uint32_t i = threadIdx.x; i < tileE / V; i += kThreads) {
-                T v[V];
-                *reinterpret_cast<uint4*>(v) = *reinterpret_cast<const uint4*>(in + base + (int64_t)i * V);
-                const uint32_t ph = lds_phys(i * V, a.pad_shift);
+    const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    if (a.mode == kContigVec || a.mode == kRowVec) {
+        const uint32_t nvec = tileE / V;
+        for (uint32_t i0 = 0; i0 < nvec; i0 += kLoadBatch * kThreads) {
+            uint4 buf[kLoadBatch];
 #pragma unroll
-                for (int e = 0; e < V; ++e) lds[ph + e] = to_c(v[e]);
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < nvec) buf[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
             }
-        } else {
-            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads)
-                lds[lds_phys(i, a.pad_shift)] = to_c(in[base + i]);
-        }
-        return;
-    }
-    const int64_t hb = (a.L == 1) ? t : t / a.L;
-    const int64_t l = t - hb * a.L;
-    if (a.mode == kRowVec) {
-        const int lcv = a.logC - __builtin_ctz(V);  // log2(vectors per row)
-        const uint32_t n = tileE / V;
-        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
-            const uint32_t r = i >> lcv;
-            const uint32_t cc = i & ((1u << lcv) - 1u);
-            T v[V];
-            *reinterpret_cast<uint4*>(v) =
-                *reinterpret_cast<const uint4*>(in + row_offset(a, hb, l, r) + (int64_t)cc * V);
-            const uint32_t ph = lds_phys(i * V, a.pad_shift);
 #pragma unroll
-            for (int e = 0; e < V; ++e) lds[ph + e] = to_c(v[e]);
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < nvec) {
+                    T vals[V];
+                    *reinterpret_cast<uint4*>(vals) = buf[v];
+                    const uint32_t ph = lds_phys(i * V, a.pad_shift);
+                    if (a.cut >= 0) {  // natural-order mask of the filter
+                        const int64_t off = vec_offset<T>(a, t, i, hb, l, tileE);
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            const bool low = (off + e) % a.N < a.cut;
+                            lds[ph + e] = (low != (a.cut_keep_high != 0)) ? to_c(vals[e]) : czero<C>();
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
+                    }
+                }
+            }
         }
-    } else {  // kRowScalar
-        const int64_t cvalid = a.S - (l << a.logC);  // > 0
-        const uint32_t Cm = (1u << a.logC) - 1u;
-        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
-            const uint32_t r = i >> a.logC;
-            const uint32_t c = i & Cm;
-            C v = czero<C>();
-            if ((int64_t)c < cvalid) v = to_c(in[row_offset(a, hb, l, r) + c]);
-            lds[lds_phys(i, a.pad_shift)] = v;
+    } else {
+        for (uint32_t i0 = 0; i0 < tileE; i0 += kLoadBatch * kThreads) {
+            T buf[kLoadBatch];
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < tileE) {
+                    const int64_t off = elem_offset(a, t, i, hb, l, tileE);
+                    if (off >= 0 && (a.cut < 0 || ((off % a.N < a.cut) != (a.cut_keep_high != 0))))
+                        buf[v] = in[off];
+                    else
+                        buf[v] = from_c<T>(czero<C>());
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < tileE) lds[lds_phys(i, a.pad_shift)] = to_c(buf[v]);
+            }
         }
     }
 }
@@ -194,44 +233,103 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
                                            uint32_t rows) {
     constexpr int V = Vec16<T>::V;
     const uint32_t tileE = rows << a.logC;
-    if (a.mode == kContigVec || a.mode == kContigScalar) {
-        const int64_t base = t * (int64_t)tileE;
-        if (a.mode == kContigVec) {
-            for (uint32_t i = threadIdx.x; i < tileE / V; i += kThreads) {
-                T v[V];
-                const uint32_t ph = lds_phys(i * V, a.pad_shift);
-#pragma unroll
-                for (int e = 0; e < V; ++e) v[e] = from_c<T>(lds[ph + e]);
-                *reinterpret_cast<uint4*>(out + base + (int64_t)i * V) = *reinterpret_cast<const uint4*>(v);
-            }
-        } else {
-            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads)
-                out[base + i] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
-        }
-        return;
-    }
-    const int64_t hb = (a.L == 1) ? t : t / a.L;
-    const int64_t l = t - hb * a.L;
-    if (a.mode == kRowVec) {
-        const int lcv = a.logC - __builtin_ctz(V);
-        const uint32_t n = tileE / V;
-        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
-            const uint32_t r = i >> lcv;
-            const uint32_t cc = i & ((1u << lcv) - 1u);
-            T v[V];
+    const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    if (a.mode == kContigVec || a.mode == kRowVec) {
+        const uint32_t nvec = tileE / V;
+        for (uint32_t i = threadIdx.x; i < nvec; i += kThreads) {
+            T vals[V];
             const uint32_t ph = lds_phys(i * V, a.pad_shift);
 #pragma unroll
-            for (int e = 0; e < V; ++e) v[e] = from_c<T>(lds[ph + e]);
-            *reinterpret_cast<uint4*>(out + row_offset(a, hb, l, r) + (int64_t)cc * V) =
-                *reinterpret_cast<const uint4*>(v);
+            for (int e = 0; e < V; ++e) vals[e] = from_c<T>(lds[ph + e]);
+            *reinterpret_cast<uint4*>(out + vec_offset<T>(a, t, i, hb, l, tileE)) =
+                *reinterpret_cast<const uint4*>(vals);
         }
     } else {
-        const int64_t cvalid = a.S - (l << a.logC);
-        const uint32_t Cm = (1u << a.logC) - 1u;
         for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
-            const uint32_t r = i >> a.logC;
-            const uint32_t c = i & Cm;
-            if ((int64_t)c < cvalid) out[row_offset(a, hb, l, r) + c] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
+            const int64_t off = elem_offset(a, t, i, hb, l, tileE);
+            if (off >= 0) out[off] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined tile loop: the global loads of the work-group's next
+// tile are issued into registers before the current tile is transformed, so
+// HBM reads overlap the LDS / ALU / matrix-core work.  Tiles are assigned
+// statically (t = blockIdx.x + i * gridDim.x), so a prefetched tile is never
+// written by another work-group and in-place calls stay safe.
+// ---------------------------------------------------------------------------
+constexpr int kPrefVec = 8;     // 16-byte vectors per thread (tile <= 32 KiB)
+
+// 128 bytes of registers per thread: 8 vectors of 16 bytes
+struct TileBuf {
+    uint4 v[kPrefVec];
+};
+
+template <typename T>
+__device__ __forceinline__ void tile_fetch(TileBuf& buf, const PassArgs& a, const T* __restrict__ in, int64_t t,
+                                           uint32_t tileE) {
+    constexpr int V = Vec16<T>::V;
+    const bool contig = a.mode == kContigVec;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    const uint32_t nvec = tileE / V;
+#pragma unroll
+    for (int v = 0; v < kPrefVec; ++v) {
+        const uint32_t i = threadIdx.x + v * kThreads;
+        if (i < nvec) buf.v[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+    }
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ void tile_commit(C* lds, const TileBuf& buf, const PassArgs& a, uint32_t tileE) {
+    constexpr int V = Vec16<T>::V;
+    const uint32_t nvec = tileE / V;
+#pragma unroll
+    for (int v = 0; v < kPrefVec; ++v) {
+        const uint32_t i = threadIdx.x + v * kThreads;
+        if (i < nvec) {
+            T vals[V];
+            *reinterpret_cast<uint4*>(vals) = buf.v[v];
+            const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+            for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
+        }
+    }
+}
+
+// Runs stages(lds, rows) on every tile of this work-group, loading/storing
+// through the storage type T (compute type C in LDS).  PF: the software
+// pipelined variant (vector tile modes, at most kPrefVec vectors per thread,
+// no filter mask; the host only selects it then).
+template <typename T, typename C, bool PF, typename Stages>
+__device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& stages) {
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const T* in = static_cast<const T*>(a.in);
+    T* out = static_cast<T*>(a.out);
+    if constexpr (PF) {
+        TileBuf buf;
+        int64_t t = blockIdx.x;
+        if (t < a.ntiles) tile_fetch<T>(buf, a, in, t, tileE);
+        for (; t < a.ntiles; t += gridDim.x) {
+            tile_commit<T, C>(lds, buf, a, tileE);
+            __syncthreads();
+            const int64_t tn = t + gridDim.x;
+            if (tn < a.ntiles) tile_fetch<T>(buf, a, in, tn, tileE);
+            stages(lds, rows);
+            tile_store<T, C>(lds, a, out, t, rows);
+            __syncthreads();
+        }
+    } else {
+        for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+            tile_load<T, C>(lds, a, in, t, rows);
+            __syncthreads();
+            stages(lds, rows);
+            tile_store<T, C>(lds, a, out, t, rows);
+            __syncthreads();
         }
     }
 }
@@ -260,7 +358,7 @@ __device__ __forceinline__ void load_w(C (&w)[B * B], const PassArgs& a) {
     }
 }
 
-template <typename T, int B>
+template <typename T, int B, bool PF>
 __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     using C = typename Tr<T>::C;
     constexpr int RD = RegDigits<B>::v;
@@ -268,14 +366,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     C* lds = reinterpret_cast<C*>(smem_raw);
     C w[B * B];
     load_w<C, B>(w, a);
-    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(lds, a, static_cast<const T*>(a.in), t, rows);
-        __syncthreads();
-        run_stages<C, B, RD>(lds, a, rows, w);
-        tile_store<T, C>(lds, a, static_cast<T*>(a.out), t, rows);
-        __syncthreads();
-    }
+    tile_loop<T, C, PF>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
 }
 
 }  // namespace gtt

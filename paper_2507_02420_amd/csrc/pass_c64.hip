@@ -27,16 +27,16 @@ hipError_t launch_pass_c64(int b, int kind, const PassArgs& a, unsigned grid, si
         return hipErrorInvalidValue;
     } else if (kind == kKindCMfma) {
         if (b != 8) return hipErrorInvalidValue;
-        GTT_LAUNCH(gtt_c64_mfma8_pass_kernel);
+        GTT_LAUNCH(gtt_c64_mfma8_pass_kernel<false>);
     } else {
         switch (b) {
-            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
-            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3>)); break;
-            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4>)); break;
-            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5>)); break;
-            case 6: GTT_LAUNCH((gtt_pass_kernel<T, 6>)); break;
-            case 7: GTT_LAUNCH((gtt_pass_kernel<T, 7>)); break;
-            case 8: GTT_LAUNCH((gtt_pass_kernel<T, 8>)); break;
+            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2, false>)); break;
+            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3, false>)); break;
+            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4, false>)); break;
+            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5, false>)); break;
+            case 6: GTT_LAUNCH((gtt_pass_kernel<T, 6, false>)); break;
+            case 7: GTT_LAUNCH((gtt_pass_kernel<T, 7, false>)); break;
+            case 8: GTT_LAUNCH((gtt_pass_kernel<T, 8, false>)); break;
             default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
         }
     }
@@ -47,7 +47,7 @@ hipError_t launch_pass_c64(int b, int kind, const PassArgs& a, unsigned grid, si
 hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     hipError_t e = set_lds(gtt_c64_mfma8_bwd_kernel, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gtt_c64_mfma8_bwd_kernel, dim3(grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(gtt_c64_mfma8_bwd_kernel, dim3(grid), dim3(kBwdThreads), lds, s, a);
     return hipGetLastError();
 }
 

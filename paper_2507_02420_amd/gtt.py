@@ -82,7 +82,32 @@ def lib() -> ctypes.CDLL:
         if name != "gtt_status_string":
             getattr(L, name).restype = ctypes.c_int
     _lib = L
+    if not os.environ.get("GTT_NO_TUNE"):
+        load_tuning()
     return L
+
+
+TUNE_PATH = os.path.join(_HERE, "tuned_gfx950.json")
+_NAME_TO_GTT = {"f64": F64, "f32": F32, "c128": C128, "c64": C64, "bf16": BF16, "f16": F16, "i32": I32}
+
+
+def load_tuning(path: Optional[str] = None) -> int:
+    """Apply the autotuner's table (tile budget and least row width per radix
+    and dtype) to plans created afterwards; returns the number of entries."""
+    path = path or os.environ.get("GTT_TUNE_FILE") or TUNE_PATH
+    if not os.path.exists(path):
+        return 0
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return 0
+    n = 0
+    for e in table.get("entries", []):
+        st = _lib.gtt_set_tuning(int(e["b"]), _NAME_TO_GTT[e["dtype"]], int(e["lds_budget"]),
+                                 int(e["min_row_bytes"]))
+        n += st == OK
+    return n
 
 
 def _check(st: int, where: str):

@@ -1,0 +1,121 @@
+"""Autotuner for the digit-group tiling of libgtt.so.
+
+For each (radix, storage dtype) workload it times the forward transform over a
+grid of tile budgets (LDS bytes per tile) and least row widths of strided
+digit groups, through gtt_set_tuning, and records the fastest pair.  The
+result is a JSON table that ``gtt.load_tuning`` feeds back into
+gtt_set_tuning before plans are built.
+
+Usage (on the GPU):
+    python -m paper_2507_02420_amd.tune [--out FILE] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import torch
+
+from . import gtt as G
+
+DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+DT_NAMES = {torch.float64: "f64", torch.float32: "f32", torch.complex128: "c128", torch.complex64: "c64",
+            torch.bfloat16: "bf16", torch.float16: "f16", torch.int32: "i32"}
+DT_BY_NAME = {v: k for k, v in DT_NAMES.items()}
+
+# representative workloads: (b, n, batch, dtype)
+WORKLOADS = [
+    (8, 6, 256, torch.complex64),
+    (4, 10, 64, torch.complex64),
+    (3, 13, 16, torch.float32),
+    (2, 20, 16, torch.int32),
+    (2, 20, 16, torch.bfloat16),
+    (4, 10, 16, torch.bfloat16),
+    (16, 5, 16, torch.bfloat16),
+    (32, 4, 16, torch.bfloat16),
+]
+BUDGETS = [16384, 24576, 32768, 49152, 65536]
+MIN_ROWS = [64, 128, 256, 512]
+
+
+def _time_forward(plan, W, x, y, iters=10, flush=None):
+    for _ in range(2):
+        plan.forward(W, x, y)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(iters):
+        if flush is not None:
+            flush()
+            torch.cuda.synchronize()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        plan.forward(W, x, y)
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_one(b, n, batch, dtype, budgets=BUDGETS, min_rows=MIN_ROWS, log=print):
+    dev = torch.device("cuda")
+    N = b ** n
+    if dtype.is_complex:
+        x = torch.randn(batch, N, dtype=dtype, device=dev)
+    elif dtype == torch.int32:
+        x = torch.randint(-100, 101, (batch, N), dtype=torch.int32, device=dev)
+    else:
+        x = torch.randn(batch, N, device=dev).to(dtype)
+    wdt = G.W_DTYPE[dtype]
+    W = (torch.randn(b, b, device=dev) if wdt != torch.int32 else torch.ones(b, b, device=dev)).to(wdt)
+    y = torch.empty_like(x)
+    small = x.numel() * x.element_size() < (512 << 20)
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev) if small else None
+    flush = (lambda: scratch.zero_()) if small else None
+    best = None
+    results = []
+    for bud in budgets:
+        for mr in min_rows:
+            G.set_tuning(b, dtype, bud, mr)
+            try:
+                plan = G.Plan(b, n, batch, dtype)
+            except G.GTTError:
+                continue
+            desc = json.dumps([(g["k"], g["C"], g["P"]) for g in plan.describe()["groups"]])
+            ms = _time_forward(plan, W, x, y, flush=flush)
+            results.append((ms, bud, mr, desc))
+            if best is None or ms < best[0]:
+                best = (ms, bud, mr, desc)
+    G.set_tuning(b, dtype, 0, 0)
+    G.set_tuning(b, dtype, 0, 0)
+    base_plan = G.Plan(b, n, batch, dtype, flags=G.FLAG_NO_TUNE)
+    base = _time_forward(base_plan, W, x, y, flush=flush)
+    log(f"b={b} n={n} batch={batch} {DT_NAMES[dtype]}: heuristic {base:.4f} ms, best {best[0]:.4f} ms "
+        f"(budget {best[1]}, min row {best[2]}, groups {best[3]})")
+    return {"b": b, "n": n, "batch": batch, "dtype": DT_NAMES[dtype], "lds_budget": best[1],
+            "min_row_bytes": best[2], "ms": best[0], "heuristic_ms": base, "groups": best[3]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--quick", action="store_true", help="fewer grid points")
+    args = ap.parse_args()
+    budgets = [16384, 32768, 65536] if args.quick else BUDGETS
+    rows = [128, 256] if args.quick else MIN_ROWS
+    table = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "entries": []}
+    for (b, n, batch, dt) in WORKLOADS:
+        e = tune_one(b, n, batch, dt, budgets, rows, log=lambda m: print(m, flush=True))
+        # keep an override only when it beats the built-in heuristic
+        if e["ms"] < 0.98 * e["heuristic_ms"]:
+            table["entries"].append(e)
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(f"wrote {args.out}", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()
