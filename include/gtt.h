@@ -193,6 +193,19 @@ gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* 
 gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff,
                       void* low, void* high, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * gtt_compress -- classical state-transmission protocol (§4.1.1): the
+ * coefficients X = G_N x of every instance, the k of largest magnitude
+ * (|X|^2 in the compute precision; ties broken towards the lower index),
+ * written as idx[t][j] (int64, ascending) and val[t][j] (storage dtype),
+ * t < batch, j < k; if recon != NULL also recon = G_N^dagger applied to the
+ * vector that keeps only those k coefficients (the receiver's
+ * reconstruction).  1 <= k <= N.  Uniform plans.  Needs gtt_workspace_size's
+ * fwd bytes plus N*batch elements of the storage dtype in `ws`.
+ */
+gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, int64_t k, int64_t* idx, void* val,
+                        void* recon, void* ws, size_t ws_bytes, void* stream);
+
 /* Frees the plan and its device work list.  NULL is accepted. */
 gtt_status gtt_plan_destroy(gtt_plan_t p);
 

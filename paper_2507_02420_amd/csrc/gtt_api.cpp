@@ -181,21 +181,35 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
     }
     (void)V;
     gr->kind = kind;
-    // LDS padding: one element per register block (contiguous tiles) or per
-    // row (strided tiles) breaks power-of-two bank strides; odd radices need none
-    int pad = 31;
+    // LDS padding (see lds_phys): for a power-of-two radix, pads one digit
+    // apart starting at the register block (contiguous tiles) or at the row
+    // (strided tiles), so digit strides become odd bank strides; odd radices
+    // need none; radix 6 gets the register-block level only
+    int pad = kNoPad;
     if (gr->kind != kKindGeneric) {
         const int b = rad[s0];
+        const int lv = ilog2_floor(16 / esize);  // vector runs must not straddle a pad
+        int p1 = -1, step = 0;
         if ((b & (b - 1)) == 0) {
-            const int nb = (b == 2) ? 16 : (b == 4) ? 16 : b;  // register block size
-            pad = (gr->C == 1) ? ilog2_floor((uint64_t)nb) : gr->logC;
-            if (pad < 2) pad = 2;
+            const int nb = (b == 2 || b == 4) ? 16 : b;  // register block size
+            p1 = (gr->C == 1) ? ilog2_floor((uint64_t)nb) : gr->logC;
+            step = ilog2_floor((uint64_t)b);
+            if (step < 2) step = 2;
         } else if (b == 6) {
-            pad = (gr->C == 1) ? 4 : gr->logC;
+            p1 = (gr->C == 1) ? 4 : gr->logC;
+            step = 0;
         }
-        // vector runs of V storage elements must not straddle a pad
-        const int lv = ilog2_floor(16 / esize);
-        if (pad < 31 && (gr->mode == kContigVec || gr->mode == kRowVec)) pad = std::max(pad, lv);
+        if (p1 >= 0) {
+            if (p1 < 2) p1 = 2;
+            if (gr->mode == kContigVec || gr->mode == kRowVec) p1 = std::max(p1, lv);
+            int p2 = step ? std::min(31, p1 + step) : 31;
+            int p3 = step ? std::min(31, p1 + 2 * step) : 31;
+            // the extra levels only where the tile has that many digits
+            const int64_t span = gr->tileE;
+            if (p2 < 31 && (int64_t(1) << p2) >= span) p2 = 31;
+            if (p3 < 31 && (int64_t(1) << p3) >= span) p3 = 31;
+            pad = p1 | (p2 << 8) | (p3 << 16);
+        }
     }
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
@@ -203,8 +217,9 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         for (int j = 0; j < k; ++j) wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
         gr->wtotal = (int)wtot;
         gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * tileE) * csize;
+        gr->pad_shift = kNoPad;
     } else {
-        const int64_t phys = tileE + (pad < 31 ? (tileE >> pad) : 0) + 1;
+        const int64_t phys = lds_tile_elems_host(tileE, pad);
         gr->wtotal = 0;
         gr->lds_bytes = (size_t)phys * csize;
     }
@@ -697,3 +712,27 @@ gtt_status filter_impl(gtt_plan_s* p, const void* W, const void* x, int64_t cuto
     return GTT_OK;
 }
 }  // namespace gtt
+
+extern "C" gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, int64_t k, int64_t* idx, void* val,
+                                   void* recon, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !W || !x || !idx || !val) return GTT_ERR_INVALID_VALUE;
+    if (!aligned16(W) || !aligned16(x) || !aligned16(idx) || !aligned16(val) || (recon && !aligned16(recon)) ||
+        (ws && !aligned16(ws)))
+        return GTT_ERR_ALIGNMENT;
+    if (p->kind != PlanKind::Uniform) return GTT_ERR_UNSUPPORTED;
+    if (k < 1 || k > p->N) return GTT_ERR_INVALID_VALUE;
+    size_t f = 0, bw = 0, sv = 0;
+    workspace_sizes(p, &f, &bw, &sv);
+    const size_t E = (size_t)p->total_elems;
+    if (!ws || ws_bytes < f + E * p->esize) return GTT_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* coef = static_cast<char*>(ws) + f;
+    gtt_status st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, coef, nullptr, E, s);
+    if (st != GTT_OK) return st;
+    timing_begin(p, s);
+    if (launch_topk(to_dt(p->dtype), coef, p->N, p->batch, k, idx, val, recon, s) != hipSuccess) return GTT_ERR_HIP;
+    timing_end(p, s, std::string("topk ") + dt_name(p->dtype), (double)E * (double)p->esize * 5.0);
+    if (recon)
+        return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, recon, recon, nullptr, E, s);
+    return GTT_OK;
+}

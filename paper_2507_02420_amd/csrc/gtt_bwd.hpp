@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
     const uint32_t tileE = rows << a.logC;
-    const uint32_t tileP = tileE + (a.pad_shift < 31 ? (tileE >> a.pad_shift) : 0u) + 1u;
+    const uint32_t tileP = lds_tile_elems(tileE, a.pad_shift);
     C* sW = reinterpret_cast<C*>(smem_raw);
     C* sWH = sW + MAXB * MAXB;
     C* acc = sWH + MAXB * MAXB;

@@ -20,7 +20,7 @@ static const char* kDtName[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32
 
 // LDS bytes of the backward kernel for a tile geometry
 size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
-    const int64_t tileP = g.tileE + (g.pad_shift < 31 ? (g.tileE >> g.pad_shift) : 0) + 1;
+    const int64_t tileP = lds_tile_elems_host(g.tileE, g.pad_shift);
     if (g.kind == kKindCMfma) return std::max<size_t>((size_t)(4 * tileP + 1) * csize, 16 * 256 * sizeof(double));
     const int maxb = b <= 8 ? 8 : 16;
     return (size_t)(3 * maxb * maxb + kThreads + 3 * tileP) * csize;

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
     const uint32_t tileE = rows << a.logC;
-    const uint32_t tileP = tileE + (a.pad_shift < 31 ? (tileE >> a.pad_shift) : 0u) + 1u;
+    const uint32_t tileP = lds_tile_elems(tileE, a.pad_shift);
     cf* A = reinterpret_cast<cf*>(smem_raw);
     cf* T1 = A + tileP;
     cf* T2 = T1 + tileP;

@@ -28,6 +28,12 @@ struct CBwdArgs;
 // backward of one digit group, complex64 radix 8 on the matrix cores
 hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
+// k dominant coefficients of every instance (ascending indices, ties to the
+// lower index); with recon != NULL also the zero-filled sparse coefficient
+// vector (the caller then applies the inverse transform in place)
+hipError_t launch_topk(DT dt, const void* coef, int64_t N, int64_t batch, int64_t k, int64_t* idx, void* val,
+                       void* recon, hipStream_t s);
+
 struct RaggedArgs;
 // ragged-batch launch (all phases with grid barriers, or one phase)
 hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s);

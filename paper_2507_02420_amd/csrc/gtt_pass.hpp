@@ -75,11 +75,19 @@ struct BlockAll<C, B, R, R> {
     __device__ __forceinline__ static void run(C (&)[(IPow<B, R>::value)], const C (&)[B * B]) {}
 };
 
-// LDS position of tile element lam: one pad element after every 2^pad_shift
-// elements, which turns the power-of-two strides of the digit fibres into
-// bank-conflict-free odd strides (pad_shift >= 31 disables padding).
+// LDS position of tile element lam.  pad_shift packs three shift amounts
+// (bits 0-7, 8-15, 16-23; 31 = none): one pad element after every 2^p1, 2^p2
+// and 2^p3 elements.  With p1, p2, p3 one digit apart, every power-of-b
+// stride of a digit fibre becomes an odd number of banks, so the lanes of a
+// wave that walk a fibre hit distinct banks.
 __device__ __forceinline__ uint32_t lds_phys(uint32_t lam, int pad_shift) {
-    return lam + (lam >> pad_shift);
+    return lam + (lam >> (pad_shift & 31)) + (lam >> ((pad_shift >> 8) & 31)) + (lam >> ((pad_shift >> 16) & 31));
+}
+
+// LDS elements of a tile of tileE elements under lds_phys
+__device__ __forceinline__ uint32_t lds_tile_elems(uint32_t tileE, int pad_shift) {
+    return tileE + (tileE >> (pad_shift & 31)) + (tileE >> ((pad_shift >> 8) & 31)) +
+           (tileE >> ((pad_shift >> 16) & 31)) + 1u;
 }
 
 // One super-stage: digits j .. j+R-1 of the group, all fibres of the tile.

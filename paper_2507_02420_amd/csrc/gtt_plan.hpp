@@ -11,6 +11,13 @@
 
 namespace gtt {
 
+constexpr int kNoPad = 31 | (31 << 8) | (31 << 16);
+
+// host mirror of the device LDS size of a padded tile
+inline int64_t lds_tile_elems_host(int64_t tileE, int ps) {
+    return tileE + (tileE >> (ps & 31)) + (tileE >> ((ps >> 8) & 31)) + (tileE >> ((ps >> 16) & 31)) + 1;
+}
+
 struct Group {
     int s0 = 0;         // lowest digit of the group
     int k = 0;          // digits in the group
@@ -22,7 +29,7 @@ struct Group {
     int64_t ntiles = 0;
     int64_t tileE = 0;
     int mode = 0;
-    int pad_shift = 31;
+    int pad_shift = kNoPad;  // packed LDS pad shifts (see lds_phys)
     int kind = 0;       // kKindValu / kKindGeneric / kKindMfma
     int wtotal = 0;
     size_t lds_bytes = 0;

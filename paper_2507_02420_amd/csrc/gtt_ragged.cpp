@@ -59,7 +59,7 @@ static void build_worklist(gtt_plan_s* p) {
             g0.tileE = 1;
             g0.elems = 1;
             g0.mode = kContigScalar;
-            g0.pad_shift = 31;
+            g0.pad_shift = kNoPad;
             g0.kind = kKindValu;
             g0.lds_bytes = 16 * p->csize;
             idg.push_back(g0);

@@ -38,7 +38,7 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 
 # every symbol declared in include/gtt.h
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
-           "gtt_backward", "gtt_filter", "gtt_plan_destroy", "gtt_status_string",
+           "gtt_backward", "gtt_filter", "gtt_compress", "gtt_plan_destroy", "gtt_status_string",
            "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_set_tuning",
            "gtt_selftest"]
 
@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_inverse.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     L.gtt_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.gtt_filter.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.gtt_compress.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     L.gtt_plan_destroy.argtypes = [vp]
     L.gtt_status_string.argtypes = [ctypes.c_int]
     L.gtt_status_string.restype = ctypes.c_char_p
@@ -247,6 +248,24 @@ class Plan:
         _check(lib().gtt_filter(self._h, _ptr(W), _ptr(x), int(cutoff), _ptr(lo), _ptr(hi), _ptr(ws), need,
                                 _stream()), "gtt_filter")
         return lo, hi
+
+
+def _compress(self, W: torch.Tensor, x: torch.Tensor, k: int, reconstruct: bool = True):
+    """(idx, val, recon): the k dominant coefficients of every instance
+    (ascending indices) and, optionally, the reconstruction from them."""
+    batch = x.numel() // x.shape[-1]
+    idx = torch.empty(batch, k, dtype=torch.int64, device=x.device)
+    val = torch.empty(batch, k, dtype=x.dtype, device=x.device)
+    recon = torch.empty_like(x) if reconstruct else None
+    fwd, _, _ = self.workspace_size()
+    need = fwd + x.numel() * x.element_size()
+    ws = self._ws(need, x.device)
+    _check(lib().gtt_compress(self._h, _ptr(W), _ptr(x), int(k), _ptr(idx), _ptr(val), _ptr(recon), _ptr(ws), need,
+                              _stream()), "gtt_compress")
+    return idx, val, recon
+
+
+Plan.compress = _compress
 
 
 def set_tuning(b: int, dtype, lds_budget_bytes: int, min_row_bytes: int):
