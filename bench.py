@@ -50,6 +50,9 @@ def time_calls(fn, iters, flush=None):
     for _ in range(iters):
         if flush is not None:
             flush()
+            # let the flush drain first: an event recorded behind a running
+            # kernel can take its timestamp before that kernel ends
+            _sync()
         s, e = _events()
         s.record()
         fn()

@@ -236,11 +236,13 @@ gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len);
  * this call, for radix b and storage dtype (used by the autotuner):
  *   lds_budget_bytes : LDS bytes of one tile (0 = default),
  *   min_row_bytes    : least contiguous bytes per tile row for strided digit
- *                      groups (0 = default).
+ *                      groups (0 = default),
+ *   max_group_digits : most digits fused into one HBM round trip (0 = no
+ *                      limit beyond the tile size).
  * Process-wide; not thread-safe against concurrent gtt_plan calls.
  */
-gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes,
-                          int32_t min_row_bytes);
+gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
+                          int32_t max_group_digits);
 
 /*
  * gtt_selftest -- host-only checks of the index arithmetic (fast division by

@@ -78,19 +78,22 @@ struct TuneEntry {
     int dtype;
     int lds_budget;
     int min_row_bytes;
+    int max_group_digits;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
 
-static void tuning_for(int b, gtt_dtype dt, uint32_t flags, int* budget, int* minrow) {
+static void tuning_for(int b, gtt_dtype dt, uint32_t flags, int* budget, int* minrow, int* maxk) {
     *budget = 0;
     *minrow = 0;
+    *maxk = 0;
     if (flags & GTT_FLAG_NO_TUNE) return;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& e : g_tune)
         if (e.b == b && e.dtype == (int)dt) {
             *budget = e.lds_budget;
             *minrow = e.min_row_bytes;
+            *maxk = e.max_group_digits;
         }
 }
 
@@ -109,12 +112,13 @@ static uint64_t pow2_floor(uint64_t v) { return v ? (uint64_t(1) << ilog2_floor(
 // Try to split the n digits into exactly R groups; group 0 contiguous, the
 // others strided with C columns.  Returns false if infeasible.
 static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t Gmax, int64_t cmin_elems,
-                      std::vector<int>* ks) {
+                      std::vector<int>* ks, int maxk) {
     const int n = (int)rad.size();
+    if (maxk <= 0) maxk = 64;
     // group 0: as many digits as fit
     int k0 = 0;
     int64_t g = 1;
-    while (k0 < n && g * rad[k0] <= std::min(T, Gmax)) g *= rad[k0++];
+    while (k0 < n && k0 < maxk && g * rad[k0] <= std::min(T, Gmax)) g *= rad[k0++];
     if (k0 == 0) return false;
     if (R == 1) {
         if (k0 < n) return false;
@@ -129,7 +133,8 @@ static bool try_split(const std::vector<int>& rad, int R, int64_t T, int64_t Gma
     for (int r = 1; r < R && s < n; ++r) {
         int k = 0;
         int64_t G = 1;
-        while (s + k < n && G * rad[s + k] * cmin_elems <= T && G * rad[s + k] <= Gmax) G *= rad[s + k++];
+        while (s + k < n && k < maxk && G * rad[s + k] * cmin_elems <= T && G * rad[s + k] <= Gmax)
+            G *= rad[s + k++];
         if (k == 0) return false;
         out.push_back(k);
         s += k;
@@ -243,8 +248,8 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16)) kind = kKindMfma;
     if (uniform && b0 == 8 && dt == GTT_C64 && !ragged) kind = kKindCMfma;
     const bool small_b = kind != kKindGeneric;
-    int tb = 0, tr = 0;
-    tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr);
+    int tb = 0, tr = 0, tk = 0;
+    tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr, &tk);
     std::vector<int64_t> budgets;
     if (tb > 0) {
         budgets.push_back(tb);
@@ -264,7 +269,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                 std::vector<int> ks;
                 // a group's positions must fit three times in LDS for backward
                 const int64_t Gmax = (int64_t)(40 * 1024) / (int64_t)cs;
-                if (!try_split(rad, R, T, Gmax, cmin, &ks)) continue;
+                if (!try_split(rad, R, T, Gmax, cmin, &ks, tk)) continue;
                 int s = 0;
                 for (int k : ks) {
                     Group g;
@@ -278,9 +283,13 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                     // tiles of at most 8192 elements, others take the
                     // runtime-radix backward
                     bwd_groups->clear();
-                    const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
                     for (const Group& fg : *groups) {
                         Group g;
+                        // strided matrix-core groups of <= 2 digits: 16 KiB
+                        // tiles, so that two work-groups share a compute unit
+                        const int64_t Tb = (int64_t)((kind == kKindCMfma && fg.k <= 2 && fg.s0 > 0) ? 16 * 1024
+                                                                                                  : 40 * 1024) /
+                                           (int64_t)cs;
                         fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
                         if (g.kind == kKindCMfma &&
                             (g.k > 4 || g.tileE > 8192 || (g.mode != kContigVec && g.mode != kRowVec)))
@@ -597,17 +606,20 @@ gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len) {
     return GTT_OK;
 }
 
-gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes) {
+gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
+                          int32_t max_group_digits) {
     if (b < 2 || !valid_dtype((int)dtype)) return GTT_ERR_INVALID_VALUE;
-    if (lds_budget_bytes < 0 || lds_budget_bytes > 160 * 1024 || min_row_bytes < 0) return GTT_ERR_INVALID_VALUE;
+    if (lds_budget_bytes < 0 || lds_budget_bytes > 160 * 1024 || min_row_bytes < 0 || max_group_digits < 0)
+        return GTT_ERR_INVALID_VALUE;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& e : g_tune)
         if (e.b == b && e.dtype == (int)dtype) {
             e.lds_budget = lds_budget_bytes;
             e.min_row_bytes = min_row_bytes;
+            e.max_group_digits = max_group_digits;
             return GTT_OK;
         }
-    g_tune.push_back(TuneEntry{b, (int)dtype, lds_budget_bytes, min_row_bytes});
+    g_tune.push_back(TuneEntry{b, (int)dtype, lds_budget_bytes, min_row_bytes, max_group_digits});
     return GTT_OK;
 }
 

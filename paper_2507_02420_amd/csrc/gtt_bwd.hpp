@@ -148,7 +148,8 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
             digit_apply<C, MAXB>(Ct, sWH, a, b, s, rows);
             __syncthreads();
         }
-        tile_store<T, C>(Ct, a, static_cast<T*>(a.out), t, rows);
+        // out is null for the first digit group when only gW is wanted
+        if (a.out) tile_store<T, C>(Ct, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
     C* part = static_cast<C*>(ba.partials) + (size_t)blockIdx.x * bb;

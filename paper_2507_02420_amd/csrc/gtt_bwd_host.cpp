@@ -21,7 +21,8 @@ static const char* kDtName[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32
 // LDS bytes of the backward kernel for a tile geometry
 size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
     const int64_t tileP = lds_tile_elems_host(g.tileE, g.pad_shift);
-    if (g.kind == kKindCMfma) return std::max<size_t>((size_t)(4 * tileP + 1) * csize, 16 * 256 * sizeof(double));
+    if (g.kind == kKindCMfma)
+        return std::max<size_t>((size_t)((g.k >= 3 ? 4 : 3) * tileP + 1) * csize, 16 * 256 * sizeof(double));
     const int maxb = b <= 8 ? 8 : 16;
     return (size_t)(3 * maxb * maxb + kThreads + 3 * tileP) * csize;
 }
@@ -29,7 +30,14 @@ size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
 // work-groups of one backward launch (fixed per plan: determinism of gW);
 // the matrix-core kernel is one 1024-thread work-group per compute unit
 static unsigned bwd_grid(const Group& g) {
-    return (unsigned)std::min<int64_t>(g.ntiles, g.kind == kKindCMfma ? 256 : 2048);
+    if (g.kind == kKindCMfma) {
+        // 1024-thread work-groups: at most two per compute unit (32 waves),
+        // fewer when their LDS does not fit twice
+        const size_t lds = bwd_lds_bytes(g, 8, 8);
+        const int per_cu = lds * 2 <= 160 * 1024 ? 2 : 1;
+        return (unsigned)std::min<int64_t>(g.ntiles, 256 * per_cu);
+    }
+    return (unsigned)std::min<int64_t>(g.ntiles, 2048);
 }
 
 size_t bwd_partials_elems(const std::vector<Group>& bg, int b) {
@@ -58,7 +66,9 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
         fill_pass_args(&ba.p, G, rad, wofs, N);
         ba.p.W = W;
         ba.p.in = (g == 0) ? x : (const void*)(saved + (size_t)(g - 1) * elems * es);
-        void* c_in = (g == 0 && gx) ? gx : (void*)cbuf;
+        // the first group's cotangent is gx itself; with gx null it is not
+        // stored at all (no buffer is reserved for it)
+        void* c_in = (g == 0) ? gx : (void*)cbuf;
         ba.p.out = c_in;
         ba.c_out = c_out;
         ba.partials = part;

@@ -50,14 +50,14 @@ __device__ __forceinline__ void load_cfrag8(CFrag8& f, const cf* __restrict__ W,
     for (int kk = 0; kk < 4; ++kk) f.a[kk] = creal_block(W, adjoint, lane & 15, 4 * kk + (lane >> 4));
 }
 
+// tile position of element 0 of fibre f of digit j (radix 8: b^j = 2^(3j))
 __device__ __forceinline__ uint32_t fibre_base(const PassArgs& a, int j, uint32_t f) {
     const uint32_t Cm = (1u << a.logC) - 1u;
-    const uint32_t bj = (uint32_t)a.bpow[j];
     const uint32_t c = f & Cm;
     const uint32_t f1 = f >> a.logC;
-    const uint32_t Q = fdiv(f1, a.divb[j]);
-    const uint32_t glo = f1 - Q * bj;
-    return ((Q * (uint32_t)a.bpow[j + 1] + glo) << a.logC) | c;
+    const uint32_t lo = f1 & ((1u << (3 * j)) - 1u);
+    const uint32_t Q = f1 >> (3 * j);
+    return ((Q << (3 * j + 3)) + lo) << a.logC | c;
 }
 
 // W (fragments f) along digit j of every fibre of the complex tile: reads
@@ -201,8 +201,8 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
     const uint32_t tileP = lds_tile_elems(tileE, a.pad_shift);
     cf* A = reinterpret_cast<cf*>(smem_raw);
     cf* T1 = A + tileP;
-    cf* T2 = T1 + tileP;
-    cf* Ct = T2 + tileP;
+    cf* Ct = T1 + tileP;
+    cf* T2 = Ct + tileP;  // used only when the group has three or more digits
     // 16 waves x 256 doubles for the final reduction, reusing the tiles' LDS
     double* red = reinterpret_cast<double*>(smem_raw);
     CFrag8 fw, fh;
@@ -263,8 +263,11 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
             adj(1);
         }
         gw(A, 0);
-        adj(0);
-        bwd_store(Ct, a, static_cast<cf*>(a.out), t, tileE);
+        // out is null for the first digit group when only gW is wanted
+        if (a.out) {
+            adj(0);
+            bwd_store(Ct, a, static_cast<cf*>(a.out), t, tileE);
+        }
         __syncthreads();
     }
     // reduce the waves' 16 x 16 blocks in a fixed order, then form the

@@ -205,9 +205,9 @@ gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int
 void destroy_ragged(gtt_plan_s* p) {
     timing_release(p);
     if (p->rs) {
-        if (p->rs->d_desc) hipFree(p->rs->d_desc);
-        if (p->rs->d_items) hipFree(p->rs->d_items);
-        if (p->rs->d_bar) hipFree(p->rs->d_bar);
+        if (p->rs->d_desc) (void)hipFree(p->rs->d_desc);
+        if (p->rs->d_items) (void)hipFree(p->rs->d_items);
+        if (p->rs->d_bar) (void)hipFree(p->rs->d_bar);
     }
     delete p->rs;
     p->rs = nullptr;
@@ -341,24 +341,24 @@ static thread_local hipEvent_t t_open = nullptr;
 void timing_begin(gtt_plan_s* p, hipStream_t s) {
     if (!p || !p->timing.enabled) return;
     t_open = pool_get(p->timing);
-    if (t_open) hipEventRecord(t_open, s);
+    if (t_open) (void)hipEventRecord(t_open, s);
 }
 
 void timing_end(gtt_plan_s* p, hipStream_t s, const std::string& name, double bytes) {
     if (!p || !p->timing.enabled || !t_open) return;
     hipEvent_t e = pool_get(p->timing);
     if (!e) return;
-    hipEventRecord(e, s);
+    (void)hipEventRecord(e, s);
     p->timing.pending.push_back(TimedLaunch{name, t_open, e, bytes});
     t_open = nullptr;
 }
 
 void timing_release(gtt_plan_s* p) {
     for (auto& tl : p->timing.pending) {
-        hipEventDestroy(tl.start);
-        hipEventDestroy(tl.stop);
+        (void)hipEventDestroy(tl.start);
+        (void)hipEventDestroy(tl.stop);
     }
-    for (auto e : p->timing.pool) hipEventDestroy(e);
+    for (auto e : p->timing.pool) (void)hipEventDestroy(e);
     p->timing.pending.clear();
     p->timing.pool.clear();
 }
@@ -417,6 +417,11 @@ std::string describe_plan(const gtt_plan_s* p) {
         for (size_t i = 0; i < p->groups.size(); ++i) {
             if (i) s += ",";
             s += grp(p->groups[i]);
+        }
+        s += "],\"bwd_groups\":[";
+        for (size_t i = 0; i < p->bwd_groups.size(); ++i) {
+            if (i) s += ",";
+            s += grp(p->bwd_groups[i]);
         }
         s += "]";
     } else {

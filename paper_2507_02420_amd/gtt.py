@@ -77,7 +77,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.gtt_plan_timing.argtypes = [vp, i32]
     L.gtt_plan_timing_read.argtypes = [vp, ctypes.c_char_p, sz]
-    L.gtt_set_tuning.argtypes = [i32, ctypes.c_int, i32, i32]
+    L.gtt_set_tuning.argtypes = [i32, ctypes.c_int, i32, i32, i32]
     L.gtt_selftest.argtypes = []
     for name in EXPORTS:
         if name != "gtt_status_string":
@@ -106,7 +106,7 @@ def load_tuning(path: Optional[str] = None) -> int:
     n = 0
     for e in table.get("entries", []):
         st = _lib.gtt_set_tuning(int(e["b"]), _NAME_TO_GTT[e["dtype"]], int(e["lds_budget"]),
-                                 int(e["min_row_bytes"]))
+                                 int(e["min_row_bytes"]), int(e.get("max_group_digits", 0)))
         n += st == OK
     return n
 
@@ -117,7 +117,19 @@ def _check(st: int, where: str):
 
 
 def _ptr(t: Optional[torch.Tensor]):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """Device address of a dense tensor.  The library reads memory in plain
+    row-major order, so a strided view (a transpose, the column-major result
+    of a LAPACK-backed op) or a host tensor is refused rather than misread."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"tensor of shape {tuple(t.shape)} is not on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"tensor of shape {tuple(t.shape)} and strides {t.stride()} is not contiguous; "
+                         "call .contiguous() first")
+    if t.is_conj() or t.is_neg():
+        raise ValueError("lazy conjugate/negative view: call .resolve_conj() / .resolve_neg() first")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream():
@@ -268,9 +280,9 @@ def _compress(self, W: torch.Tensor, x: torch.Tensor, k: int, reconstruct: bool 
 Plan.compress = _compress
 
 
-def set_tuning(b: int, dtype, lds_budget_bytes: int, min_row_bytes: int):
-    _check(lib().gtt_set_tuning(int(b), TORCH_TO_GTT[dtype], int(lds_budget_bytes), int(min_row_bytes)),
-           "gtt_set_tuning")
+def set_tuning(b: int, dtype, lds_budget_bytes: int, min_row_bytes: int, max_group_digits: int = 0):
+    _check(lib().gtt_set_tuning(int(b), TORCH_TO_GTT[dtype], int(lds_budget_bytes), int(min_row_bytes),
+                                int(max_group_digits)), "gtt_set_tuning")
 
 
 def selftest() -> int:

@@ -38,6 +38,7 @@ WORKLOADS = [
 ]
 BUDGETS = [16384, 24576, 32768, 49152, 65536]
 MIN_ROWS = [64, 128, 256, 512]
+MAX_DIGITS = [0, 2, 3, 4, 5, 6, 7]
 
 
 def _time_forward(plan, W, x, y, iters=10, flush=None):
@@ -60,7 +61,7 @@ def _time_forward(plan, W, x, y, iters=10, flush=None):
     return ts[len(ts) // 2]
 
 
-def tune_one(b, n, batch, dtype, budgets=BUDGETS, min_rows=MIN_ROWS, log=print):
+def tune_one(b, n, batch, dtype, budgets=BUDGETS, min_rows=MIN_ROWS, max_digits=MAX_DIGITS, log=print):
     dev = torch.device("cuda")
     N = b ** n
     if dtype.is_complex:
@@ -76,27 +77,30 @@ def tune_one(b, n, batch, dtype, budgets=BUDGETS, min_rows=MIN_ROWS, log=print):
     scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev) if small else None
     flush = (lambda: scratch.zero_()) if small else None
     best = None
-    results = []
+    seen = set()
     for bud in budgets:
         for mr in min_rows:
-            G.set_tuning(b, dtype, bud, mr)
-            try:
-                plan = G.Plan(b, n, batch, dtype)
-            except G.GTTError:
-                continue
-            desc = json.dumps([(g["k"], g["C"], g["P"]) for g in plan.describe()["groups"]])
-            ms = _time_forward(plan, W, x, y, flush=flush)
-            results.append((ms, bud, mr, desc))
-            if best is None or ms < best[0]:
-                best = (ms, bud, mr, desc)
-    G.set_tuning(b, dtype, 0, 0)
-    G.set_tuning(b, dtype, 0, 0)
+            for mk in max_digits:
+                G.set_tuning(b, dtype, bud, mr, mk)
+                try:
+                    plan = G.Plan(b, n, batch, dtype)
+                except G.GTTError:
+                    continue
+                desc = json.dumps([(g["k"], g["C"], g["P"]) for g in plan.describe()["groups"]])
+                if desc in seen:      # same tiling as an earlier grid point
+                    continue
+                seen.add(desc)
+                ms = _time_forward(plan, W, x, y, flush=flush)
+                if best is None or ms < best[0]:
+                    best = (ms, bud, mr, desc, mk)
+    G.set_tuning(b, dtype, 0, 0, 0)
     base_plan = G.Plan(b, n, batch, dtype, flags=G.FLAG_NO_TUNE)
     base = _time_forward(base_plan, W, x, y, flush=flush)
     log(f"b={b} n={n} batch={batch} {DT_NAMES[dtype]}: heuristic {base:.4f} ms, best {best[0]:.4f} ms "
         f"(budget {best[1]}, min row {best[2]}, groups {best[3]})")
     return {"b": b, "n": n, "batch": batch, "dtype": DT_NAMES[dtype], "lds_budget": best[1],
-            "min_row_bytes": best[2], "ms": best[0], "heuristic_ms": base, "groups": best[3]}
+            "min_row_bytes": best[2], "max_group_digits": best[4], "ms": best[0], "heuristic_ms": base,
+            "groups": best[3]}
 
 
 def main():
@@ -106,9 +110,10 @@ def main():
     args = ap.parse_args()
     budgets = [16384, 32768, 65536] if args.quick else BUDGETS
     rows = [128, 256] if args.quick else MIN_ROWS
+    maxd = [0, 3] if args.quick else MAX_DIGITS
     table = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "entries": []}
     for (b, n, batch, dt) in WORKLOADS:
-        e = tune_one(b, n, batch, dt, budgets, rows, log=lambda m: print(m, flush=True))
+        e = tune_one(b, n, batch, dt, budgets, rows, maxd, log=lambda m: print(m, flush=True))
         # keep an override only when it beats the built-in heuristic
         if e["ms"] < 0.98 * e["heuristic_ms"]:
             table["entries"].append(e)

@@ -42,7 +42,8 @@ def riemannian_direction(W: torch.Tensor, gW: torch.Tensor) -> torch.Tensor:
 
 def cayley_step(W: torch.Tensor, A: torch.Tensor, t: float) -> torch.Tensor:
     I = torch.eye(W.shape[0], dtype=W.dtype, device=W.device)
-    return torch.linalg.solve(I - 0.5 * t * A, (I + 0.5 * t * A) @ W)
+    # linalg.solve returns a column-major matrix; the transform reads W row-major
+    return torch.linalg.solve(I - 0.5 * t * A, (I + 0.5 * t * A) @ W).contiguous()
 
 
 def tune(x: torch.Tensor, W0: torch.Tensor, b: int, n: int, k: int, steps: int = 50, lr: float = 0.5,

@@ -88,8 +88,20 @@ def test_call_validation_before_any_hip_call():
 
 def test_tuning_validation():
     L = G.lib()
-    assert L.gtt_set_tuning(1, G.F32, 0, 0) == 1
-    assert L.gtt_set_tuning(2, G.F32, 200 * 1024, 0) == 1
+    assert L.gtt_set_tuning(1, G.F32, 0, 0, 0) == 1
+    assert L.gtt_set_tuning(2, G.F32, 200 * 1024, 0, 0) == 1
+    assert L.gtt_set_tuning(2, G.F32, 0, 0, -1) == 1
+
+
+def test_tuning_changes_split_and_not_results():
+    G.set_tuning(8, torch.complex64, 0, 0, 3)
+    try:
+        ks = [g["k"] for g in G.Plan(8, 6, 256, torch.complex64).describe()["groups"]]
+    finally:
+        G.set_tuning(8, torch.complex64, 0, 0, 0)
+    assert ks == [3, 3]
+    ks = [g["k"] for g in G.Plan(8, 6, 256, torch.complex64).describe()["groups"]]
+    assert ks == [4, 2]
 
 
 def _describe(b, n, batch, dtype):
@@ -124,3 +136,9 @@ def test_mixed_plan_and_describe():
     d = p.describe()
     assert d["kind"] == "mixed"
     assert sum(g["k"] for g in d["groups"]) == 4
+
+
+def test_binding_refuses_host_tensors():
+    import pytest
+    with pytest.raises(ValueError):
+        G._ptr(torch.zeros(4))

@@ -84,6 +84,24 @@ def test_backward_only_gw_and_only_gx_and_inplace():
     assert torch.equal(gW2, gW)
 
 
+@pytest.mark.parametrize("b,n,batch,dtype", [(4, 6, 4, torch.float32), (8, 3, 2, torch.complex64),
+                                             (8, 4, 2, torch.complex64), (2, 10, 2, torch.float64)], ids=str)
+def test_backward_gw_only_single_group(b, n, batch, dtype):
+    # one digit group and no gx: the first group's cotangent is not stored;
+    # x and gy must come back untouched
+    say(f"backward gW only b={b} n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=97 + b + n)
+    g = torch.from_numpy(gaussian((batch, b ** n), seed=98, complex_=dtype.is_complex)).to(dtype).cuda()
+    plan = G.Plan(b, n, batch, dtype)
+    assert len(plan.describe()["groups"]) == 1
+    x0, g0 = x.clone(), g.clone()
+    _, gW = plan.backward(W, x, g, want_gx=False)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x0) and torch.equal(g, g0)
+    _, rgW = O.grad(W64, x64, host64(g), n)
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+
+
 def test_backward_deterministic():
     b, n, batch, dtype = 8, 6, 8, torch.complex64
     x, W, _, _ = make_inputs(b, n, batch, dtype, seed=93)

@@ -168,3 +168,15 @@ def test_mfma_radix_16_32(b, n, batch, dtype):
     say(f"  rel err {err:.3e}")
     assert err < 1e-2
     assert rel_err(host64(xi), x64) < 2e-2
+
+
+def test_strided_or_conjugate_views_are_refused():
+    b, n = 4, 3
+    x, W, _, _ = make_inputs(b, n, 2, torch.complex64, seed=5)
+    plan = G.Plan(b, n, 2, torch.complex64)
+    with pytest.raises(ValueError):
+        plan.forward(W.t(), x)
+    with pytest.raises(ValueError):
+        plan.forward(W.conj(), x)
+    with pytest.raises(ValueError):
+        plan.forward(W, x.t().contiguous().t())      # column-major (2, N)
