@@ -23,6 +23,8 @@
 // total is rounded to FP32 once.
 #pragma once
 
+#include <type_traits>
+
 #include "gtt_args.hpp"
 #include "gtt_pass.hpp"
 #include "gtt_types.hpp"
@@ -149,26 +151,29 @@ __global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_pass_kernel(PassArgs a
 constexpr int kBwdThreads = 1024;
 constexpr int kBwdVec = 4;  // 16-byte vectors per thread and buffer (tile <= 8192 c64)
 
-__device__ __forceinline__ void bwd_fetch(uint4 (&buf)[kBwdVec], const PassArgs& a, const cf* __restrict__ in,
+// NV 16-byte vectors per thread and buffer; FULL: the tile has exactly
+// NV * kBwdThreads vectors (no bounds test)
+template <int NV = kBwdVec, bool FULL = false>
+__device__ __forceinline__ void bwd_fetch(uint4 (&buf)[NV], const PassArgs& a, const cf* __restrict__ in,
                                           int64_t t, uint32_t tileE) {
     const bool contig = a.mode == kContigVec;
     const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
     const int64_t l = contig ? 0 : t - hb * a.L;
     const uint32_t nvec = tileE / 2;
 #pragma unroll
-    for (int v = 0; v < kBwdVec; ++v) {
+    for (int v = 0; v < NV; ++v) {
         const uint32_t i = threadIdx.x + v * kBwdThreads;
-        if (i < nvec) buf[v] = *reinterpret_cast<const uint4*>(in + vec_offset<cf>(a, t, i, hb, l, tileE));
+        if (FULL || i < nvec) buf[v] = *reinterpret_cast<const uint4*>(in + vec_offset<cf>(a, t, i, hb, l, tileE));
     }
 }
 
-__device__ __forceinline__ void bwd_commit(cf* lds, const uint4 (&buf)[kBwdVec], const PassArgs& a,
-                                           uint32_t tileE) {
+template <int NV = kBwdVec, bool FULL = false>
+__device__ __forceinline__ void bwd_commit(cf* lds, const uint4 (&buf)[NV], const PassArgs& a, uint32_t tileE) {
     const uint32_t nvec = tileE / 2;
 #pragma unroll
-    for (int v = 0; v < kBwdVec; ++v) {
+    for (int v = 0; v < NV; ++v) {
         const uint32_t i = threadIdx.x + v * kBwdThreads;
-        if (i < nvec) {
+        if (FULL || i < nvec) {
             cf vals[2];
             *reinterpret_cast<uint4*>(vals) = buf[v];
             const uint32_t ph = lds_phys(i * 2, a.pad_shift);
@@ -273,6 +278,190 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
     // reduce the waves' 16 x 16 blocks in a fixed order, then form the
     // complex gradient
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = Md[v];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int r = threadIdx.x >> 3, q = threadIdx.x & 7;
+        auto Mv = [&](int mm, int nn) {
+            double s = 0.0;
+            for (int w = 0; w < kBwdThreads / 64; ++w) s += red[w * 256 + mm * 16 + nn];
+            return s;
+        };
+        cf g;
+        g.re = (float)(Mv(2 * r, 2 * q) + Mv(2 * r + 1, 2 * q + 1));
+        g.im = (float)(Mv(2 * r + 1, 2 * q) - Mv(2 * r, 2 * q + 1));
+        static_cast<cf*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Backward of one digit group with per-lane LDS addresses computed once per
+// launch (tiles of 2048 * NI elements, K <= 4 digits).
+//
+// A tile position is a bit string: column bits (logC), three bits per digit,
+// then row bits.  The LDS padding adds x >> p for a few shifts p, and a shift
+// of a sum of numbers with disjoint bits is the sum of their shifts, so
+// phys(u | v) = phys(u) + phys(v) when u & v == 0.  Element e of fibre f of
+// digit j sits at dep_j(f) | e << h_j, where dep_j inserts three zero bits at
+// h_j = logC + 3 j; dep_j is additive over disjoint bits too.  Splitting the
+// fibre index into a lane part and a loop part with disjoint bits therefore
+// splits every LDS address into a per-lane base (registers, once per launch)
+// plus an offset that is the same for the whole work-group.
+//
+// Fibres of a digit (F = 256 NI) are split so that wave w owns
+// 256 it + 16 w + i (it < NI, i < 16).  In the pass, lane (q, i) handles
+// elements 2q, 2q+1 of fibre i of step it.  In the gradient sums, MFMA t
+// (t < 4 NI) takes fibre 256 (t / 4) + 16 w + 4 (t % 4) + k on lane group k,
+// so a wave reads for the sums exactly the fibres that its own pass rewrites
+// next: the sums and the adjoint pass of a digit need no barrier in between.
+__device__ __forceinline__ uint32_t digit_deposit(uint32_t v, uint32_t h) {
+    return ((v >> h) << (h + 3)) | (v & ((1u << h) - 1u));
+}
+
+template <int V>
+using IntC = std::integral_constant<int, V>;
+
+template <int K, int NI>
+__global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
+    static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
+    const PassArgs& a = ba.p;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr uint32_t tileE = 2048u * NI;
+    const int pad = a.pad_shift;
+    const uint32_t tileB = lds_tile_elems(tileE, pad) * (uint32_t)sizeof(cf);
+    unsigned char* Ab = smem_raw;
+    unsigned char* T1b = Ab + tileB;
+    unsigned char* Cb = T1b + tileB;
+    unsigned char* T2b = Cb + tileB;  // K >= 3 only
+    double* red = reinterpret_cast<double*>(smem_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
+    // per-lane byte offsets: pass elements 2q and 2q+1, gradient element
+    uint32_t P0[K], P1[K], GB[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t h = (uint32_t)a.logC + 3u * j;
+        const uint32_t L0 = digit_deposit(16u * wave + lo, h) | ((2u * hi) << h);
+        P0[j] = lds_phys(L0, pad) * 8u;
+        P1[j] = lds_phys(L0 | (1u << h), pad) * 8u;
+        const uint32_t GL = digit_deposit(16u * wave + hi, h) | ((lo >> 1) << h);
+        GB[j] = lds_phys(GL, pad) * 8u + 4u * (lo & 1u);
+    }
+    // uniform offsets of pass step it and gradient MFMA t
+    auto soff = [&](int j, int it) {
+        return lds_phys(digit_deposit(256u * it, (uint32_t)a.logC + 3u * j), pad) * 8u;
+    };
+    auto goff = [&](int j, int t) {
+        return lds_phys(digit_deposit(256u * (t >> 2) + 4u * (t & 3), (uint32_t)a.logC + 3u * j), pad) * 8u;
+    };
+    CFrag8 fw, fh;
+    load_cfrag8(fw, static_cast<const cf*>(a.W), 0);
+    load_cfrag8(fh, static_cast<const cf*>(a.W), 1);
+    double Md[4] = {0.0, 0.0, 0.0, 0.0};
+    const cf* xin = static_cast<const cf*>(a.in);
+    const cf* cin = static_cast<const cf*>(ba.c_out);
+
+    // W (fragments fr) along digit J: src -> dst (in place when equal)
+    auto pass = [&](auto J, const unsigned char* src, unsigned char* dst, const CFrag8& fr) {
+        constexpr int j = decltype(J)::value;
+        cf x0[NI], x1[NI];
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const uint32_t so = soff(j, it);
+            x0[it] = *reinterpret_cast<const cf*>(src + P0[j] + so);
+            x1[it] = *reinterpret_cast<const cf*>(src + P1[j] + so);
+        }
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0[it].re, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], x0[it].im, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1[it].re, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1[it].im, acc, 0, 0, 0);
+            const uint32_t so = soff(j, it);
+            *reinterpret_cast<cf*>(dst + P0[j] + so) = cf{acc[0], acc[1]};
+            *reinterpret_cast<cf*>(dst + P1[j] + so) = cf{acc[2], acc[3]};
+        }
+    };
+    // gradient sums of digit J (cotangent in Ct, activation act), then the
+    // adjoint pass on Ct along J (skipped when adj is false)
+    auto fused = [&](auto J, const unsigned char* act, bool adj) {
+        constexpr int j = decltype(J)::value;
+        f32x4_c M = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            float cv[4], av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t o = GB[j] + goff(j, 4 * it + u);
+                cv[u] = *reinterpret_cast<const float*>(Cb + o);
+                av[u] = *reinterpret_cast<const float*>(act + o);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[u], av[u], M, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
+        // the pass rewrites only fibres this wave has just read
+        if (adj) pass(J, Cb, Cb, fh);
+    };
+
+    uint4 pa[NI], pc[NI];
+    int64_t t = blockIdx.x;
+    if (t < a.ntiles) {
+        bwd_fetch<NI, true>(pa, a, xin, t, tileE);
+        bwd_fetch<NI, true>(pc, a, cin, t, tileE);
+    }
+    const bool want_gx = a.out != nullptr;
+    for (; t < a.ntiles; t += gridDim.x) {
+        // keep base + offset sums inside the loop: hoisted, they would hold
+        // one register per (digit, step) and spill
+#pragma unroll
+        for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]), "+v"(GB[j]));
+        bwd_commit<NI, true>(reinterpret_cast<cf*>(Ab), pa, a, tileE);
+        bwd_commit<NI, true>(reinterpret_cast<cf*>(Cb), pc, a, tileE);
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        if (tn < a.ntiles) {  // in flight while this tile is processed
+            bwd_fetch<NI, true>(pa, a, xin, tn, tileE);
+            bwd_fetch<NI, true>(pc, a, cin, tn, tileE);
+        }
+        if constexpr (K >= 2) {
+            pass(IntC<0>{}, Ab, T1b, fw);  // a_1
+            __syncthreads();
+        }
+        if constexpr (K >= 3) {
+            pass(IntC<1>{}, T1b, T2b, fw);  // a_2
+            __syncthreads();
+        }
+        if constexpr (K == 4) {
+            pass(IntC<2>{}, T2b, T2b, fw);  // a_3
+            __syncthreads();
+            fused(IntC<3>{}, T2b, true);
+            __syncthreads();
+            pass(IntC<1>{}, T1b, T2b, fw);  // a_2 again
+            __syncthreads();
+        }
+        if constexpr (K >= 3) {
+            fused(IntC<2>{}, T2b, true);
+            __syncthreads();
+        }
+        if constexpr (K >= 2) {
+            fused(IntC<1>{}, T1b, true);
+            __syncthreads();
+        }
+        // out is null for the first digit group when only gW is wanted
+        fused(IntC<0>{}, Ab, want_gx);
+        __syncthreads();
+        if (want_gx) {
+            bwd_store(reinterpret_cast<const cf*>(Cb), a, static_cast<cf*>(a.out), t, tileE);
+            __syncthreads();
+        }
+    }
+    // reduce the waves' 16 x 16 blocks in a fixed order, then form the
+    // complex gradient
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = Md[v];
     __syncthreads();

@@ -27,6 +27,9 @@ hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, vo
 struct CBwdArgs;
 // backward of one digit group, complex64 radix 8 on the matrix cores
 hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
+// the same on tiles of 2048 * ni elements (ni = 1, 2) with k <= 4 digits,
+// LDS addresses precomputed per lane
+hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 // k dominant coefficients of every instance (ascending indices, ties to the
 // lower index); with recon != NULL also the zero-filled sparse coefficient

@@ -102,6 +102,25 @@ def test_backward_gw_only_single_group(b, n, batch, dtype):
     assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
 
 
+# complex radix-8 shapes covering every (digits, tile) variant of the
+# matrix-core backward with per-lane addresses: 1-4 digits, 2048 / 4096
+# element tiles, contiguous and strided (C = 8, 32, 256) groups
+@pytest.mark.parametrize("n,batch", [(1, 512), (2, 64), (3, 4), (3, 8), (4, 2), (5, 2), (6, 8), (7, 1)])
+@pytest.mark.parametrize("want_gx", [True, False])
+def test_backward_c64_radix8_tiles(n, batch, want_gx):
+    b, dtype = 8, torch.complex64
+    say(f"backward c64 b=8 n={n} batch={batch} want_gx={want_gx}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=700 + n)
+    g = torch.from_numpy(gaussian((batch, b ** n), seed=800 + n, complex_=True)).to(dtype).cuda()
+    plan = G.Plan(b, n, batch, dtype)
+    gx, gW = plan.backward(W, x, g, want_gx=want_gx)
+    torch.cuda.synchronize()
+    rgx, rgW = O.grad(W64, x64, host64(g), n)
+    if want_gx:
+        assert rel_err(host64(gx), rgx) < TOL[dtype]
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+
+
 def test_backward_deterministic():
     b, n, batch, dtype = 8, 6, 8, torch.complex64
     x, W, _, _ = make_inputs(b, n, batch, dtype, seed=93)
