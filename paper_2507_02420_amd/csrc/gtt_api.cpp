@@ -364,9 +364,21 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     // occupancy than the overlap gains)
     a.pf = 0;
     const int64_t gmax = (int64_t)0x7fffffff;
-    const unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, gmax);
+    unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, gmax);
+    // complex radix-8 tiles of 2048 / 4096 elements: the matrix-core pass
+    // with per-lane addresses, two 1024-thread work-groups per compute unit
+    // looping over tiles with a register prefetch
+    const int fast_ni = (g.kind == kKindCMfma && cut < 0 && g.k <= 4 && (g.mode == kContigVec || g.mode == kRowVec))
+                            ? (g.tileE == 2048 ? 1 : g.tileE == 4096 ? 2 : 0)
+                            : 0;
     timing_begin(tp, s);
-    hipError_t e = launch_pass(to_dt(dt), rad[g.s0], g.kind, a, grid, g.lds_bytes, s);
+    hipError_t e;
+    if (fast_ni) {
+        grid = (unsigned)std::min<int64_t>(g.ntiles, 2 * 256);
+        e = launch_cpass8_fast(g.k, fast_ni, a, grid, g.lds_bytes, s);
+    } else {
+        e = launch_pass(to_dt(dt), rad[g.s0], g.kind, a, grid, g.lds_bytes, s);
+    }
     if (tp && tp->timing.enabled) {
         char nm[128];
         std::snprintf(nm, sizeof nm, "pass %s b=%d%s s0=%d k=%d%s", dt_name(dt), rad[g.s0],

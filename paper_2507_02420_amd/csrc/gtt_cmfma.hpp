@@ -323,6 +323,82 @@ __device__ __forceinline__ uint32_t digit_deposit(uint32_t v, uint32_t h) {
 template <int V>
 using IntC = std::integral_constant<int, V>;
 
+// W (fragments fr) along the digit whose three bits start at h, over all
+// fibres of a 2048 * NI element tile, 1024 threads: lane (q, i) of wave w
+// takes elements 2q, 2q+1 of fibre 256 it + 16 w + i at byte offsets
+// p0, p1 (+ the step's uniform offset).  src -> dst, in place when equal.
+template <int NI>
+__device__ __forceinline__ void cpass8(const unsigned char* src, unsigned char* dst, uint32_t p0, uint32_t p1,
+                                       uint32_t h, int pad, const CFrag8& fr) {
+    cf x0[NI], x1[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+        x0[it] = *reinterpret_cast<const cf*>(src + p0 + so);
+        x1[it] = *reinterpret_cast<const cf*>(src + p1 + so);
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], x0[it].im, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1[it].im, acc, 0, 0, 0);
+        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[0], acc[1]};
+        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[2], acc[3]};
+    }
+}
+
+// per-lane byte offsets of the pass elements 2q, 2q+1 for digits 0..K-1
+template <int K>
+__device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t (&P1)[K], int logC, int pad) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t h = (uint32_t)logC + 3u * j;
+        const uint32_t L0 = digit_deposit(16u * wave + lo, h) | ((2u * hi) << h);
+        P0[j] = lds_phys(L0, pad) * 8u;
+        P1[j] = lds_phys(L0 | (1u << h), pad) * 8u;
+    }
+}
+
+// Forward (or adjoint) pass of K <= 4 radix-8 digits on tiles of 2048 * NI
+// complex64 elements, per-lane LDS addresses as in the backward below; the
+// next tile is fetched into registers while the current one is processed.
+template <int K, int NI>
+__global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_pass_fast_kernel(PassArgs a) {
+    static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr uint32_t tileE = 2048u * NI;
+    const int pad = a.pad_shift;
+    uint32_t P0[K], P1[K];
+    cpass8_lane_offsets<K>(P0, P1, a.logC, pad);
+    CFrag8 fr;
+    load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
+    const cf* in = static_cast<const cf*>(a.in);
+    cf* out = static_cast<cf*>(a.out);
+    uint4 pa[NI];
+    int64_t t = blockIdx.x;
+    if (t < a.ntiles) bwd_fetch<NI, true>(pa, a, in, t, tileE);
+    for (; t < a.ntiles; t += gridDim.x) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]));
+        bwd_commit<NI, true>(reinterpret_cast<cf*>(smem_raw), pa, a, tileE);
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        if (tn < a.ntiles) bwd_fetch<NI, true>(pa, a, in, tn, tileE);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            cpass8<NI>(smem_raw, smem_raw, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
+            __syncthreads();
+        }
+        bwd_store(reinterpret_cast<const cf*>(smem_raw), a, out, t, tileE);
+        __syncthreads();
+    }
+}
+
 template <int K, int NI>
 __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
@@ -340,19 +416,14 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
     // per-lane byte offsets: pass elements 2q and 2q+1, gradient element
     uint32_t P0[K], P1[K], GB[K];
+    cpass8_lane_offsets<K>(P0, P1, a.logC, pad);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const uint32_t h = (uint32_t)a.logC + 3u * j;
-        const uint32_t L0 = digit_deposit(16u * wave + lo, h) | ((2u * hi) << h);
-        P0[j] = lds_phys(L0, pad) * 8u;
-        P1[j] = lds_phys(L0 | (1u << h), pad) * 8u;
         const uint32_t GL = digit_deposit(16u * wave + hi, h) | ((lo >> 1) << h);
         GB[j] = lds_phys(GL, pad) * 8u + 4u * (lo & 1u);
     }
-    // uniform offsets of pass step it and gradient MFMA t
-    auto soff = [&](int j, int it) {
-        return lds_phys(digit_deposit(256u * it, (uint32_t)a.logC + 3u * j), pad) * 8u;
-    };
+    // uniform offset of gradient MFMA t
     auto goff = [&](int j, int t) {
         return lds_phys(digit_deposit(256u * (t >> 2) + 4u * (t & 3), (uint32_t)a.logC + 3u * j), pad) * 8u;
     };
@@ -366,24 +437,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     // W (fragments fr) along digit J: src -> dst (in place when equal)
     auto pass = [&](auto J, const unsigned char* src, unsigned char* dst, const CFrag8& fr) {
         constexpr int j = decltype(J)::value;
-        cf x0[NI], x1[NI];
-#pragma unroll
-        for (int it = 0; it < NI; ++it) {
-            const uint32_t so = soff(j, it);
-            x0[it] = *reinterpret_cast<const cf*>(src + P0[j] + so);
-            x1[it] = *reinterpret_cast<const cf*>(src + P1[j] + so);
-        }
-#pragma unroll
-        for (int it = 0; it < NI; ++it) {
-            f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0[it].re, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], x0[it].im, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1[it].re, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1[it].im, acc, 0, 0, 0);
-            const uint32_t so = soff(j, it);
-            *reinterpret_cast<cf*>(dst + P0[j] + so) = cf{acc[0], acc[1]};
-            *reinterpret_cast<cf*>(dst + P1[j] + so) = cf{acc[2], acc[3]};
-        }
+        cpass8<NI>(src, dst, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
     };
     // gradient sums of digit J (cotangent in Ct, activation act), then the
     // adjoint pass on Ct along J (skipped when adj is false)

@@ -29,6 +29,9 @@ struct CBwdArgs;
 hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 // the same on tiles of 2048 * ni elements (ni = 1, 2) with k <= 4 digits,
 // LDS addresses precomputed per lane
+// forward / adjoint pass of k <= 4 radix-8 digits, complex64, tiles of
+// 2048 * ni elements, 1024 threads, per-lane LDS addresses
+hipError_t launch_cpass8_fast(int k, int ni, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
 hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 // k dominant coefficients of every instance (ascending indices, ties to the

@@ -59,6 +59,28 @@ static hipError_t launch_fast(const CBwdArgs& a, unsigned grid, size_t lds, hipS
     return hipGetLastError();
 }
 
+template <int K, int NI>
+static hipError_t launch_pfast(const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds(gtt_c64_mfma8_pass_fast_kernel<K, NI>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((gtt_c64_mfma8_pass_fast_kernel<K, NI>), dim3(grid), dim3(kBwdThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpass8_fast(int k, int ni, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    switch (k * 4 + ni) {
+        case 1 * 4 + 1: return launch_pfast<1, 1>(a, grid, lds, s);
+        case 1 * 4 + 2: return launch_pfast<1, 2>(a, grid, lds, s);
+        case 2 * 4 + 1: return launch_pfast<2, 1>(a, grid, lds, s);
+        case 2 * 4 + 2: return launch_pfast<2, 2>(a, grid, lds, s);
+        case 3 * 4 + 1: return launch_pfast<3, 1>(a, grid, lds, s);
+        case 3 * 4 + 2: return launch_pfast<3, 2>(a, grid, lds, s);
+        case 4 * 4 + 1: return launch_pfast<4, 1>(a, grid, lds, s);
+        case 4 * 4 + 2: return launch_pfast<4, 2>(a, grid, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     switch (k * 4 + ni) {
         case 1 * 4 + 1: return launch_fast<1, 1>(a, grid, lds, s);

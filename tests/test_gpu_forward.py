@@ -40,6 +40,22 @@ def test_forward_matches_oracle(b, n, dtype):
     assert err < TOL[dtype], (b, n, dtype, err, plan.describe())
 
 
+# complex radix 8: every (digits, tile) variant of the matrix-core pass with
+# per-lane addresses (1-4 digits, 2048 / 4096 element tiles, contiguous and
+# strided groups) and the general kernel (8192 element tiles)
+@pytest.mark.parametrize("n,batch", [(1, 512), (2, 64), (3, 4), (3, 8), (4, 2), (5, 3), (6, 8), (7, 1), (8, 1)])
+def test_c64_radix8_tiles_forward_inverse(n, batch):
+    b, dtype = 8, torch.complex64
+    say(f"forward/inverse c64 b=8 n={n} batch={batch}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=3000 + n)
+    plan = G.Plan(b, n, batch, dtype)
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, x)
+    torch.cuda.synchronize()
+    assert rel_err(host64(y), O.staged(W64, x64, n)) < TOL[dtype]
+    assert rel_err(host64(xi), O.adjoint(W64, x64, n)) < TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64, torch.bfloat16], ids=str)
 @pytest.mark.parametrize("b,n", [(2, 14), (3, 9), (4, 8), (5, 5), (8, 5), (16, 3)])
 def test_inverse_matches_oracle_and_roundtrip(b, n, dtype):
