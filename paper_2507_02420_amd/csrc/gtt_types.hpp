@@ -13,7 +13,7 @@
 
 namespace gtt {
 
-struct cf {
+struct alignas(8) cf {  // 8-byte aligned: LDS accesses are single 64-bit operations
     float re, im;
 };
 struct cd {
