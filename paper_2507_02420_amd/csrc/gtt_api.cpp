@@ -230,6 +230,25 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
     }
 }
 
+// Complex radix-8 matrix-core groups of up to four digits on tiles of 2048
+// or 4096 elements run the kernels with per-lane LDS addresses, on the
+// padding and fibre-to-lane maps chosen for them (bwd: with the gradient
+// sums' accesses).
+static void make_fast(Group* g, size_t csize, bool bwd) {
+    g->fast_ni = 0;
+    g->fmap = 0;
+    if (g->kind != kKindCMfma || g->k < 1 || g->k > 4) return;
+    if (g->mode != kContigVec && g->mode != kRowVec) return;
+    const int ni = g->tileE == 2048 ? 1 : g->tileE == 4096 ? 2 : 0;
+    if (!ni) return;
+    const FastMap m = fast_map(g->k, ni, g->logC, bwd);
+    g->fast_ni = ni;
+    g->fmap = m.map;
+    g->fast_conflicts = m.conflicts;
+    g->pad_shift = m.pad;
+    g->lds_bytes = (size_t)lds_tile_elems_host(g->tileE, m.pad) * csize;
+}
+
 // Plan the digit groups for one radix list.
 gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags,
                        bool uniform, std::vector<Group>* groups, std::vector<Group>* bwd_groups, bool ragged) {
@@ -277,6 +296,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                     groups->push_back(g);
                     s += k;
                 }
+                for (Group& g : *groups) make_fast(&g, cs, false);
                 if (bwd_groups) {
                     // backward: same digit groups, tiles of at most 40 KiB; the
                     // matrix-core backward handles up to 4 digits on vector
@@ -285,15 +305,12 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                     bwd_groups->clear();
                     for (const Group& fg : *groups) {
                         Group g;
-                        // strided matrix-core groups of <= 2 digits: 16 KiB
-                        // tiles, so that two work-groups share a compute unit
-                        const int64_t Tb = (int64_t)((kind == kKindCMfma && fg.k <= 2 && fg.s0 > 0) ? 16 * 1024
-                                                                                                  : 40 * 1024) /
-                                           (int64_t)cs;
+                        const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
                         fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
                         if (g.kind == kKindCMfma &&
                             (g.k > 4 || g.tileE > 8192 || (g.mode != kContigVec && g.mode != kRowVec)))
                             g.kind = kKindValu;
+                        make_fast(&g, cs, true);
                         bwd_groups->push_back(g);
                     }
                 }
@@ -340,6 +357,7 @@ void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, co
         }
     }
     a->wtotal = g.wtotal;
+    a->fmap = g.fmap;
 }
 }  // namespace gtt
 
@@ -368,9 +386,7 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     // complex radix-8 tiles of 2048 / 4096 elements: the matrix-core pass
     // with per-lane addresses, two 1024-thread work-groups per compute unit
     // looping over tiles with a register prefetch
-    const int fast_ni = (g.kind == kKindCMfma && cut < 0 && g.k <= 4 && (g.mode == kContigVec || g.mode == kRowVec))
-                            ? (g.tileE == 2048 ? 1 : g.tileE == 4096 ? 2 : 0)
-                            : 0;
+    const int fast_ni = cut < 0 ? g.fast_ni : 0;
     timing_begin(tp, s);
     hipError_t e;
     if (fast_ni) {

@@ -58,6 +58,10 @@ struct PassArgs {
     int32_t wofs[kMaxDigits];      // element offset of digit j's matrix in W
     FastDiv divrad[kMaxDigits];    // division by rad[j]
     int32_t wtotal;                // elements of W to stage in LDS
+    // radix-8 matrix-core kernels with per-lane addresses: per digit j,
+    // bits 16j..16j+7 = fibre-bit mask of the lane index, then the two
+    // gradient lane-group bits (3 bits each)
+    uint64_t fmap;
 };
 
 // backward of one group, complex64 radix 8 on the matrix cores

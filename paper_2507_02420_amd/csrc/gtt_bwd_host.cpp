@@ -27,15 +27,6 @@ size_t bwd_lds_bytes(const Group& g, size_t csize, int b) {
     return (size_t)(3 * maxb * maxb + kThreads + 3 * tileP) * csize;
 }
 
-// tile steps of the precomputed-address matrix-core backward for a group
-// (0: not applicable)
-static int cbwd_fast_ni(const Group& g) {
-    if (g.kind != kKindCMfma || g.k < 1 || g.k > 4) return 0;
-    if (g.tileE == 2048) return 1;
-    if (g.tileE == 4096) return 2;
-    return 0;
-}
-
 // work-groups of one backward launch (fixed per plan: determinism of gW);
 // the matrix-core kernel is one 1024-thread work-group per compute unit
 static unsigned bwd_grid(const Group& g) {
@@ -90,7 +81,7 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
             ca.p = ba.p;
             ca.c_out = ba.c_out;
             ca.partials = ba.partials;
-            const int ni = cbwd_fast_ni(G);
+            const int ni = G.fast_ni;
             const size_t lds = bwd_lds_bytes(G, cs, b);
             const hipError_t e = ni ? launch_cbwd8_fast(G.k, ni, ca, grid, lds, s) : launch_cbwd8(ca, grid, lds, s);
             if (e != hipSuccess) return GTT_ERR_HIP;

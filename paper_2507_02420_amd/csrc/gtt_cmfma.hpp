@@ -297,8 +297,8 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
 
 
 // ---------------------------------------------------------------------------
-// Backward of one digit group with per-lane LDS addresses computed once per
-// launch (tiles of 2048 * NI elements, K <= 4 digits).
+// Radix-8 passes and backward with per-lane LDS addresses (tiles of 2048 * NI
+// complex64 elements, K <= 4 digits, 1024 threads).
 //
 // A tile position is a bit string: column bits (logC), three bits per digit,
 // then row bits.  The LDS padding adds x >> p for a few shifts p, and a shift
@@ -310,101 +310,210 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
 // splits every LDS address into a per-lane base (registers, once per launch)
 // plus an offset that is the same for the whole work-group.
 //
-// Fibres of a digit (F = 256 NI) are split so that wave w owns
-// 256 it + 16 w + i (it < NI, i < 16).  In the pass, lane (q, i) handles
-// elements 2q, 2q+1 of fibre i of step it.  In the gradient sums, MFMA t
-// (t < 4 NI) takes fibre 256 (t / 4) + 16 w + 4 (t % 4) + k on lane group k,
-// so a wave reads for the sums exactly the fibres that its own pass rewrites
-// next: the sums and the adjoint pass of a digit need no barrier in between.
+// Fibres of a digit: F = 256 NI; bit 8 is the loop step it.  The planner
+// picks per digit an 8-bit mask (PassArgs::fmap): in step it, wave w owns the
+// 16 fibres whose bits outside the mask spell w.  In the pass, lane (q, i)
+// handles elements 2q, 2q+1 of the fibre whose mask bits spell i.  In the
+// gradient sums, lane group k (0..3) sets fibre bits kb0 (k & 1) and kb1
+// (k >> 1), and the four MFMAs of a block run over the other two mask bits;
+// so a wave reads for the sums exactly the fibres its own pass rewrites next
+// and the two need no barrier in between.  The planner chooses the padding
+// and the maps so that these accesses avoid LDS bank conflicts.
 __device__ __forceinline__ uint32_t digit_deposit(uint32_t v, uint32_t h) {
     return ((v >> h) << (h + 3)) | (v & ((1u << h) - 1u));
+}
+
+// the low bits of v placed, in order, at the set bits of mask (8 bits)
+__device__ __forceinline__ uint32_t deposit8(uint32_t v, uint32_t mask) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if (mask >> b & 1u) {
+            r |= (v & 1u) << b;
+            v >>= 1;
+        }
+    return r;
 }
 
 template <int V>
 using IntC = std::integral_constant<int, V>;
 
+struct DigitMap {
+    uint32_t mask, kb0, kb1, ob0, ob1;
+};
+
+__device__ __forceinline__ DigitMap digit_map(uint64_t fmap, int j) {
+    const uint32_t code = (uint32_t)(fmap >> (16 * j)) & 0xffffu;
+    DigitMap d;
+    d.mask = code & 0xffu;
+    d.kb0 = (code >> 8) & 7u;
+    d.kb1 = (code >> 11) & 7u;
+    const uint32_t rest = d.mask & ~(1u << d.kb0) & ~(1u << d.kb1);
+    d.ob0 = __builtin_ctz(rest);
+    d.ob1 = __builtin_ctz(rest & (rest - 1u));
+    return d;
+}
+
 // W (fragments fr) along the digit whose three bits start at h, over all
-// fibres of a 2048 * NI element tile, 1024 threads: lane (q, i) of wave w
-// takes elements 2q, 2q+1 of fibre 256 it + 16 w + i at byte offsets
-// p0, p1 (+ the step's uniform offset).  src -> dst, in place when equal.
+// fibres of a 2048 * NI element tile: lane (q, i) takes elements 2q, 2q+1 of
+// its fibre of step it at byte offsets p0, p1 plus the step's uniform
+// offset.  src -> dst, in place when equal.
+template <int NI>
+struct PassRegs {
+    cf x0[NI], x1[NI];
+};
+
+template <int NI>
+__device__ __forceinline__ void cpass8_load(PassRegs<NI>& r, const unsigned char* src, uint32_t p0, uint32_t p1,
+                                            uint32_t h, int pad) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+        r.x0[it] = *reinterpret_cast<const cf*>(src + p0 + so);
+        r.x1[it] = *reinterpret_cast<const cf*>(src + p1 + so);
+    }
+}
+
+// the steps' MFMA chains interleaved, then the stores
+template <int NI>
+__device__ __forceinline__ void cpass8_compute_store(const PassRegs<NI>& r, unsigned char* dst, uint32_t p0,
+                                                     uint32_t p1, uint32_t h, int pad, const CFrag8& fr) {
+    f32x4_c acc[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) acc[it] = f32x4_c{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], r.x0[it].re, acc[it], 0, 0, 0);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], r.x0[it].im, acc[it], 0, 0, 0);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], r.x1[it].re, acc[it], 0, 0, 0);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], r.x1[it].im, acc[it], 0, 0, 0);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[it][0], acc[it][1]};
+        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[it][2], acc[it][3]};
+    }
+}
+
+// W (fragments fr) along the digit whose three bits start at h, over all
+// fibres of a 2048 * NI element tile: lane (q, i) takes elements 2q, 2q+1 of
+// its fibre of step it at byte offsets p0, p1 plus the step's uniform
+// offset.  src -> dst, in place when equal.  All loads are issued before the
+// first MFMA, so the phase waits for LDS once.
 template <int NI>
 __device__ __forceinline__ void cpass8(const unsigned char* src, unsigned char* dst, uint32_t p0, uint32_t p1,
                                        uint32_t h, int pad, const CFrag8& fr) {
-    cf x0[NI], x1[NI];
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
-        x0[it] = *reinterpret_cast<const cf*>(src + p0 + so);
-        x1[it] = *reinterpret_cast<const cf*>(src + p1 + so);
-    }
-#pragma unroll
-    for (int it = 0; it < NI; ++it) {
-        f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], x0[it].re, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], x0[it].im, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], x1[it].re, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], x1[it].im, acc, 0, 0, 0);
-        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
-        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[0], acc[1]};
-        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[2], acc[3]};
-    }
+    PassRegs<NI> r;
+    cpass8_load<NI>(r, src, p0, p1, h, pad);
+    __builtin_amdgcn_sched_barrier(0);
+    cpass8_compute_store<NI>(r, dst, p0, p1, h, pad, fr);
 }
 
 // per-lane byte offsets of the pass elements 2q, 2q+1 for digits 0..K-1
 template <int K>
-__device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t (&P1)[K], int logC, int pad) {
+__device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t (&P1)[K], const PassArgs& a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const uint32_t h = (uint32_t)logC + 3u * j;
-        const uint32_t L0 = digit_deposit(16u * wave + lo, h) | ((2u * hi) << h);
-        P0[j] = lds_phys(L0, pad) * 8u;
-        P1[j] = lds_phys(L0 | (1u << h), pad) * 8u;
+        const DigitMap d = digit_map(a.fmap, j);
+        const uint32_t h = (uint32_t)a.logC + 3u * j;
+        const uint32_t f = deposit8((uint32_t)wave, ~d.mask & 0xffu) | deposit8(lo, d.mask);
+        const uint32_t L0 = digit_deposit(f, h) | ((2u * hi) << h);
+        P0[j] = lds_phys(L0, a.pad_shift) * 8u;
+        P1[j] = lds_phys(L0 | (1u << h), a.pad_shift) * 8u;
+    }
+}
+
+// Tile transfers: 16-byte global accesses (two elements per lane and
+// access), two 64-bit LDS accesses.  NV = tileE / 2048 vectors per thread.
+template <int NV>
+__device__ __forceinline__ void fast_fetch(uint4 (&buf)[NV], const PassArgs& a, const cf* __restrict__ in, int64_t t,
+                                           uint32_t tileE) {
+    bwd_fetch<NV, true>(buf, a, in, t, tileE);
+}
+
+template <int NV>
+__device__ __forceinline__ void fast_commit(unsigned char* lds, const uint4 (&buf)[NV], int pad) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        cf vals[2];
+        *reinterpret_cast<uint4*>(vals) = buf[v];
+        // a pair never straddles a pad (shifts >= 1): consecutive slots
+        const uint32_t ph = lds_phys(2u * (threadIdx.x + v * kBwdThreads), pad) * 8u;
+        *reinterpret_cast<cf*>(lds + ph) = vals[0];
+        *reinterpret_cast<cf*>(lds + ph + 8) = vals[1];
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void fast_store(const unsigned char* lds, const PassArgs& a, cf* __restrict__ out,
+                                           int64_t t, uint32_t tileE) {
+    const bool contig = a.mode == kContigVec;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const uint32_t i = threadIdx.x + v * kBwdThreads;
+        const uint32_t ph = lds_phys(2u * i, a.pad_shift) * 8u;
+        cf vals[2];
+        vals[0] = *reinterpret_cast<const cf*>(lds + ph);
+        vals[1] = *reinterpret_cast<const cf*>(lds + ph + 8);
+        *reinterpret_cast<uint4*>(out + vec_offset<cf>(a, t, i, hb, l, tileE)) = *reinterpret_cast<const uint4*>(vals);
     }
 }
 
 // Forward (or adjoint) pass of K <= 4 radix-8 digits on tiles of 2048 * NI
-// complex64 elements, per-lane LDS addresses as in the backward below; the
-// next tile is fetched into registers while the current one is processed.
+// complex64 elements; the next tile is fetched into registers while the
+// current one runs its digit passes.
+// (two work-groups per compute unit: eight waves per SIMD, at most 64 VGPRs)
 template <int K, int NI>
-__global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_pass_fast_kernel(PassArgs a) {
+__global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel(PassArgs a) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr uint32_t tileE = 2048u * NI;
+    constexpr int NE = NI;  // 16-byte vectors per thread
     const int pad = a.pad_shift;
     uint32_t P0[K], P1[K];
-    cpass8_lane_offsets<K>(P0, P1, a.logC, pad);
+    cpass8_lane_offsets<K>(P0, P1, a);
     CFrag8 fr;
     load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
     const cf* in = static_cast<const cf*>(a.in);
     cf* out = static_cast<cf*>(a.out);
-    uint4 pa[NI];
+    uint4 pa[NE];
     int64_t t = blockIdx.x;
-    if (t < a.ntiles) bwd_fetch<NI, true>(pa, a, in, t, tileE);
+    if (t < a.ntiles) fast_fetch<NE>(pa, a, in, t, tileE);
     for (; t < a.ntiles; t += gridDim.x) {
+        // keep base + offset sums inside the loop: hoisted, they would hold
+        // one register per (digit, step)
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]));
-        bwd_commit<NI, true>(reinterpret_cast<cf*>(smem_raw), pa, a, tileE);
+        fast_commit<NE>(smem_raw, pa, pad);
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        if (tn < a.ntiles) bwd_fetch<NI, true>(pa, a, in, tn, tileE);
+        if (tn < a.ntiles) fast_fetch<NE>(pa, a, in, tn, tileE);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             cpass8<NI>(smem_raw, smem_raw, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
             __syncthreads();
         }
-        bwd_store(reinterpret_cast<const cf*>(smem_raw), a, out, t, tileE);
+        fast_store<NE>(smem_raw, a, out, t, tileE);
         __syncthreads();
     }
 }
 
+// Backward of one digit group (see gtt_c64_mfma8_bwd_kernel for the
+// checkpointing).  In the gradient sums, row m = 8 comp + e of the real
+// 16 x 16 block is component comp of element e.
 template <int K, int NI>
 __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
     const PassArgs& a = ba.p;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr uint32_t tileE = 2048u * NI;
+    constexpr int NE = NI;  // 16-byte vectors per thread
     const int pad = a.pad_shift;
     const uint32_t tileB = lds_tile_elems(tileE, pad) * (uint32_t)sizeof(cf);
     unsigned char* Ab = smem_raw;
@@ -414,18 +523,21 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     double* red = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
-    // per-lane byte offsets: pass elements 2q and 2q+1, gradient element
     uint32_t P0[K], P1[K], GB[K];
-    cpass8_lane_offsets<K>(P0, P1, a.logC, pad);
+    cpass8_lane_offsets<K>(P0, P1, a);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
+        const DigitMap d = digit_map(a.fmap, j);
         const uint32_t h = (uint32_t)a.logC + 3u * j;
-        const uint32_t GL = digit_deposit(16u * wave + hi, h) | ((lo >> 1) << h);
-        GB[j] = lds_phys(GL, pad) * 8u + 4u * (lo & 1u);
+        const uint32_t f = deposit8((uint32_t)wave, ~d.mask & 0xffu) | ((hi & 1u) << d.kb0) | ((hi >> 1) << d.kb1);
+        GB[j] = lds_phys(digit_deposit(f, h) | ((lo & 7u) << h), pad) * 8u + 4u * (lo >> 3);
     }
-    // uniform offset of gradient MFMA t
+    // uniform offset of gradient MFMA t of digit j
     auto goff = [&](int j, int t) {
-        return lds_phys(digit_deposit(256u * (t >> 2) + 4u * (t & 3), (uint32_t)a.logC + 3u * j), pad) * 8u;
+        const DigitMap d = digit_map(a.fmap, j);
+        const uint32_t u = (uint32_t)(t & 3);
+        const uint32_t f = 256u * (uint32_t)(t >> 2) | ((u & 1u) << d.ob0) | ((u >> 1) << d.ob1);
+        return lds_phys(digit_deposit(f, (uint32_t)a.logC + 3u * j), pad) * 8u;
     };
     CFrag8 fw, fh;
     load_cfrag8(fw, static_cast<const cf*>(a.W), 0);
@@ -440,9 +552,13 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
         cpass8<NI>(src, dst, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
     };
     // gradient sums of digit J (cotangent in Ct, activation act), then the
-    // adjoint pass on Ct along J (skipped when adj is false)
-    auto fused = [&](auto J, const unsigned char* act, bool adj) {
+    // adjoint pass on Ct along J (skipped when ADJ is false).  Per step, all
+    // LDS loads are issued before the first MFMA; the adjoint pass rewrites
+    // only fibres this wave has just read.
+    auto fused = [&](auto J, const unsigned char* act, auto ADJ) {
         constexpr int j = decltype(J)::value;
+        constexpr bool adj = decltype(ADJ)::value != 0;
+        const uint32_t h = (uint32_t)a.logC + 3u * j;
         f32x4_c M = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
@@ -453,34 +569,51 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
                 cv[u] = *reinterpret_cast<const float*>(Cb + o);
                 av[u] = *reinterpret_cast<const float*>(act + o);
             }
+            cf x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
+            const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+            if constexpr (adj) {
+                x0 = *reinterpret_cast<const cf*>(Cb + P0[j] + so);
+                x1 = *reinterpret_cast<const cf*>(Cb + P1[j] + so);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (adj) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[0], x0.re, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[0], av[0], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[1], x0.im, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[1], av[1], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[2], x1.re, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[2], av[2], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[3], x1.im, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[3], av[3], M, 0, 0, 0);
+                *reinterpret_cast<cf*>(Cb + P0[j] + so) = cf{acc[0], acc[1]};
+                *reinterpret_cast<cf*>(Cb + P1[j] + so) = cf{acc[2], acc[3]};
+            } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[u], av[u], M, 0, 0, 0);
+                for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[u], av[u], M, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
-        // the pass rewrites only fibres this wave has just read
-        if (adj) pass(J, Cb, Cb, fh);
     };
 
-    uint4 pa[NI], pc[NI];
+    uint4 pa[NE], pc[NE];
     int64_t t = blockIdx.x;
     if (t < a.ntiles) {
-        bwd_fetch<NI, true>(pa, a, xin, t, tileE);
-        bwd_fetch<NI, true>(pc, a, cin, t, tileE);
+        fast_fetch<NE>(pa, a, xin, t, tileE);
+        fast_fetch<NE>(pc, a, cin, t, tileE);
     }
     const bool want_gx = a.out != nullptr;
     for (; t < a.ntiles; t += gridDim.x) {
-        // keep base + offset sums inside the loop: hoisted, they would hold
-        // one register per (digit, step) and spill
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]), "+v"(GB[j]));
-        bwd_commit<NI, true>(reinterpret_cast<cf*>(Ab), pa, a, tileE);
-        bwd_commit<NI, true>(reinterpret_cast<cf*>(Cb), pc, a, tileE);
+        fast_commit<NE>(Ab, pa, pad);
+        fast_commit<NE>(Cb, pc, pad);
         __syncthreads();
         const int64_t tn = t + gridDim.x;
         if (tn < a.ntiles) {  // in flight while this tile is processed
-            bwd_fetch<NI, true>(pa, a, xin, tn, tileE);
-            bwd_fetch<NI, true>(pc, a, cin, tn, tileE);
+            fast_fetch<NE>(pa, a, xin, tn, tileE);
+            fast_fetch<NE>(pc, a, cin, tn, tileE);
         }
         if constexpr (K >= 2) {
             pass(IntC<0>{}, Ab, T1b, fw);  // a_1
@@ -493,29 +626,32 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
         if constexpr (K == 4) {
             pass(IntC<2>{}, T2b, T2b, fw);  // a_3
             __syncthreads();
-            fused(IntC<3>{}, T2b, true);
+            fused(IntC<3>{}, T2b, IntC<1>{});
             __syncthreads();
             pass(IntC<1>{}, T1b, T2b, fw);  // a_2 again
             __syncthreads();
         }
         if constexpr (K >= 3) {
-            fused(IntC<2>{}, T2b, true);
+            fused(IntC<2>{}, T2b, IntC<1>{});
             __syncthreads();
         }
         if constexpr (K >= 2) {
-            fused(IntC<1>{}, T1b, true);
+            fused(IntC<1>{}, T1b, IntC<1>{});
             __syncthreads();
         }
         // out is null for the first digit group when only gW is wanted
-        fused(IntC<0>{}, Ab, want_gx);
+        if (want_gx)
+            fused(IntC<0>{}, Ab, IntC<1>{});
+        else
+            fused(IntC<0>{}, Ab, IntC<0>{});
         __syncthreads();
         if (want_gx) {
-            bwd_store(reinterpret_cast<const cf*>(Cb), a, static_cast<cf*>(a.out), t, tileE);
+            fast_store<NE>(Cb, a, static_cast<cf*>(a.out), t, tileE);
             __syncthreads();
         }
     }
     // reduce the waves' 16 x 16 blocks in a fixed order, then form the
-    // complex gradient
+    // complex gradient (row / column m = 8 comp + e)
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wave * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = Md[v];
     __syncthreads();
@@ -527,8 +663,8 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             return s;
         };
         cf g;
-        g.re = (float)(Mv(2 * r, 2 * q) + Mv(2 * r + 1, 2 * q + 1));
-        g.im = (float)(Mv(2 * r + 1, 2 * q) - Mv(2 * r, 2 * q + 1));
+        g.re = (float)(Mv(r, q) + Mv(8 + r, 8 + q));
+        g.im = (float)(Mv(8 + r, q) - Mv(r, 8 + q));
         static_cast<cf*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
     }
 }

@@ -1,0 +1,212 @@
+// LDS layout of the radix-8 matrix-core kernels with per-lane addresses:
+// padding shifts and, per digit, the fibre-to-lane map, chosen so that the
+// kernels' LDS accesses avoid bank conflicts.
+//
+// Bank model (measured on gfx950 with ds_read_b32/b64/b128 patterns):
+// 64-bit accesses are served 32 lanes per cycle over 64 four-byte banks, so
+// the 32 complex64 elements of a half-wave conflict exactly when two
+// distinct elements agree modulo 32; 32-bit accesses are served 32 lanes
+// per cycle over 32 banks; equal addresses are broadcast.
+//
+// Tile positions are bit strings (logC column bits, three bits per digit,
+// row bits); the padding phys(x) = x + sum_p (x >> p) is additive over
+// disjoint bits, which is what lets the kernels split addresses into lane
+// and loop parts.  Per digit j the low eight bits of a fibre index carry
+// the lane and wave: the four bits in mask_j take the lane's 16-value index,
+// the other four the wave.  In the gradient sums, lane group k (0..3) sets
+// fibre bits kb0_j (k & 1) and kb1_j (k >> 1); the remaining two mask bits
+// are the loop over the four MFMAs of a block.
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "gtt_plan.hpp"
+
+namespace gtt {
+
+namespace {
+
+struct Pads {
+    int p[3];
+    int n;
+    uint32_t phys(uint32_t x) const {
+        uint32_t r = x;
+        for (int i = 0; i < n; ++i) r += x >> p[i];
+        return r;
+    }
+    int packed() const {
+        int q[3] = {31, 31, 31};
+        for (int i = 0; i < n; ++i) q[i] = p[i];
+        return q[0] | (q[1] << 8) | (q[2] << 16);
+    }
+};
+
+uint32_t dep3(uint32_t v, uint32_t h) { return ((v >> h) << (h + 3)) | (v & ((1u << h) - 1u)); }
+
+uint32_t pdep8(uint32_t v, uint32_t mask) {
+    uint32_t r = 0;
+    for (int b = 0; b < 8; ++b)
+        if (mask >> b & 1u) {
+            r |= (v & 1u) << b;
+            v >>= 1;
+        }
+    return r;
+}
+
+// largest number of distinct elements sharing a residue modulo `mod`
+int conflict(const uint32_t* e, int n, uint32_t mod = 32) {
+    int worst = 0;
+    for (int i = 0; i < n; ++i) {
+        bool dup = false;
+        for (int k = 0; k < i; ++k) dup |= e[k] == e[i];
+        if (dup) continue;
+        int c = 0;
+        for (int k = 0; k <= i; ++k) {
+            bool first = true;
+            for (int m = 0; m < k; ++m) first &= e[m] != e[k];
+            if (first && (e[k] & (mod - 1u)) == (e[i] & (mod - 1u))) ++c;
+        }
+        if (c > worst) worst = c;
+    }
+    return worst;
+}
+
+// passes: half-waves (q in {0,1} or {2,3}) of the loads at elements 2q and
+// 2q+1 of the 16 fibres of a block
+int stage_cost(const Pads& pd, uint32_t h, uint32_t mask) {
+    int tot = 0;
+    for (int qh = 0; qh < 2; ++qh)
+        for (int which = 0; which < 2; ++which) {
+            uint32_t e[32];
+            int n = 0;
+            for (int q = 2 * qh; q < 2 * qh + 2; ++q)
+                for (uint32_t x = 0; x < 16; ++x)
+                    e[n++] = pd.phys(dep3(pdep8(x, mask), h) | ((uint32_t)(2 * q + which) << h));
+            tot += conflict(e, n) - 1;
+        }
+    return tot;
+}
+
+// gradient sums: per MFMA, lane groups k = 0, 1 (and 2, 3) read one
+// 32-bit component of the 8 elements of fibres with bits kb0, kb1 set from k;
+// 32-bit accesses are served 32 lanes per cycle over 32 banks, so the 16
+// elements of a half-wave must differ modulo 16
+int gw_cost(const Pads& pd, uint32_t h, uint32_t mask, int kb0, int kb1) {
+    int ob[2], no = 0;
+    for (int b = 0; b < 8; ++b)
+        if ((mask >> b & 1u) && b != kb0 && b != kb1) ob[no++] = b;
+    int tot = 0;
+    for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t base = ((u & 1u) << ob[0]) | ((u >> 1) << ob[1]);
+        for (uint32_t kh = 0; kh < 2; ++kh) {
+            uint32_t e[16];
+            int n = 0;
+            for (uint32_t kl = 0; kl < 2; ++kl) {
+                const uint32_t f = base | (kl << kb0) | (kh << kb1);
+                for (uint32_t el = 0; el < 8; ++el) e[n++] = pd.phys(dep3(f, h) | (el << h));
+            }
+            tot += conflict(e, n, 16) - 1;
+        }
+    }
+    return tot;
+}
+
+// tile load / store: a half-wave holds 64 consecutive elements, two per
+// lane, and accesses the even ones, then the odd ones
+int io_cost(const Pads& pd, uint32_t tileE) {
+    int tot = 0;
+    for (uint32_t s = 0; s < tileE; s += 64)
+        for (uint32_t odd = 0; odd < 2; ++odd) {
+            uint32_t e[32];
+            for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(s + 2 * l + odd);
+            tot += conflict(e, 32) - 1;
+        }
+    return tot;
+}
+
+struct Best {
+    int cost = 1 << 30;
+    FastMap m;
+};
+
+FastMap search(int K, int NI, int logC, bool gw) {
+    const uint32_t tileE = 2048u * (uint32_t)NI;
+    // candidate paddings, fewest extra elements first
+    std::vector<std::pair<uint32_t, Pads>> cands;
+    for (int n = 0; n <= 3; ++n) {
+        int p[3];
+        for (p[0] = 4; p[0] <= 12; ++p[0])
+            for (p[1] = (n > 1 ? p[0] + 1 : 13); p[1] <= (n > 1 ? 12 : 13); ++p[1])
+                for (p[2] = (n > 2 ? p[1] + 1 : 13); p[2] <= (n > 2 ? 12 : 13); ++p[2]) {
+                    Pads pd{{p[0], p[1], p[2]}, n};
+                    if (n == 0 && p[0] != 4) continue;
+                    uint32_t extra = 0;
+                    for (int i = 0; i < n; ++i) extra += tileE >> pd.p[i];
+                    if (extra > tileE / 8) continue;  // LDS budget of the four backward tiles
+                    cands.push_back({extra, pd});
+                }
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const std::pair<uint32_t, Pads>& a, const std::pair<uint32_t, Pads>& b) {
+                         return a.first < b.first;
+                     });
+    Best best;
+    for (const auto& c : cands) {
+        const Pads& pd = c.second;
+        int total = io_cost(pd, tileE);
+        FastMap m;
+        m.pad = pd.packed();
+        m.map = 0;
+        for (int j = 0; j < K && total < best.cost; ++j) {
+            const uint32_t h = (uint32_t)logC + 3u * (uint32_t)j;
+            int bj = 1 << 30;
+            uint64_t code = 0;
+            for (uint32_t mask = 0; mask < 256 && bj > 0; ++mask) {
+                if (__builtin_popcount(mask) != 4) continue;
+                const int sc = stage_cost(pd, h, mask);
+                if (sc >= bj) continue;
+                if (!gw) {
+                    bj = sc;
+                    code = mask;
+                    continue;
+                }
+                for (int kb0 = 0; kb0 < 8 && bj > 0; ++kb0)
+                    for (int kb1 = 0; kb1 < 8 && bj > 0; ++kb1) {
+                        if (kb0 == kb1 || !(mask >> kb0 & 1u) || !(mask >> kb1 & 1u)) continue;
+                        const int cst = sc + gw_cost(pd, h, mask, kb0, kb1);
+                        if (cst < bj) {
+                            bj = cst;
+                            code = mask | ((uint64_t)kb0 << 8) | ((uint64_t)kb1 << 11);
+                        }
+                    }
+            }
+            total += bj;
+            m.map |= code << (16 * j);
+        }
+        if (total < best.cost) {
+            best.cost = total;
+            best.m = m;
+            if (total == 0) break;
+        }
+    }
+    best.m.conflicts = best.cost;
+    return best.m;
+}
+
+}  // namespace
+
+FastMap fast_map(int K, int NI, int logC, bool gw) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, bool>, FastMap> cache;
+    const auto key = std::make_tuple(K, NI, logC, gw);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const FastMap m = search(K, NI, logC, gw);
+    cache[key] = m;
+    return m;
+}
+
+}  // namespace gtt

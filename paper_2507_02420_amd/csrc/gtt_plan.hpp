@@ -34,7 +34,19 @@ struct Group {
     int wtotal = 0;
     size_t lds_bytes = 0;
     int64_t elems = 0;  // elements covered by one launch of this group
+    int fast_ni = 0;     // > 0: radix-8 matrix-core kernel with per-lane addresses, tile 2048 * fast_ni
+    uint64_t fmap = 0;   // its fibre-to-lane maps (PassArgs::fmap)
+    int fast_conflicts = 0;  // residual LDS bank conflicts of that layout (model)
 };
+
+// LDS layout of the per-lane-address radix-8 kernels for K digits, tiles of
+// 2048 * NI elements, 2^logC columns; gw: the backward's gradient sums too
+struct FastMap {
+    int pad = kNoPad;   // packed pad shifts
+    uint64_t map = 0;   // PassArgs::fmap
+    int conflicts = 0;  // residual bank conflicts of the layout (0: none)
+};
+FastMap fast_map(int K, int NI, int logC, bool gw);
 
 enum class PlanKind { Uniform, Ragged, Mixed };
 
