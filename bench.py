@@ -70,9 +70,22 @@ def dominant(timing: dict):
     return name, t, achieved
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 over the HIP/C++ sources of libgtt.so (sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2507_02420_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
 def load_traffic(kernel_name: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    for this kernel (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel factor)."""
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a copy-kernel factor) -- only when it was taken on
+    the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -80,8 +93,10 @@ def load_traffic(kernel_name: str, workload: str):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
+    if d.get("kernel_source_sha256") != kernel_source_digest():
+        return None
     ent = d.get("kernels", {}).get(kernel_name)
-    if not ent or ent.get("stale"):
+    if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -122,24 +137,38 @@ def headline(steps, warmup):
     _sync()
     plan.timing(True)
     _sync()
-    s, e = _events()
+    marks = [_events()[0] for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    s.record()
-    for _ in range(steps):
+    marks[0].record()
+    for i in range(steps):
         step()
-    e.record()
+        marks[i + 1].record()
     _sync()
     wall = time.perf_counter() - t0
     plan.timing(False)
-    ms = s.elapsed_time(e) / steps
+    per_step = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+    ms = marks[0].elapsed_time(marks[-1]) / steps
     timing = plan.timing_read()
     name, t, achieved = dominant(timing)
+    q = lambda f: per_step[min(steps - 1, int(f * steps))]
     out = {
         "E": E, "ms_per_step": ms, "wall_s": wall, "timing": timing, "plan": plan.describe(),
+        "step_ms_p10_p50_p90": [q(0.1), q(0.5), q(0.9)],
         "dominant": name, "achieved_GBs": achieved, "bytes_per_launch": t["bytes_per_launch"],
         "tensors": (x, g, W, y, gx, gW),
     }
     return out
+
+
+def copy_ceiling_gbs(nbytes=1 << 30, iters=5):
+    """Device-to-device copy of a 1 GiB buffer: the practical HBM ceiling."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms, _ = time_calls(lambda: b.copy_(a), iters)
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline_headline(tensors, budget_s=20.0):
@@ -293,8 +322,8 @@ def secondary(iters=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
     args = ap.parse_args()
@@ -310,9 +339,12 @@ def main():
     h = headline(args.steps, args.warmup)
     E = h["E"]
     value = E / (h["ms_per_step"] * 1e-3)
+    traffic = load_traffic(h["dominant"], "c64_b8_n6_x256")
     roof = {"bound": "hbm", "achieved": h["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": h["achieved_GBs"] / HBM_PEAK_GBS, "traffic": load_traffic(h["dominant"], "c64_b8_n6_x256"),
-            "kernel": h["dominant"], "algorithmic_bytes_per_launch": h["bytes_per_launch"]}
+            "frac": h["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": h["dominant"], "algorithmic_bytes_per_launch": h["bytes_per_launch"],
+            "round_trips_measured_over_algorithmic": (traffic / h["bytes_per_launch"]) if traffic else None,
+            "copy_ceiling_GBs": copy_ceiling_gbs()}
     cpu = None
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -323,7 +355,8 @@ def main():
         extra = secondary()
     line = {
         "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "step_ms_p10_p50_p90": h["step_ms_p10_p50_p90"],
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": "fwd+bwd: 256 x complex64, b=8, n=6 (N=262144), W 8x8 unitary, L=Re<g,y>",
                    "b": 8, "n": 6, "batch": 256, "elements": E, "parallelism": "single GPU"},
