@@ -413,19 +413,39 @@ __device__ __forceinline__ void cpass8(const unsigned char* src, unsigned char* 
 
 // per-lane byte offsets of the pass elements 2q, 2q+1 for digits 0..K-1
 template <int K>
-__device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t (&P1)[K], const PassArgs& a) {
+__device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t (&P1)[K], uint64_t fmap, int logC,
+                                                    int pad) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const DigitMap d = digit_map(a.fmap, j);
-        const uint32_t h = (uint32_t)a.logC + 3u * j;
+        const DigitMap d = digit_map(fmap, j);
+        const uint32_t h = (uint32_t)logC + 3u * j;
         const uint32_t f = deposit8((uint32_t)wave, ~d.mask & 0xffu) | deposit8(lo, d.mask);
         const uint32_t L0 = digit_deposit(f, h) | ((2u * hi) << h);
-        P0[j] = lds_phys(L0, a.pad_shift) * 8u;
-        P1[j] = lds_phys(L0 | (1u << h), a.pad_shift) * 8u;
+        P0[j] = lds_phys(L0, pad) * 8u;
+        P1[j] = lds_phys(L0 | (1u << h), pad) * 8u;
     }
 }
+
+// LDS layout parameters of a launch: from the arguments, or fixed at compile
+// time for the layouts the planner produces for common shapes, so that
+// every uniform LDS offset becomes an instruction immediate
+struct LayoutArgs {
+    static constexpr bool kFixed = false;
+    __device__ static int pad(const PassArgs& a) { return a.pad_shift; }
+    __device__ static int logc(const PassArgs& a) { return a.logC; }
+    __device__ static uint64_t fmap(const PassArgs& a) { return a.fmap; }
+};
+template <int PAD, int LOGC, uint64_t FMAP>
+struct LayoutFixed {
+    static constexpr bool kFixed = true;
+    static constexpr int kPad = PAD, kLogC = LOGC;
+    static constexpr uint64_t kFmap = FMAP;
+    __device__ static int pad(const PassArgs&) { return PAD; }
+    __device__ static int logc(const PassArgs&) { return LOGC; }
+    __device__ static uint64_t fmap(const PassArgs&) { return FMAP; }
+};
 
 // Tile transfers: 16-byte global accesses (two elements per lane and
 // access), two 64-bit LDS accesses.  NV = tileE / 2048 vectors per thread.
@@ -450,14 +470,14 @@ __device__ __forceinline__ void fast_commit(unsigned char* lds, const uint4 (&bu
 
 template <int NV>
 __device__ __forceinline__ void fast_store(const unsigned char* lds, const PassArgs& a, cf* __restrict__ out,
-                                           int64_t t, uint32_t tileE) {
+                                           int64_t t, uint32_t tileE, int pad) {
     const bool contig = a.mode == kContigVec;
     const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
     const int64_t l = contig ? 0 : t - hb * a.L;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const uint32_t i = threadIdx.x + v * kBwdThreads;
-        const uint32_t ph = lds_phys(2u * i, a.pad_shift) * 8u;
+        const uint32_t ph = lds_phys(2u * i, pad) * 8u;
         cf vals[2];
         vals[0] = *reinterpret_cast<const cf*>(lds + ph);
         vals[1] = *reinterpret_cast<const cf*>(lds + ph + 8);
@@ -469,15 +489,16 @@ __device__ __forceinline__ void fast_store(const unsigned char* lds, const PassA
 // complex64 elements; the next tile is fetched into registers while the
 // current one runs its digit passes.
 // (two work-groups per compute unit: eight waves per SIMD, at most 64 VGPRs)
-template <int K, int NI>
+template <int K, int NI, class LAY>
 __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel(PassArgs a) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr uint32_t tileE = 2048u * NI;
     constexpr int NE = NI;  // 16-byte vectors per thread
-    const int pad = a.pad_shift;
+    const int pad = LAY::pad(a);
+    const int logC = LAY::logc(a);
     uint32_t P0[K], P1[K];
-    cpass8_lane_offsets<K>(P0, P1, a);
+    cpass8_lane_offsets<K>(P0, P1, LAY::fmap(a), logC, pad);
     CFrag8 fr;
     load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
     const cf* in = static_cast<const cf*>(a.in);
@@ -496,10 +517,10 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
         if (tn < a.ntiles) fast_fetch<NE>(pa, a, in, tn, tileE);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            cpass8<NI>(smem_raw, smem_raw, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
+            cpass8<NI>(smem_raw, smem_raw, P0[j], P1[j], (uint32_t)logC + 3u * j, pad, fr);
             __syncthreads();
         }
-        fast_store<NE>(smem_raw, a, out, t, tileE);
+        fast_store<NE>(smem_raw, a, out, t, tileE, pad);
         __syncthreads();
     }
 }
@@ -507,37 +528,40 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
 // Backward of one digit group (see gtt_c64_mfma8_bwd_kernel for the
 // checkpointing).  In the gradient sums, row m = 8 comp + e of the real
 // 16 x 16 block is component comp of element e.
-template <int K, int NI>
+template <int K, int NI, class LAY>
 __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
     const PassArgs& a = ba.p;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr uint32_t tileE = 2048u * NI;
     constexpr int NE = NI;  // 16-byte vectors per thread
-    const int pad = a.pad_shift;
+    const int pad = LAY::pad(a);
+    const int logC = LAY::logc(a);
+    const uint64_t fmap = LAY::fmap(a);
     const uint32_t tileB = lds_tile_elems(tileE, pad) * (uint32_t)sizeof(cf);
-    unsigned char* Ab = smem_raw;
-    unsigned char* T1b = Ab + tileB;
-    unsigned char* Cb = T1b + tileB;
+    // the most used tiles first: their offsets fit instruction immediates
+    unsigned char* Cb = smem_raw;
     unsigned char* T2b = Cb + tileB;  // K >= 3 only
+    unsigned char* T1b = Cb + (K >= 3 ? 2u : 1u) * tileB;
+    unsigned char* Ab = Cb + (K >= 3 ? 3u : K == 2 ? 2u : 1u) * tileB;
     double* red = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
     uint32_t P0[K], P1[K], GB[K];
-    cpass8_lane_offsets<K>(P0, P1, a);
+    cpass8_lane_offsets<K>(P0, P1, fmap, logC, pad);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const DigitMap d = digit_map(a.fmap, j);
-        const uint32_t h = (uint32_t)a.logC + 3u * j;
+        const DigitMap d = digit_map(fmap, j);
+        const uint32_t h = (uint32_t)logC + 3u * j;
         const uint32_t f = deposit8((uint32_t)wave, ~d.mask & 0xffu) | ((hi & 1u) << d.kb0) | ((hi >> 1) << d.kb1);
         GB[j] = lds_phys(digit_deposit(f, h) | ((lo & 7u) << h), pad) * 8u + 4u * (lo >> 3);
     }
     // uniform offset of gradient MFMA t of digit j
     auto goff = [&](int j, int t) {
-        const DigitMap d = digit_map(a.fmap, j);
+        const DigitMap d = digit_map(fmap, j);
         const uint32_t u = (uint32_t)(t & 3);
         const uint32_t f = 256u * (uint32_t)(t >> 2) | ((u & 1u) << d.ob0) | ((u >> 1) << d.ob1);
-        return lds_phys(digit_deposit(f, (uint32_t)a.logC + 3u * j), pad) * 8u;
+        return lds_phys(digit_deposit(f, (uint32_t)logC + 3u * j), pad) * 8u;
     };
     CFrag8 fw, fh;
     load_cfrag8(fw, static_cast<const cf*>(a.W), 0);
@@ -549,7 +573,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     // W (fragments fr) along digit J: src -> dst (in place when equal)
     auto pass = [&](auto J, const unsigned char* src, unsigned char* dst, const CFrag8& fr) {
         constexpr int j = decltype(J)::value;
-        cpass8<NI>(src, dst, P0[j], P1[j], (uint32_t)a.logC + 3u * j, pad, fr);
+        cpass8<NI>(src, dst, P0[j], P1[j], (uint32_t)logC + 3u * j, pad, fr);
     };
     // gradient sums of digit J (cotangent in Ct, activation act), then the
     // adjoint pass on Ct along J (skipped when ADJ is false).  Per step, all
@@ -558,7 +582,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     auto fused = [&](auto J, const unsigned char* act, auto ADJ) {
         constexpr int j = decltype(J)::value;
         constexpr bool adj = decltype(ADJ)::value != 0;
-        const uint32_t h = (uint32_t)a.logC + 3u * j;
+        const uint32_t h = (uint32_t)logC + 3u * j;
         f32x4_c M = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
@@ -646,7 +670,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             fused(IntC<0>{}, Ab, IntC<0>{});
         __syncthreads();
         if (want_gx) {
-            fast_store<NE>(Cb, a, static_cast<cf*>(a.out), t, tileE);
+            fast_store<NE>(Cb, a, static_cast<cf*>(a.out), t, tileE, pad);
             __syncthreads();
         }
     }

@@ -142,3 +142,15 @@ def test_binding_refuses_host_tensors():
     import pytest
     with pytest.raises(ValueError):
         G._ptr(torch.zeros(4))
+
+
+def test_planner_layouts_match_compiled_specializations():
+    # the radix-8 kernels have compile-time-offset instantiations for the
+    # layouts of the 256 x 8^6 complex64 workload (pass_c64.hip: FwdLay4,
+    # FwdLay2, BwdLay4, BwdLay2); the planner must keep producing them, or
+    # that workload silently falls back to run-time offsets
+    d = G.Plan(8, 6, 256, torch.complex64).describe()
+    fwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"]) for g in d["groups"]]
+    bwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"]) for g in d["bwd_groups"]]
+    assert fwd == [(4, 2, 1, 0x1f0a05, 0x1e001b00270017), (2, 2, 64, 0x1f0a05, 0x1e001b)]
+    assert bwd == [(4, 2, 1, 0x1f0905, 0x31d081b01270817), (2, 2, 64, 0x1f0905, 0x31d081b)]
