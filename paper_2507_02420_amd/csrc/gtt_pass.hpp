@@ -75,6 +75,9 @@ struct BlockAll<C, B, R, R> {
     __device__ __forceinline__ static void run(C (&)[(IPow<B, R>::value)], const C (&)[B * B]) {}
 };
 
+// pad_shift of an unpadded tile (all three shifts 31)
+constexpr int kPadNone = 31 | (31 << 8) | (31 << 16);
+
 // LDS position of tile element lam.  pad_shift packs three shift amounts
 // (bits 0-7, 8-15, 16-23; 31 = none): one pad element after every 2^p1, 2^p2
 // and 2^p3 elements.  With p1, p2, p3 one digit apart, every power-of-b
@@ -91,27 +94,46 @@ __device__ __forceinline__ uint32_t lds_tile_elems(uint32_t tileE, int pad_shift
 }
 
 // One super-stage: digits j .. j+R-1 of the group, all fibres of the tile.
+// For a power-of-two radix the block's positions lam0 | m * step have the
+// register digits in bits where lam0 is zero, and lds_phys is additive over
+// numbers with disjoint bits, so every position costs one add of a
+// work-group-uniform offset; without padding positions are linear.
 template <typename C, int B, int R>
 __device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, uint32_t rows,
                                            const C (&w)[B * B]) {
     constexpr int NB = IPow<B, R>::value;
+    constexpr bool kPow2 = (B & (B - 1)) == 0;
     const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t F = (rows << a.logC) / NB;
     const uint32_t bj = (uint32_t)a.bpow[j];
     const uint32_t bjr = (uint32_t)a.bpow[j + R];
     const uint32_t step = bj << a.logC;
+    const int pad = a.pad_shift;
+    const bool linear = pad == kPadNone;
+    uint32_t off[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) off[m] = (kPow2 && !linear) ? lds_phys(m * step, pad) : m * step;
     for (uint32_t f = threadIdx.x; f < F; f += kThreads) {
         const uint32_t c = f & Cm;
         const uint32_t f1 = f >> a.logC;
         const uint32_t Q = fdiv(f1, a.divb[j]);
         const uint32_t glo = f1 - Q * bj;
         const uint32_t lam0 = ((Q * bjr + glo) << a.logC) | c;
+        uint32_t idx[NB];
+        if (kPow2 || linear) {
+            const uint32_t ph0 = linear ? lam0 : lds_phys(lam0, pad);
+#pragma unroll
+            for (int m = 0; m < NB; ++m) idx[m] = ph0 + off[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) idx[m] = lds_phys(lam0 + m * step, pad);
+        }
         C v[NB];
 #pragma unroll
-        for (int m = 0; m < NB; ++m) v[m] = lds[lds_phys(lam0 + m * step, a.pad_shift)];
+        for (int m = 0; m < NB; ++m) v[m] = lds[idx[m]];
         BlockAll<C, B, R, 0>::run(v, w);
 #pragma unroll
-        for (int m = 0; m < NB; ++m) lds[lds_phys(lam0 + m * step, a.pad_shift)] = v[m];
+        for (int m = 0; m < NB; ++m) lds[idx[m]] = v[m];
     }
 }
 
