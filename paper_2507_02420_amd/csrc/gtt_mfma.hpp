@@ -106,24 +106,33 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     const int wave = threadIdx.x >> 6;
     const int q = lane >> 4;
     const uint32_t ngrp = (F + 15) / 16;
+    const int pad = a.pad_shift;
+    // element (16 h + 4 q + v) of a fibre sits at lam0 | that * step, with
+    // the digit's bits zero in lam0: lds_phys splits into a per-fibre base,
+    // a per-lane part (q) and a uniform part (h, v)
+    const uint32_t qoff = lds_phys(4u * q * step, pad);
+    uint32_t off[NB][4];
+#pragma unroll
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) off[h][v] = lds_phys((16u * h + v) * step, pad);
     for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
         const uint32_t f = grp * 16 + (lane & 15);
         const bool valid = f < F;
-        uint32_t lam0 = 0;
+        uint32_t base = 0;
         if (valid) {
             const uint32_t c = f & Cm;
             const uint32_t f1 = f >> a.logC;
             const uint32_t Q = fdiv(f1, a.divb[j]);
             const uint32_t glo = f1 - Q * bj;
-            lam0 = ((Q * bj1 + glo) << a.logC) | c;
+            base = lds_phys(((Q * bj1 + glo) << a.logC) | c, pad) + qoff;
         }
         typename Op::V xb[NB];
 #pragma unroll
         for (int h = 0; h < NB; ++h) {
             float x[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                x[v] = valid ? lds[lds_phys(lam0 + (16 * h + 4 * q + v) * step, a.pad_shift)] : 0.f;
+            for (int v = 0; v < 4; ++v) x[v] = valid ? lds[base + off[h][v]] : 0.f;
             xb[h] = Op::pack(x);
         }
 #pragma unroll
@@ -136,7 +145,7 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
             }
             if (valid) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) lds[lds_phys(lam0 + (16 * bi + 4 * q + v) * step, a.pad_shift)] = acc[v];
+                for (int v = 0; v < 4; ++v) lds[base + off[bi][v]] = acc[v];
             }
         }
     }
