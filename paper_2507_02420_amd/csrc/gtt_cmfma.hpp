@@ -449,41 +449,86 @@ struct LayoutFixed {
 
 // Tile transfers: 16-byte global accesses (two elements per lane and
 // access), two 64-bit LDS accesses.  NV = tileE / 2048 vectors per thread.
-template <int NV>
-__device__ __forceinline__ void fast_fetch(uint4 (&buf)[NV], const PassArgs& a, const cf* __restrict__ in, int64_t t,
-                                           uint32_t tileE) {
-    bwd_fetch<NV, true>(buf, a, in, t, tileE);
-}
+// A thread's global offsets relative to the tile origin and its LDS offsets
+// are the same for every tile; only the origin changes, and the walk over
+// the work-group's tiles (t += gridDim.x) updates it without divisions.
+// position of a work-group's current tile in the walk t += gridDim.x
+struct TileCursor {
+    int64_t origin;  // element offset of the tile's origin
+    int64_t hb, l;   // strided tiles: hi block and column block
+};
 
 template <int NV>
-__device__ __forceinline__ void fast_commit(unsigned char* lds, const uint4 (&buf)[NV], int pad) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        cf vals[2];
-        *reinterpret_cast<uint4*>(vals) = buf[v];
-        // a pair never straddles a pad (shifts >= 1): consecutive slots
-        const uint32_t ph = lds_phys(2u * (threadIdx.x + v * kBwdThreads), pad) * 8u;
-        *reinterpret_cast<cf*>(lds + ph) = vals[0];
-        *reinterpret_cast<cf*>(lds + ph + 8) = vals[1];
-    }
-}
+struct TileWalk {
+    int64_t goff[NV];   // elements from the tile origin to this thread's vector v
+    uint32_t loff[NV];  // LDS byte offset of that vector's first element
+    int64_t dq, dr;     // gridDim.x = dq * L + dr (strided tiles)
+    int64_t span;       // elements per hi block (G * S, strided tiles)
 
-template <int NV>
-__device__ __forceinline__ void fast_store(const unsigned char* lds, const PassArgs& a, cf* __restrict__ out,
-                                           int64_t t, uint32_t tileE, int pad) {
-    const bool contig = a.mode == kContigVec;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
-    const int64_t l = contig ? 0 : t - hb * a.L;
+    __device__ __forceinline__ TileCursor init(const PassArgs& a, uint32_t tileE, int pad) {
+        const bool contig = a.mode == kContigVec;
+        const int lcv = a.logC - 1;  // log2(vectors per row)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const uint32_t i = threadIdx.x + v * kBwdThreads;
-        const uint32_t ph = lds_phys(2u * i, pad) * 8u;
-        cf vals[2];
-        vals[0] = *reinterpret_cast<const cf*>(lds + ph);
-        vals[1] = *reinterpret_cast<const cf*>(lds + ph + 8);
-        *reinterpret_cast<uint4*>(out + vec_offset<cf>(a, t, i, hb, l, tileE)) = *reinterpret_cast<const uint4*>(vals);
+        for (int v = 0; v < NV; ++v) {
+            const uint32_t i = threadIdx.x + v * kBwdThreads;
+            goff[v] = contig ? (int64_t)i * 2
+                             : (int64_t)(i >> lcv) * a.S + (int64_t)(i & ((1u << lcv) - 1u)) * 2;
+            loff[v] = lds_phys(2u * i, pad) * 8u;
+        }
+        span = (int64_t)a.G * a.S;
+        const int64_t t = blockIdx.x;
+        TileCursor c;
+        if (contig) {
+            c.origin = t * (int64_t)tileE;
+            c.hb = c.l = dq = dr = 0;
+        } else {
+            c.hb = t / a.L;
+            c.l = t - c.hb * a.L;
+            dq = (int64_t)gridDim.x / a.L;
+            dr = (int64_t)gridDim.x - dq * a.L;
+            c.origin = c.hb * span + (c.l << a.logC);
+        }
+        return c;
     }
-}
+    // the work-group's next tile (t + gridDim.x)
+    __device__ __forceinline__ TileCursor next(const PassArgs& a, uint32_t tileE, TileCursor c) const {
+        if (a.mode == kContigVec) {
+            c.origin += (int64_t)gridDim.x * tileE;
+        } else {
+            c.l += dr;
+            c.hb += dq;
+            if (c.l >= a.L) {
+                c.l -= a.L;
+                c.hb += 1;
+            }
+            c.origin = c.hb * span + (c.l << a.logC);
+        }
+        return c;
+    }
+    __device__ __forceinline__ void fetch(uint4 (&buf)[NV], const cf* __restrict__ in, const TileCursor& c) const {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) buf[v] = *reinterpret_cast<const uint4*>(in + c.origin + goff[v]);
+    }
+    __device__ __forceinline__ void commit(unsigned char* lds, const uint4 (&buf)[NV]) const {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cf vals[2];
+            *reinterpret_cast<uint4*>(vals) = buf[v];
+            // a pair never straddles a pad (shifts >= 1): consecutive slots
+            *reinterpret_cast<cf*>(lds + loff[v]) = vals[0];
+            *reinterpret_cast<cf*>(lds + loff[v] + 8) = vals[1];
+        }
+    }
+    __device__ __forceinline__ void store(const unsigned char* lds, cf* __restrict__ out, const TileCursor& c) const {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cf vals[2];
+            vals[0] = *reinterpret_cast<const cf*>(lds + loff[v]);
+            vals[1] = *reinterpret_cast<const cf*>(lds + loff[v] + 8);
+            *reinterpret_cast<uint4*>(out + c.origin + goff[v]) = *reinterpret_cast<const uint4*>(vals);
+        }
+    }
+};
 
 // Forward (or adjoint) pass of K <= 4 radix-8 digits on tiles of 2048 * NI
 // complex64 elements; the next tile is fetched into registers while the
@@ -504,30 +549,37 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
     const cf* in = static_cast<const cf*>(a.in);
     cf* out = static_cast<cf*>(a.out);
     uint4 pa[NE];
+    TileWalk<NE> tw;
+    TileCursor cur = tw.init(a, tileE, pad);
     int64_t t = blockIdx.x;
-    if (t < a.ntiles) fast_fetch<NE>(pa, a, in, t, tileE);
+    if (t < a.ntiles) tw.fetch(pa, in, cur);
     for (; t < a.ntiles; t += gridDim.x) {
         // keep base + offset sums inside the loop: hoisted, they would hold
         // one register per (digit, step)
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]));
-        fast_commit<NE>(smem_raw, pa, pad);
+        tw.commit(smem_raw, pa);
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if (tn < a.ntiles) fast_fetch<NE>(pa, a, in, tn, tileE);
+        const TileCursor nxt = tw.next(a, tileE, cur);
+        if (t + gridDim.x < a.ntiles) tw.fetch(pa, in, nxt);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             cpass8<NI>(smem_raw, smem_raw, P0[j], P1[j], (uint32_t)logC + 3u * j, pad, fr);
             __syncthreads();
         }
-        fast_store<NE>(smem_raw, a, out, t, tileE, pad);
+        tw.store(smem_raw, out, cur);
         __syncthreads();
+        cur = nxt;
     }
 }
 
-// Backward of one digit group (see gtt_c64_mfma8_bwd_kernel for the
-// checkpointing).  In the gradient sums, row m = 8 comp + e of the real
-// 16 x 16 block is component comp of element e.
+// Backward of one digit group.  LDS holds the cotangent Ct, the group input
+// A and activation slots T1, T2 (a_s = input of the pass on digit s).  K = 4:
+//   T1 = a_1; T2 = a_2; T1 = a_3;  digit 3: sums + adjoint;
+//   digit 2 (reads T2, Ct) in the same phase as T1 = a_1 recomputed from A;
+//   digit 1 (T1); digit 0 (A).
+// K = 3 keeps a_1, a_2; K = 2 keeps a_1.  In the gradient sums, row
+// m = 8 comp + e of the real 16 x 16 block is component comp of element e.
 template <int K, int NI, class LAY>
 __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
@@ -541,8 +593,8 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     const uint32_t tileB = lds_tile_elems(tileE, pad) * (uint32_t)sizeof(cf);
     // the most used tiles first: their offsets fit instruction immediates
     unsigned char* Cb = smem_raw;
-    unsigned char* T2b = Cb + tileB;  // K >= 3 only
-    unsigned char* T1b = Cb + (K >= 3 ? 2u : 1u) * tileB;
+    unsigned char* T1b = Cb + tileB;
+    unsigned char* T2b = Cb + 2u * tileB;  // K >= 3 only
     unsigned char* Ab = Cb + (K >= 3 ? 3u : K == 2 ? 2u : 1u) * tileB;
     double* red = reinterpret_cast<double*>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -622,22 +674,24 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     };
 
     uint4 pa[NE], pc[NE];
+    TileWalk<NE> tw;
+    TileCursor cur = tw.init(a, tileE, pad);
     int64_t t = blockIdx.x;
     if (t < a.ntiles) {
-        fast_fetch<NE>(pa, a, xin, t, tileE);
-        fast_fetch<NE>(pc, a, cin, t, tileE);
+        tw.fetch(pa, xin, cur);
+        tw.fetch(pc, cin, cur);
     }
     const bool want_gx = a.out != nullptr;
     for (; t < a.ntiles; t += gridDim.x) {
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]), "+v"(GB[j]));
-        fast_commit<NE>(Ab, pa, pad);
-        fast_commit<NE>(Cb, pc, pad);
+        tw.commit(Ab, pa);
+        tw.commit(Cb, pc);
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if (tn < a.ntiles) {  // in flight while this tile is processed
-            fast_fetch<NE>(pa, a, xin, tn, tileE);
-            fast_fetch<NE>(pc, a, cin, tn, tileE);
+        const TileCursor nxt = tw.next(a, tileE, cur);
+        if (t + gridDim.x < a.ntiles) {  // in flight while this tile is processed
+            tw.fetch(pa, xin, nxt);
+            tw.fetch(pc, cin, nxt);
         }
         if constexpr (K >= 2) {
             pass(IntC<0>{}, Ab, T1b, fw);  // a_1
@@ -648,14 +702,17 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             __syncthreads();
         }
         if constexpr (K == 4) {
-            pass(IntC<2>{}, T2b, T2b, fw);  // a_3
+            // a_3 replaces a_1 (recomputed from A once digit 3 is done); the
+            // recompute shares the phase of digit 2, which reads only T2 and Ct
+            pass(IntC<2>{}, T2b, T1b, fw);  // a_3
             __syncthreads();
-            fused(IntC<3>{}, T2b, IntC<1>{});
+            fused(IntC<3>{}, T1b, IntC<1>{});
             __syncthreads();
-            pass(IntC<1>{}, T1b, T2b, fw);  // a_2 again
+            fused(IntC<2>{}, T2b, IntC<1>{});
+            pass(IntC<0>{}, Ab, T1b, fw);  // a_1 again
             __syncthreads();
         }
-        if constexpr (K >= 3) {
+        if constexpr (K == 3) {
             fused(IntC<2>{}, T2b, IntC<1>{});
             __syncthreads();
         }
@@ -670,9 +727,10 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             fused(IntC<0>{}, Ab, IntC<0>{});
         __syncthreads();
         if (want_gx) {
-            fast_store<NE>(Cb, a, static_cast<cf*>(a.out), t, tileE, pad);
+            tw.store(Cb, static_cast<cf*>(a.out), cur);
             __syncthreads();
         }
+        cur = nxt;
     }
     // reduce the waves' 16 x 16 blocks in a fixed order, then form the
     // complex gradient (row / column m = 8 comp + e)
