@@ -377,10 +377,7 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     a.out = out;
     a.W = W;
     a.adjoint = adjoint ? 1 : 0;
-    // one work-group per tile (the prefetching persistent variant of the
-    // tile loop measured slower on MI355X: its extra registers cost more
-    // occupancy than the overlap gains)
-    a.pf = 0;
+    // one work-group per tile
     const int64_t gmax = (int64_t)0x7fffffff;
     unsigned grid = (unsigned)std::min<int64_t>(g.ntiles, gmax);
     // complex radix-8 tiles of 2048 / 4096 elements: the matrix-core pass

@@ -42,7 +42,6 @@ struct PassArgs {
     int32_t mode;       // LoadMode
     int32_t pad_shift;  // LDS: one pad element after every 2^pad_shift elements
     int32_t cut_keep_high;  // with cut >= 0: keep natural indices >= cut instead of < cut
-    int32_t pf;             // software-pipelined (prefetching) tile loop
     int64_t cut;        // >= 0: zero the loaded elements by natural index (filter)
     int64_t S;          // place value of the group's lowest digit, b^s0
     int64_t L;          // column blocks per hi block, ceil(S / C)

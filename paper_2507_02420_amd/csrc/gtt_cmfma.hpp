@@ -124,13 +124,12 @@ __device__ __forceinline__ void cmfma_gw8(const cf* ct, const cf* at, const Pass
 }
 
 
-template <bool PF>
 __global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cf* lds = reinterpret_cast<cf*>(smem_raw);
     CFrag8 fr;
     load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
-    tile_loop<cf, cf, PF>(lds, a, [&](cf* t, uint32_t rows) {
+    tile_loop<cf, cf>(lds, a, [&](cf* t, uint32_t rows) {
         for (int j = 0; j < a.k; ++j) {
             cmfma_stage8(t, t, a, j, rows, fr);
             __syncthreads();

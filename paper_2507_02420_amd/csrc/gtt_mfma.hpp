@@ -151,13 +151,13 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     }
 }
 
-template <typename T, int B, bool PF>
+template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float* lds = reinterpret_cast<float*>(smem_raw);
     WFrag<T, B> wf;
     load_w_frag<T, B>(wf, a);
-    tile_loop<T, float, PF>(lds, a, [&](float* t, uint32_t rows) {
+    tile_loop<T, float>(lds, a, [&](float* t, uint32_t rows) {
         for (int j = 0; j < a.k; ++j) {
             mfma_stage<T, B>(t, a, j, rows, wf);
             __syncthreads();

@@ -284,83 +284,20 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
     }
 }
 
-// ---------------------------------------------------------------------------
-// Software-pipelined tile loop: the global loads of the work-group's next
-// tile are issued into registers before the current tile is transformed, so
-// HBM reads overlap the LDS / ALU / matrix-core work.  Tiles are assigned
-// statically (t = blockIdx.x + i * gridDim.x), so a prefetched tile is never
-// written by another work-group and in-place calls stay safe.
-// ---------------------------------------------------------------------------
-constexpr int kPrefVec = 8;     // 16-byte vectors per thread (tile <= 32 KiB)
-
-// 128 bytes of registers per thread: 8 vectors of 16 bytes
-struct TileBuf {
-    uint4 v[kPrefVec];
-};
-
-template <typename T>
-__device__ __forceinline__ void tile_fetch(TileBuf& buf, const PassArgs& a, const T* __restrict__ in, int64_t t,
-                                           uint32_t tileE) {
-    constexpr int V = Vec16<T>::V;
-    const bool contig = a.mode == kContigVec;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
-    const int64_t l = contig ? 0 : t - hb * a.L;
-    const uint32_t nvec = tileE / V;
-#pragma unroll
-    for (int v = 0; v < kPrefVec; ++v) {
-        const uint32_t i = threadIdx.x + v * kThreads;
-        if (i < nvec) buf.v[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
-    }
-}
-
-template <typename T, typename C>
-__device__ __forceinline__ void tile_commit(C* lds, const TileBuf& buf, const PassArgs& a, uint32_t tileE) {
-    constexpr int V = Vec16<T>::V;
-    const uint32_t nvec = tileE / V;
-#pragma unroll
-    for (int v = 0; v < kPrefVec; ++v) {
-        const uint32_t i = threadIdx.x + v * kThreads;
-        if (i < nvec) {
-            T vals[V];
-            *reinterpret_cast<uint4*>(vals) = buf.v[v];
-            const uint32_t ph = lds_phys(i * V, a.pad_shift);
-#pragma unroll
-            for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
-        }
-    }
-}
-
-// Runs stages(lds, rows) on every tile of this work-group, loading/storing
-// through the storage type T (compute type C in LDS).  PF: the software
-// pipelined variant (vector tile modes, at most kPrefVec vectors per thread,
-// no filter mask; the host only selects it then).
-template <typename T, typename C, bool PF, typename Stages>
+// Runs stages(lds, rows) on every tile of this work-group (t = blockIdx.x +
+// i * gridDim.x), loading and storing through the storage type T (compute
+// type C in LDS).
+template <typename T, typename C, typename Stages>
 __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& stages) {
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    const uint32_t tileE = rows << a.logC;
     const T* in = static_cast<const T*>(a.in);
     T* out = static_cast<T*>(a.out);
-    if constexpr (PF) {
-        TileBuf buf;
-        int64_t t = blockIdx.x;
-        if (t < a.ntiles) tile_fetch<T>(buf, a, in, t, tileE);
-        for (; t < a.ntiles; t += gridDim.x) {
-            tile_commit<T, C>(lds, buf, a, tileE);
-            __syncthreads();
-            const int64_t tn = t + gridDim.x;
-            if (tn < a.ntiles) tile_fetch<T>(buf, a, in, tn, tileE);
-            stages(lds, rows);
-            tile_store<T, C>(lds, a, out, t, rows);
-            __syncthreads();
-        }
-    } else {
-        for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-            tile_load<T, C>(lds, a, in, t, rows);
-            __syncthreads();
-            stages(lds, rows);
-            tile_store<T, C>(lds, a, out, t, rows);
-            __syncthreads();
-        }
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, C>(lds, a, in, t, rows);
+        __syncthreads();
+        stages(lds, rows);
+        tile_store<T, C>(lds, a, out, t, rows);
+        __syncthreads();
     }
 }
 
@@ -388,7 +325,7 @@ __device__ __forceinline__ void load_w(C (&w)[B * B], const PassArgs& a) {
     }
 }
 
-template <typename T, int B, bool PF>
+template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     using C = typename Tr<T>::C;
     constexpr int RD = RegDigits<B>::v;
@@ -396,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     C* lds = reinterpret_cast<C*>(smem_raw);
     C w[B * B];
     load_w<C, B>(w, a);
-    tile_loop<T, C, PF>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
+    tile_loop<T, C>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
 }
 
 }  // namespace gtt

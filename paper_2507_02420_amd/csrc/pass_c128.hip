@@ -27,10 +27,10 @@ hipError_t launch_pass_c128(int b, int kind, const PassArgs& a, unsigned grid, s
         return hipErrorInvalidValue;
     } else {
         switch (b) {
-            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2, false>)); break;
-            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3, false>)); break;
-            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4, false>)); break;
-            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5, false>)); break;
+            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
+            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3>)); break;
+            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4>)); break;
+            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5>)); break;
             default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
         }
     }

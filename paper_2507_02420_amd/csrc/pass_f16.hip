@@ -25,20 +25,20 @@ hipError_t launch_pass_f16(int b, int kind, const PassArgs& a, unsigned grid, si
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
         if (b == 16)
-            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 16, false>));
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 16>));
         else if (b == 32)
-            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 32, false>));
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 32>));
         else
             return hipErrorInvalidValue;
     } else {
         switch (b) {
-            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2, false>)); break;
-            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3, false>)); break;
-            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4, false>)); break;
-            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5, false>)); break;
-            case 6: GTT_LAUNCH((gtt_pass_kernel<T, 6, false>)); break;
-            case 7: GTT_LAUNCH((gtt_pass_kernel<T, 7, false>)); break;
-            case 8: GTT_LAUNCH((gtt_pass_kernel<T, 8, false>)); break;
+            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
+            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3>)); break;
+            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4>)); break;
+            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5>)); break;
+            case 6: GTT_LAUNCH((gtt_pass_kernel<T, 6>)); break;
+            case 7: GTT_LAUNCH((gtt_pass_kernel<T, 7>)); break;
+            case 8: GTT_LAUNCH((gtt_pass_kernel<T, 8>)); break;
             default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
         }
     }
