@@ -73,10 +73,16 @@ typedef enum gtt_dtype {
 } gtt_dtype;
 
 /* Plan flags (bit set). */
-#define GTT_FLAG_FP32_INTERMEDIATE 0x1u /* bf16/f16: keep the values between
-                                           digit groups in float32 inside the
-                                           workspace instead of the storage
-                                           dtype */
+#define GTT_FLAG_FP32_INTERMEDIATE 0x1u /* bf16/f16 uniform plans: convert
+                                           the operands to float32 inside the
+                                           workspace, run every digit group in
+                                           float32 and round to the storage
+                                           dtype once, at the end (saved
+                                           activations are then float32).
+                                           No effect on the other dtypes;
+                                           GTT_ERR_UNSUPPORTED for ragged and
+                                           mixed-radix plans, and from
+                                           gtt_filter / gtt_compress */
 #define GTT_FLAG_NO_TUNE 0x2u           /* ignore the tuning table; use the
                                            built-in heuristics */
 #define GTT_FLAG_PERSISTENT 0x4u        /* ragged batch: run every digit group
@@ -108,7 +114,8 @@ typedef struct gtt_plan_s* gtt_plan_t;
  * n == 0 is allowed (N = 1, the identity; base case of §2.2).
  * Errors: GTT_ERR_SHAPE (b < 2, n < 0, b^n overflows, batch < 1),
  * GTT_ERR_DTYPE, GTT_ERR_INVALID_VALUE (out == NULL, count < 1, bad
- * w_idx / x_off), GTT_ERR_UNSUPPORTED.  On error *out is set to NULL.
+ * w_idx / x_off), GTT_ERR_UNSUPPORTED (GTT_FLAG_FP32_INTERMEDIATE with
+ * count > 1).  On error *out is set to NULL.
  * The plan holds host memory and, for ragged batches, a device work list
  * (one descriptor per instance and digit group, one entry per tile) and the
  * grid-barrier words, allocated and uploaded by the first forward / inverse

@@ -468,6 +468,48 @@ static bool pow_fits(int64_t b, int64_t n, int64_t* out) {
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// ---------------------------------------------------------------------------
+// GTT_FLAG_FP32_INTERMEDIATE (16-bit storage): convert the operands to
+// float32 in the workspace, run the float32 plan there (in place), convert
+// the results back (round to nearest even).
+// ---------------------------------------------------------------------------
+static size_t f32_buf_bytes(const gtt_plan_s* p) {
+    return (((size_t)p->total_elems * sizeof(float)) + 255) & ~(size_t)255;
+}
+
+static gtt_status f32_apply(gtt_plan_s* p, const void* W, const void* in, void* out, void* saved, void* ws,
+                            size_t ws_bytes, bool adjoint, hipStream_t s) {
+    size_t fi = 0, bi = 0, si = 0;
+    workspace_sizes(p->inner, &fi, &bi, &si);
+    const size_t buf = f32_buf_bytes(p);
+    if (!ws || ws_bytes < buf + fi) return GTT_ERR_WORKSPACE;
+    char* xf = static_cast<char*>(ws);
+    const DT dt = to_dt(p->dtype);
+    const int64_t E = p->total_elems;
+    if (launch_convert(dt, DT::F32, in, xf, E, s) != hipSuccess) return GTT_ERR_HIP;
+    gtt_status st = adjoint ? gtt_inverse(p->inner, W, xf, xf, fi ? xf + buf : nullptr, fi, s)
+                            : gtt_forward(p->inner, W, xf, xf, saved, fi ? xf + buf : nullptr, fi, s);
+    if (st != GTT_OK) return st;
+    return launch_convert(DT::F32, dt, xf, out, E, s) == hipSuccess ? GTT_OK : GTT_ERR_HIP;
+}
+
+static gtt_status f32_backward(gtt_plan_s* p, const void* W, const void* x, const void* saved, const void* gy,
+                               void* gx, void* gW, void* ws, size_t ws_bytes, hipStream_t s) {
+    // the inner plan checks the rest of the workspace against its own needs
+    const size_t buf = f32_buf_bytes(p);
+    if (!ws || ws_bytes < 2 * buf) return GTT_ERR_WORKSPACE;
+    char* xf = static_cast<char*>(ws);
+    char* gf = xf + buf;
+    const DT dt = to_dt(p->dtype);
+    const int64_t E = p->total_elems;
+    if (launch_convert(dt, DT::F32, x, xf, E, s) != hipSuccess) return GTT_ERR_HIP;
+    if (launch_convert(dt, DT::F32, gy, gf, E, s) != hipSuccess) return GTT_ERR_HIP;
+    gtt_status st = gtt_backward(p->inner, W, xf, saved, gf, gx ? gf : nullptr, gW, gf + buf,
+                                 ws_bytes - 2 * buf, s);
+    if (st != GTT_OK || !gx) return st;
+    return launch_convert(DT::F32, dt, gf, gx, E, s) == hipSuccess ? GTT_OK : GTT_ERR_HIP;
+}
+
 gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n, int64_t batch,
                     const int64_t* x_off, const int32_t* w_idx, gtt_dtype dtype, uint32_t flags) {
     if (!out) return GTT_ERR_INVALID_VALUE;
@@ -476,7 +518,7 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
     if (!valid_dtype((int)dtype)) return GTT_ERR_DTYPE;
     if (flags & ~(GTT_FLAG_FP32_INTERMEDIATE | GTT_FLAG_NO_TUNE | GTT_FLAG_PERSISTENT | GTT_FLAG_PER_INSTANCE))
         return GTT_ERR_INVALID_VALUE;
-    if (flags & GTT_FLAG_FP32_INTERMEDIATE) return GTT_ERR_UNSUPPORTED;
+    if ((flags & GTT_FLAG_FP32_INTERMEDIATE) && count != 1) return GTT_ERR_UNSUPPORTED;
     if (batch < 1) return GTT_ERR_SHAPE;
     if (count == 1 && (x_off || w_idx)) return GTT_ERR_INVALID_VALUE;
     if (count > 1 && batch != 1) return GTT_ERR_SHAPE;
@@ -505,6 +547,10 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
         st = plan_groups(p->rad, batch, dtype, flags, true, &p->groups, &p->bwd_groups);
         p->total_elems = p->N * batch;
         p->w_elems = (int64_t)b[0] * b[0];
+        // float32 between digit groups: only the 16-bit storage types keep
+        // less (the other dtypes already compute and store in >= 32 bits)
+        if (st == GTT_OK && (flags & GTT_FLAG_FP32_INTERMEDIATE) && (dtype == GTT_BF16 || dtype == GTT_F16))
+            st = gtt_plan(&p->inner, 1, b, n, batch, nullptr, nullptr, GTT_F32, flags & ~GTT_FLAG_FP32_INTERMEDIATE);
     } else {
         st = plan_ragged(p, count, b, n, x_off, w_idx);
     }
@@ -568,6 +614,7 @@ gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, in
 
 gtt_status gtt_plan_destroy(gtt_plan_t p) {
     if (!p) return GTT_OK;
+    if (p->inner) gtt_plan_destroy(p->inner);
     destroy_ragged(p);
     delete p;
     return GTT_OK;
@@ -576,7 +623,15 @@ gtt_status gtt_plan_destroy(gtt_plan_t p) {
 gtt_status gtt_workspace_size(gtt_plan_t p, size_t* fwd, size_t* bwd, size_t* saved) {
     if (!p) return GTT_ERR_INVALID_VALUE;
     size_t f = 0, bw = 0, sv = 0;
-    workspace_sizes(p, &f, &bw, &sv);
+    if (p->inner) {
+        // float32 copies of the operands ahead of the inner plan's workspace
+        workspace_sizes(p->inner, &f, &bw, &sv);
+        const size_t buf = f32_buf_bytes(p);
+        f += buf;
+        bw += 2 * buf;
+    } else {
+        workspace_sizes(p, &f, &bw, &sv);
+    }
     if (fwd) *fwd = f;
     if (bwd) *bwd = bw;
     if (saved) *saved = sv;
@@ -589,9 +644,8 @@ gtt_status gtt_forward(gtt_plan_t p, const void* W, const void* x, void* y, void
     if (!aligned16(x) || !aligned16(y) || !aligned16(W) || (saved && !aligned16(saved)) ||
         (ws && !aligned16(ws)))
         return GTT_ERR_ALIGNMENT;
-    (void)ws;
-    (void)ws_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->inner) return f32_apply(p, W, x, y, saved, ws, ws_bytes, false, s);
     if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, x, y, false, (char*)saved, s);
     return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, y, (char*)saved,
                       (size_t)p->total_elems, s);
@@ -601,9 +655,8 @@ gtt_status gtt_inverse(gtt_plan_t p, const void* W, const void* y, void* x, void
                        void* stream) {
     if (!p || !W || !x || !y) return GTT_ERR_INVALID_VALUE;
     if (!aligned16(x) || !aligned16(y) || !aligned16(W) || (ws && !aligned16(ws))) return GTT_ERR_ALIGNMENT;
-    (void)ws;
-    (void)ws_bytes;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->inner) return f32_apply(p, W, y, x, nullptr, ws, ws_bytes, true, s);
     if (p->kind == PlanKind::Ragged) return ragged_apply(p, W, y, x, true, nullptr, s);
     // the adjoint applies W^H per digit; digit passes commute, so the group
     // order of the forward plan is reused as is
@@ -621,12 +674,18 @@ gtt_status gtt_plan_describe(gtt_plan_t p, char* buf, size_t len) {
 gtt_status gtt_plan_timing(gtt_plan_t p, int32_t enable) {
     if (!p) return GTT_ERR_INVALID_VALUE;
     p->timing.enabled = enable != 0;
+    if (p->inner) p->inner->timing.enabled = enable != 0;
     return GTT_OK;
 }
 
 gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len) {
     if (!p || !buf || len == 0) return GTT_ERR_INVALID_VALUE;
     std::string s = timing_read(p);
+    if (p->inner) {
+        // one JSON object: the conversions, then the float32 launches
+        const std::string in = timing_read(p->inner);
+        if (in.size() > 2) s = (s.size() > 2 ? s.substr(0, s.size() - 1) + "," : std::string("{")) + in.substr(1);
+    }
     std::snprintf(buf, len, "%s", s.c_str());
     return GTT_OK;
 }
@@ -707,6 +766,7 @@ gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* 
         (saved && !aligned16(saved)) || (ws && !aligned16(ws)))
         return GTT_ERR_ALIGNMENT;
     if (p->dtype == GTT_I32 || p->kind == PlanKind::Mixed) return GTT_ERR_UNSUPPORTED;
+    if (p->inner) return f32_backward(p, W, x, saved, gy, gx, gW, ws, ws_bytes, static_cast<hipStream_t>(stream));
     return backward_impl(p, W, x, saved, gy, gx, gW, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
@@ -716,7 +776,7 @@ gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff
     if (!aligned16(W) || !aligned16(x) || (low && !aligned16(low)) || (high && !aligned16(high)) ||
         (ws && !aligned16(ws)))
         return GTT_ERR_ALIGNMENT;
-    if (p->kind != PlanKind::Uniform || p->dtype == GTT_I32) return GTT_ERR_UNSUPPORTED;
+    if (p->kind != PlanKind::Uniform || p->dtype == GTT_I32 || p->inner) return GTT_ERR_UNSUPPORTED;
     if (cutoff < 0) return GTT_ERR_INVALID_VALUE;
     return filter_impl(p, W, x, cutoff, low, high, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
@@ -756,7 +816,7 @@ extern "C" gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, i
     if (!aligned16(W) || !aligned16(x) || !aligned16(idx) || !aligned16(val) || (recon && !aligned16(recon)) ||
         (ws && !aligned16(ws)))
         return GTT_ERR_ALIGNMENT;
-    if (p->kind != PlanKind::Uniform) return GTT_ERR_UNSUPPORTED;
+    if (p->kind != PlanKind::Uniform || p->inner) return GTT_ERR_UNSUPPORTED;
     if (k < 1 || k > p->N) return GTT_ERR_INVALID_VALUE;
     size_t f = 0, bw = 0, sv = 0;
     workspace_sizes(p, &f, &bw, &sv);

@@ -40,6 +40,9 @@ hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, si
 hipError_t launch_topk(DT dt, const void* coef, int64_t N, int64_t batch, int64_t k, int64_t* idx, void* val,
                        void* recon, hipStream_t s);
 
+// elementwise storage conversion bf16/f16 <-> float32 (RNE to 16 bits)
+hipError_t launch_convert(DT from, DT to, const void* in, void* out, int64_t n, hipStream_t s);
+
 struct RaggedArgs;
 // ragged-batch launch (all phases with grid barriers, or one phase)
 hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s);

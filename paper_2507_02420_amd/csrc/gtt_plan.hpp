@@ -95,6 +95,9 @@ struct gtt_plan_s {
     std::vector<int64_t> w_off;   // element offset of W table entry
     gtt::RaggedState* rs = nullptr;
     gtt::Timing timing;
+    // GTT_FLAG_FP32_INTERMEDIATE on a 16-bit storage dtype: the same
+    // transform planned in float32; calls convert at the boundaries and run it
+    gtt_plan_s* inner = nullptr;
 };
 
 namespace gtt {

@@ -414,15 +414,17 @@ std::string describe_plan(const gtt_plan_s* p) {
                   kind, (int)p->dtype, p->b, p->n, (long long)p->N, (long long)p->batch);
     s += head;
     if (p->kind != PlanKind::Ragged) {
-        s += "\"groups\":[";
-        for (size_t i = 0; i < p->groups.size(); ++i) {
+        // with a float32 inner plan, its digit groups are the ones that run
+        const gtt_plan_s* q = p->inner ? p->inner : p;
+        s += p->inner ? "\"fp32_intermediate\":true,\"groups\":[" : "\"groups\":[";
+        for (size_t i = 0; i < q->groups.size(); ++i) {
             if (i) s += ",";
-            s += grp(p->groups[i]);
+            s += grp(q->groups[i]);
         }
         s += "],\"bwd_groups\":[";
-        for (size_t i = 0; i < p->bwd_groups.size(); ++i) {
+        for (size_t i = 0; i < q->bwd_groups.size(); ++i) {
             if (i) s += ",";
-            s += grp(p->bwd_groups[i]);
+            s += grp(q->bwd_groups[i]);
         }
         s += "]";
     } else {

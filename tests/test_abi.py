@@ -154,3 +154,37 @@ def test_planner_layouts_match_compiled_specializations():
     bwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"]) for g in d["bwd_groups"]]
     assert fwd == [(4, 2, 1, 0x1f0a05, 0x1e001b00270017), (2, 2, 64, 0x1f0a05, 0x1e001b)]
     assert bwd == [(4, 2, 1, 0x1f0905, 0x31d081b01270817), (2, 2, 64, 0x1f0905, 0x31d081b)]
+
+
+def test_fp32_intermediate_plan_sizes_and_limits():
+    L = G.lib()
+    F = G.FLAG_FP32_INTERMEDIATE
+    b, n, batch = 4, 8, 3
+    E = batch * b ** n
+    buf = (E * 4 + 255) // 256 * 256
+    for dt in (torch.bfloat16, torch.float16):
+        p, q = G.Plan(b, n, batch, dt, flags=F), G.Plan(b, n, batch, torch.float32)
+        (f, bw, sv), (f0, bw0, sv0) = p.workspace_size(), q.workspace_size()
+        # float32 operand copies ahead of the float32 plan's workspace;
+        # saved activations are float32
+        assert (f, bw, sv) == (f0 + buf, bw0 + 2 * buf, sv0)
+        d = p.describe()
+        assert d["fp32_intermediate"] is True and d["dtype"] == G.TORCH_TO_GTT[dt]
+        assert [g["k"] for g in d["groups"]] == [g["k"] for g in q.describe()["groups"]]
+    # filter and compress refuse such plans before any HIP call
+    hp = G.Plan(b, n, batch, torch.bfloat16, flags=F)
+    buf16 = ctypes.c_void_p(256)
+    assert L.gtt_filter(hp.handle, buf16, buf16, 3, buf16, buf16, buf16, 1 << 30, None) == 6
+    assert L.gtt_compress(hp.handle, buf16, buf16, 3, buf16, buf16, buf16, buf16, 1 << 30, None) == 6
+    # too small a workspace is refused before any HIP call
+    assert L.gtt_forward(hp.handle, buf16, buf16, buf16, None, buf16, 16, None) == 5
+    assert L.gtt_forward(hp.handle, buf16, buf16, buf16, None, None, 0, None) == 5
+    assert L.gtt_backward(hp.handle, buf16, buf16, None, buf16, buf16, buf16, buf16, 16, None) == 5
+    # ragged and mixed-radix plans: unsupported
+    assert _plan(2, [2, 4], [4, 2], dtype=G.BF16, flags=F)[0] == 6
+    h = ctypes.c_void_p()
+    assert L.gtt_plan_mixed(ctypes.byref(h), 2, (ctypes.c_int32 * 2)(2, 3), 1, G.BF16, F) == 6
+    # the flag alone on float32 / int32 plans changes nothing
+    assert (G.Plan(b, n, batch, torch.float32, flags=F).workspace_size()
+            == G.Plan(b, n, batch, torch.float32).workspace_size())
+    assert "fp32_intermediate" not in G.Plan(b, n, batch, torch.int32, flags=F).describe()

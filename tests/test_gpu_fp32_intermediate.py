@@ -1,0 +1,86 @@
+"""GTT_FLAG_FP32_INTERMEDIATE on 16-bit storage: every digit group runs in
+float32 and the result is rounded to the storage dtype once.  Each output
+element is then the correctly rounded oracle value up to the float32 error,
+i.e. within half a unit in the last place of the storage dtype plus a float32
+term; without the flag the intermediate roundings between digit groups add
+up (compared on multi-group shapes)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import TOL, host64, make_inputs, rel_err, say
+from oracle import gtt_oracle as O
+from paper_2507_02420_amd import gtt as G
+from paper_2507_02420_amd.inputs import gaussian
+
+pytestmark = pytest.mark.gpu
+
+# unit roundoff (half an ulp, relative) of the storage dtypes
+U = {torch.bfloat16: 2.0 ** -8, torch.float16: 2.0 ** -11}
+F = G.FLAG_FP32_INTERMEDIATE
+
+
+def _rounded_once(y, ref, dtype):
+    # |y_i - ref_i| <= u |ref_i| (one rounding) + a float32 error term
+    f32 = 1e-5 * np.max(np.abs(ref))
+    bound = U[dtype] * (np.abs(ref) + f32) + f32
+    return np.all(np.abs(y - ref) <= bound), float(np.max(np.abs(y - ref) - bound))
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=str)
+@pytest.mark.parametrize("b,n,batch", [(2, 12, 2), (2, 17, 1), (3, 9, 2), (4, 8, 3), (8, 5, 2), (16, 3, 2),
+                                       (32, 2, 3), (5, 1, 4)])
+def test_forward_inverse_rounded_once(b, n, batch, dtype):
+    say(f"fp32-intermediate forward/inverse b={b} n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=8100 + 13 * b + n)
+    plan = G.Plan(b, n, batch, dtype, flags=F)
+    assert plan.describe().get("fp32_intermediate") is True
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, x)
+    y0 = G.Plan(b, n, batch, dtype).forward(W, x)
+    torch.cuda.synchronize()
+    ref = O.staged(W64, x64, n)
+    ok, slack = _rounded_once(host64(y), ref, dtype)
+    assert ok, (b, n, dtype, slack)
+    ok, slack = _rounded_once(host64(xi), O.adjoint(W64, x64, n), dtype)
+    assert ok, (b, n, dtype, slack)
+    e1, e0 = rel_err(host64(y), ref), rel_err(host64(y0), ref)
+    say(f"  rel err with flag {e1:.3e}, without {e0:.3e}")
+    assert e1 < TOL[dtype] and e1 <= e0 * 1.05 + 1e-7
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=str)
+@pytest.mark.parametrize("b,n,batch,use_saved", [(4, 8, 2, True), (4, 8, 2, False), (8, 5, 2, True),
+                                                 (3, 7, 3, False), (16, 3, 1, True)])
+def test_backward(b, n, batch, dtype, use_saved):
+    say(f"fp32-intermediate backward b={b} n={n} batch={batch} dtype={dtype} saved={use_saved}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=8300 + b + n)
+    g = torch.from_numpy(gaussian((batch, b ** n), seed=8400 + b + n)).to(dtype).cuda()
+    plan = G.Plan(b, n, batch, dtype, flags=F)
+    saved = None
+    if use_saved:
+        _, _, sv = plan.workspace_size()
+        saved = torch.empty(max(sv, 16), dtype=torch.uint8, device="cuda")
+        plan.forward(W, x, saved=saved)
+    gx, gW = plan.backward(W, x, g, saved=saved)
+    g2 = g.clone()
+    gx2, gW2 = plan.backward(W, x, g2, saved=saved, gx=g2)      # gx aliases gy
+    _, gW3 = plan.backward(W, x, g, saved=saved, want_gx=False)
+    torch.cuda.synchronize()
+    rgx, rgW = O.grad(W64, x64, host64(g), n)
+    ok, slack = _rounded_once(host64(gx), rgx, dtype)
+    assert ok, slack
+    # the weight gradient is float32 (W's dtype): float32 accuracy
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-4
+    assert torch.equal(gx2, gx) and torch.equal(gW2, gW) and torch.equal(gW3, gW)
+
+
+def test_flag_is_a_no_op_for_wider_dtypes():
+    b, n, batch = 4, 7, 2
+    for dtype in (torch.float32, torch.complex64, torch.float64):
+        x, W, _, _ = make_inputs(b, n, batch, dtype, seed=8500)
+        p1, p0 = G.Plan(b, n, batch, dtype, flags=F), G.Plan(b, n, batch, dtype)
+        assert p1.workspace_size() == p0.workspace_size()
+        y1, y0 = p1.forward(W, x), p0.forward(W, x)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y0), dtype
