@@ -370,29 +370,26 @@ __device__ __forceinline__ void cpass8_load(PassRegs<NI>& r, const unsigned char
         const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
         r.x0[it] = *reinterpret_cast<const cf*>(src + p0 + so);
         r.x1[it] = *reinterpret_cast<const cf*>(src + p1 + so);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// the steps' MFMA chains interleaved, then the stores
+// step by step: the MFMA chain of a step and its stores, then the next
+// step (whose loads may still be in flight while the first one computes)
 template <int NI>
 __device__ __forceinline__ void cpass8_compute_store(const PassRegs<NI>& r, unsigned char* dst, uint32_t p0,
                                                      uint32_t p1, uint32_t h, int pad, const CFrag8& fr) {
-    f32x4_c acc[NI];
-#pragma unroll
-    for (int it = 0; it < NI; ++it) acc[it] = f32x4_c{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], r.x0[it].re, acc[it], 0, 0, 0);
-#pragma unroll
-    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], r.x0[it].im, acc[it], 0, 0, 0);
-#pragma unroll
-    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], r.x1[it].re, acc[it], 0, 0, 0);
-#pragma unroll
-    for (int it = 0; it < NI; ++it) acc[it] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], r.x1[it].im, acc[it], 0, 0, 0);
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], r.x0[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], r.x0[it].im, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], r.x1[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], r.x1[it].im, acc, 0, 0, 0);
         const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
-        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[it][0], acc[it][1]};
-        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[it][2], acc[it][3]};
+        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[0], acc[1]};
+        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[2], acc[3]};
     }
 }
 
@@ -627,47 +624,61 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
         cpass8<NI>(src, dst, P0[j], P1[j], (uint32_t)logC + 3u * j, pad, fr);
     };
     // gradient sums of digit J (cotangent in Ct, activation act), then the
-    // adjoint pass on Ct along J (skipped when ADJ is false).  Per step, all
-    // LDS loads are issued before the first MFMA; the adjoint pass rewrites
-    // only fibres this wave has just read.
-    auto fused = [&](auto J, const unsigned char* act, auto ADJ) {
+    // adjoint pass on Ct along J (skipped when ADJ is false); with RE, also
+    // the pass of digit 0 from A into T1 (a_1 recomputed), whose operands
+    // do not depend on the rest of the phase.  Every LDS load of the phase
+    // is issued before the first MFMA, in the order of use, so the MFMAs of
+    // the first step run while the later loads are still in flight.  The
+    // adjoint pass rewrites only fibres this wave has just read.
+    auto fused = [&](auto J, const unsigned char* act, auto ADJ, auto RE) {
         constexpr int j = decltype(J)::value;
         constexpr bool adj = decltype(ADJ)::value != 0;
+        constexpr bool re = decltype(RE)::value != 0;
         const uint32_t h = (uint32_t)logC + 3u * j;
-        f32x4_c M = {0.f, 0.f, 0.f, 0.f};
+        float cv[NI][4], av[NI][4];
+        cf x0[NI], x1[NI];
+        PassRegs<NI> rr;
 #pragma unroll
         for (int it = 0; it < NI; ++it) {
-            float cv[4], av[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t o = GB[j] + goff(j, 4 * it + u);
-                cv[u] = *reinterpret_cast<const float*>(Cb + o);
-                av[u] = *reinterpret_cast<const float*>(act + o);
+                cv[it][u] = *reinterpret_cast<const float*>(Cb + o);
+                av[it][u] = *reinterpret_cast<const float*>(act + o);
             }
-            cf x0 = {0.f, 0.f}, x1 = {0.f, 0.f};
-            const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
             if constexpr (adj) {
-                x0 = *reinterpret_cast<const cf*>(Cb + P0[j] + so);
-                x1 = *reinterpret_cast<const cf*>(Cb + P1[j] + so);
+                const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+                x0[it] = *reinterpret_cast<const cf*>(Cb + P0[j] + so);
+                x1[it] = *reinterpret_cast<const cf*>(Cb + P1[j] + so);
             }
             __builtin_amdgcn_sched_barrier(0);
-            f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+        }
+        if constexpr (re) cpass8_load<NI>(rr, Ab, P0[0], P1[0], (uint32_t)logC, pad);
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4_c M = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            __builtin_amdgcn_sched_barrier(0);
             if constexpr (adj) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[0], x0.re, acc, 0, 0, 0);
-                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[0], av[0], M, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[1], x0.im, acc, 0, 0, 0);
-                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[1], av[1], M, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[2], x1.re, acc, 0, 0, 0);
-                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[2], av[2], M, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[3], x1.im, acc, 0, 0, 0);
-                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[3], av[3], M, 0, 0, 0);
+                const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+                f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[0], x0[it].re, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][0], av[it][0], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[1], x0[it].im, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][1], av[it][1], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[2], x1[it].re, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][2], av[it][2], M, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[3], x1[it].im, acc, 0, 0, 0);
+                M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][3], av[it][3], M, 0, 0, 0);
                 *reinterpret_cast<cf*>(Cb + P0[j] + so) = cf{acc[0], acc[1]};
                 *reinterpret_cast<cf*>(Cb + P1[j] + so) = cf{acc[2], acc[3]};
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[u], av[u], M, 0, 0, 0);
+                for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][u], av[it][u], M, 0, 0, 0);
             }
         }
+        if constexpr (re) cpass8_compute_store<NI>(rr, T1b, P0[0], P1[0], (uint32_t)logC, pad, fw);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Md[v] += (double)M[v];
     };
@@ -705,25 +716,24 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             // recompute shares the phase of digit 2, which reads only T2 and Ct
             pass(IntC<2>{}, T2b, T1b, fw);  // a_3
             __syncthreads();
-            fused(IntC<3>{}, T1b, IntC<1>{});
+            fused(IntC<3>{}, T1b, IntC<1>{}, IntC<0>{});
             __syncthreads();
-            fused(IntC<2>{}, T2b, IntC<1>{});
-            pass(IntC<0>{}, Ab, T1b, fw);  // a_1 again
+            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<1>{});  // and a_1 again
             __syncthreads();
         }
         if constexpr (K == 3) {
-            fused(IntC<2>{}, T2b, IntC<1>{});
+            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<0>{});
             __syncthreads();
         }
         if constexpr (K >= 2) {
-            fused(IntC<1>{}, T1b, IntC<1>{});
+            fused(IntC<1>{}, T1b, IntC<1>{}, IntC<0>{});
             __syncthreads();
         }
         // out is null for the first digit group when only gW is wanted
         if (want_gx)
-            fused(IntC<0>{}, Ab, IntC<1>{});
+            fused(IntC<0>{}, Ab, IntC<1>{}, IntC<0>{});
         else
-            fused(IntC<0>{}, Ab, IntC<0>{});
+            fused(IntC<0>{}, Ab, IntC<0>{}, IntC<0>{});
         __syncthreads();
         if (want_gx) {
             tw.store(Cb, static_cast<cf*>(a.out), cur);
