@@ -576,9 +576,18 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
 //   digit 1 (T1); digit 0 (A).
 // K = 3 keeps a_1, a_2; K = 2 keeps a_1.  In the gradient sums, row
 // m = 8 comp + e of the real 16 x 16 block is component comp of element e.
-template <int K, int NI, class LAY>
+//
+// D0 (contiguous tiles whose digit 0 has stride 1): a lane's two pass
+// elements of a digit-0 fibre are 16 contiguous bytes in global memory, and
+// every fibre is one aligned 64-byte segment.  The group input is then
+// loaded straight in the digit-0 pass layout, so a_1 is computed from the
+// registers in the phase that stores A, and the adjoint pass of digit 0
+// writes gx straight to global memory: two phases and their LDS round trips
+// fewer per tile.
+template <int K, int NI, class LAY, bool D0 = false>
 __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBwdArgs ba) {
     static_assert(K >= 1 && K <= 4 && NI >= 1 && NI <= 2, "tile shape");
+    static_assert(!D0 || (K >= 2 && LAY::kFixed), "direct digit-0 I/O: fixed layouts, two digits or more");
     const PassArgs& a = ba.p;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr uint32_t tileE = 2048u * NI;
@@ -617,6 +626,25 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     double Md[4] = {0.0, 0.0, 0.0, 0.0};
     const cf* xin = static_cast<const cf*>(a.in);
     const cf* cin = static_cast<const cf*>(ba.c_out);
+    cf* gxo = static_cast<cf*>(a.out);
+    // one wave of each SIMD per priority level: after a barrier, the LDS
+    // serves the top wave of every SIMD first, which then starts its MFMAs
+    // while the others still load, instead of all waves waiting together
+    switch (wave >> 2) {
+        case 0: __builtin_amdgcn_s_setprio(3); break;
+        case 1: __builtin_amdgcn_s_setprio(2); break;
+        case 2: __builtin_amdgcn_s_setprio(1); break;
+        default: break;
+    }
+    if constexpr (D0) static_assert(LAY::kLogC == 0, "direct digit-0 I/O: digit 0 has stride 1");
+    // D0: tile position of element 2q of this lane's digit-0 fibre, step it
+    uint32_t dpos[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const DigitMap d = digit_map(fmap, 0);
+        const uint32_t f = 256u * it | deposit8((uint32_t)wave, ~d.mask & 0xffu) | deposit8(lo, d.mask);
+        dpos[it] = (f << 3) | (2u * hi);
+    }
 
     // W (fragments fr) along digit J: src -> dst (in place when equal)
     auto pass = [&](auto J, const unsigned char* src, unsigned char* dst, const CFrag8& fr) {
@@ -630,10 +658,12 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     // is issued before the first MFMA, in the order of use, so the MFMAs of
     // the first step run while the later loads are still in flight.  The
     // adjoint pass rewrites only fibres this wave has just read.
-    auto fused = [&](auto J, const unsigned char* act, auto ADJ, auto RE) {
+    auto fused = [&](auto J, const unsigned char* act, auto ADJ, auto RE, auto OUT, int64_t origin) {
         constexpr int j = decltype(J)::value;
         constexpr bool adj = decltype(ADJ)::value != 0;
         constexpr bool re = decltype(RE)::value != 0;
+        constexpr bool direct = decltype(OUT)::value != 0;  // D0, digit 0: result to gx
+        static_assert(!direct || j == 0, "direct output: digit 0 only");
         const uint32_t h = (uint32_t)logC + 3u * j;
         float cv[NI][4], av[NI][4];
         cf x0[NI], x1[NI];
@@ -670,8 +700,12 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
                 M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][2], av[it][2], M, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[3], x1[it].im, acc, 0, 0, 0);
                 M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][3], av[it][3], M, 0, 0, 0);
-                *reinterpret_cast<cf*>(Cb + P0[j] + so) = cf{acc[0], acc[1]};
-                *reinterpret_cast<cf*>(Cb + P1[j] + so) = cf{acc[2], acc[3]};
+                if constexpr (direct) {
+                    *reinterpret_cast<f32x4_c*>(gxo + origin + dpos[it]) = acc;
+                } else {
+                    *reinterpret_cast<cf*>(Cb + P0[j] + so) = cf{acc[0], acc[1]};
+                    *reinterpret_cast<cf*>(Cb + P1[j] + so) = cf{acc[2], acc[3]};
+                }
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][u], av[it][u], M, 0, 0, 0);
@@ -686,24 +720,51 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     uint4 pa[NE], pc[NE];
     TileWalk<NE> tw;
     TileCursor cur = tw.init(a, tileE, pad);
+    // the group input: tile layout, or (D0) the digit-0 pass layout
+    auto fetch_a = [&](const TileCursor& c) {
+        if constexpr (D0) {
+#pragma unroll
+            for (int it = 0; it < NI; ++it) pa[it] = *reinterpret_cast<const uint4*>(xin + c.origin + dpos[it]);
+        } else {
+            tw.fetch(pa, xin, c);
+        }
+    };
     int64_t t = blockIdx.x;
     if (t < a.ntiles) {
-        tw.fetch(pa, xin, cur);
+        fetch_a(cur);
         tw.fetch(pc, cin, cur);
     }
     const bool want_gx = a.out != nullptr;
     for (; t < a.ntiles; t += gridDim.x) {
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]), "+v"(GB[j]));
-        tw.commit(Ab, pa);
-        tw.commit(Cb, pc);
-        __syncthreads();
+        if constexpr (D0) {
+            // A into its slot and a_1 = W_0 A into T1, both from registers
+            PassRegs<NI> r;
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                cf v[2];
+                *reinterpret_cast<uint4*>(v) = pa[it];
+                r.x0[it] = v[0];
+                r.x1[it] = v[1];
+                const uint32_t so = lds_phys(256u * it << 3, pad) * 8u;
+                *reinterpret_cast<cf*>(Ab + P0[0] + so) = v[0];
+                *reinterpret_cast<cf*>(Ab + P1[0] + so) = v[1];
+            }
+            tw.commit(Cb, pc);
+            cpass8_compute_store<NI>(r, T1b, P0[0], P1[0], 0u, pad, fw);
+            __syncthreads();
+        } else {
+            tw.commit(Ab, pa);
+            tw.commit(Cb, pc);
+            __syncthreads();
+        }
         const TileCursor nxt = tw.next(a, tileE, cur);
         if (t + gridDim.x < a.ntiles) {  // in flight while this tile is processed
-            tw.fetch(pa, xin, nxt);
+            fetch_a(nxt);
             tw.fetch(pc, cin, nxt);
         }
-        if constexpr (K >= 2) {
+        if constexpr (K >= 2 && !D0) {
             pass(IntC<0>{}, Ab, T1b, fw);  // a_1
             __syncthreads();
         }
@@ -716,27 +777,27 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             // recompute shares the phase of digit 2, which reads only T2 and Ct
             pass(IntC<2>{}, T2b, T1b, fw);  // a_3
             __syncthreads();
-            fused(IntC<3>{}, T1b, IntC<1>{}, IntC<0>{});
+            fused(IntC<3>{}, T1b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
             __syncthreads();
-            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<1>{});  // and a_1 again
+            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<1>{}, IntC<0>{}, cur.origin);  // and a_1 again
             __syncthreads();
         }
         if constexpr (K == 3) {
-            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<0>{});
+            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
             __syncthreads();
         }
         if constexpr (K >= 2) {
-            fused(IntC<1>{}, T1b, IntC<1>{}, IntC<0>{});
+            fused(IntC<1>{}, T1b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
             __syncthreads();
         }
         // out is null for the first digit group when only gW is wanted
         if (want_gx)
-            fused(IntC<0>{}, Ab, IntC<1>{}, IntC<0>{});
+            fused(IntC<0>{}, Ab, IntC<1>{}, IntC<0>{}, IntC<D0 ? 1 : 0>{}, cur.origin);
         else
-            fused(IntC<0>{}, Ab, IntC<0>{}, IntC<0>{});
+            fused(IntC<0>{}, Ab, IntC<0>{}, IntC<0>{}, IntC<0>{}, cur.origin);
         __syncthreads();
-        if (want_gx) {
-            tw.store(Cb, static_cast<cf*>(a.out), cur);
+        if (want_gx && !D0) {
+            tw.store(Cb, gxo, cur);
             __syncthreads();
         }
         cur = nxt;

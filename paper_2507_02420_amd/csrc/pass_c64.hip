@@ -98,15 +98,19 @@ hipError_t launch_cpass8_fast(int k, int ni, const PassArgs& a, unsigned grid, s
     }
 }
 
-template <int K, int NI, class LAY>
+template <int K, int NI, class LAY, bool D0 = false>
 static hipError_t launch_fast(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
-    hipError_t e = set_lds(gtt_c64_mfma8_bwd_fast_kernel<K, NI, LAY>, lds);
+    hipError_t e = set_lds(gtt_c64_mfma8_bwd_fast_kernel<K, NI, LAY, D0>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gtt_c64_mfma8_bwd_fast_kernel<K, NI, LAY>), dim3(grid), dim3(kBwdThreads), lds, s, a);
+    hipLaunchKernelGGL((gtt_c64_mfma8_bwd_fast_kernel<K, NI, LAY, D0>), dim3(grid), dim3(kBwdThreads), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    // contiguous tiles with digit 0 at stride 1: input and gx move in the
+    // digit-0 pass layout
+    if (k == 4 && ni == 2 && layout_is<BwdLay4>(a.p) && a.p.mode == kContigVec)
+        return launch_fast<4, 2, BwdLay4, true>(a, grid, lds, s);
     if (k == 4 && ni == 2 && layout_is<BwdLay4>(a.p)) return launch_fast<4, 2, BwdLay4>(a, grid, lds, s);
     if (k == 2 && ni == 2 && layout_is<BwdLay2>(a.p)) return launch_fast<2, 2, BwdLay2>(a, grid, lds, s);
     switch (k * 4 + ni) {
