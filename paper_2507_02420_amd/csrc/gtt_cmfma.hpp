@@ -393,6 +393,26 @@ __device__ __forceinline__ void cpass8_compute_store(const PassRegs<NI>& r, unsi
     }
 }
 
+// as above, keeping the results in registers (out)
+template <int NI>
+__device__ __forceinline__ void cpass8_compute_store_keep(const PassRegs<NI>& r, unsigned char* dst, uint32_t p0,
+                                                          uint32_t p1, uint32_t h, int pad, const CFrag8& fr,
+                                                          f32x4_c (&out)[NI]) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4_c acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[0], r.x0[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[1], r.x0[it].im, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[2], r.x1[it].re, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fr.a[3], r.x1[it].im, acc, 0, 0, 0);
+        const uint32_t so = lds_phys(digit_deposit(256u * it, h), pad) * 8u;
+        *reinterpret_cast<cf*>(dst + p0 + so) = cf{acc[0], acc[1]};
+        *reinterpret_cast<cf*>(dst + p1 + so) = cf{acc[2], acc[3]};
+        out[it] = acc;
+    }
+}
+
 // W (fragments fr) along the digit whose three bits start at h, over all
 // fibres of a 2048 * NI element tile: lane (q, i) takes elements 2q, 2q+1 of
 // its fibre of step it at byte offsets p0, p1 plus the step's uniform
@@ -581,7 +601,8 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
 // elements of a digit-0 fibre are 16 contiguous bytes in global memory, and
 // every fibre is one aligned 64-byte segment.  The group input is then
 // loaded straight in the digit-0 pass layout, so a_1 is computed from the
-// registers in the phase that stores A, and the adjoint pass of digit 0
+// registers in the phase that stores A (and kept there: K = 4 writes it
+// back into T1 instead of recomputing it), and the adjoint pass of digit 0
 // writes gx straight to global memory: two phases and their LDS round trips
 // fewer per tile.
 template <int K, int NI, class LAY, bool D0 = false>
@@ -735,6 +756,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
         tw.fetch(pc, cin, cur);
     }
     const bool want_gx = a.out != nullptr;
+    [[maybe_unused]] f32x4_c a1keep[NI];  // D0: a_1 of the current tile (digit-0 pass layout)
     for (; t < a.ntiles; t += gridDim.x) {
 #pragma unroll
         for (int j = 0; j < K; ++j) asm volatile("" : "+v"(P0[j]), "+v"(P1[j]), "+v"(GB[j]));
@@ -752,7 +774,7 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
                 *reinterpret_cast<cf*>(Ab + P1[0] + so) = v[1];
             }
             tw.commit(Cb, pc);
-            cpass8_compute_store<NI>(r, T1b, P0[0], P1[0], 0u, pad, fw);
+            cpass8_compute_store_keep<NI>(r, T1b, P0[0], P1[0], 0u, pad, fw, a1keep);
             __syncthreads();
         } else {
             tw.commit(Ab, pa);
@@ -779,7 +801,18 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             __syncthreads();
             fused(IntC<3>{}, T1b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
             __syncthreads();
-            fused(IntC<2>{}, T2b, IntC<1>{}, IntC<1>{}, IntC<0>{}, cur.origin);  // and a_1 again
+            if constexpr (D0) {
+                // a_1 back into T1 from the registers of the first phase
+                fused(IntC<2>{}, T2b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
+#pragma unroll
+                for (int it = 0; it < NI; ++it) {
+                    const uint32_t so = lds_phys(256u * it << 3, pad) * 8u;
+                    *reinterpret_cast<cf*>(T1b + P0[0] + so) = cf{a1keep[it][0], a1keep[it][1]};
+                    *reinterpret_cast<cf*>(T1b + P1[0] + so) = cf{a1keep[it][2], a1keep[it][3]};
+                }
+            } else {
+                fused(IntC<2>{}, T2b, IntC<1>{}, IntC<1>{}, IntC<0>{}, cur.origin);  // and a_1 again
+            }
             __syncthreads();
         }
         if constexpr (K == 3) {
