@@ -7,9 +7,14 @@ digit groups) + gtt_backward, inputs resident in HBM.  value = elements per
 second of that step.
 
 The JSON line also carries:
-  roofline     -- the kernel with the largest share of the timed region, its
-                  algorithmic HBM bytes per launch over its HIP-event duration,
-                  against the 8 TB/s HBM peak;
+  roofline     -- the kernel with the largest share of the timed region: its
+                  algorithmic HBM bytes and matrix-core flops per launch over
+                  its HIP-event duration, against the 8 TB/s HBM peak and the
+                  157.3 TFLOP/s FP32 MFMA peak; "bound" is the resource whose
+                  time at peak is the larger (the roofline that binds), and
+                  both views are kept;
+  directions   -- forward and backward HBM rates (algorithmic bytes of all
+                  their launches over their summed durations);
   cpu_baseline -- the FP64 oracle (numpy, one core) on a bounded sample of the
                   same workload, and the GPU error against it on that sample;
   workloads    -- the other configurations (single FP64 vector, complex64
@@ -31,6 +36,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTT fwd+bwd elements/s and % of HBM roofline vs plain FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def kernel_flops(name: str, elems: int) -> float:
+    """Algorithmic flops of one launch named by the library's timing
+    ("pass c64 b=8 cmfma s0=0 k=4", "bwd c64 ..."): per element and digit,
+    one complex b-term dot product (8 b real flops) for a pass; the adjoint
+    pass plus the gradient sums (16 b) for a backward launch.  Only the
+    complex radix-8 launches are priced (0 otherwise)."""
+    parts = dict(p.split("=", 1) for p in name.split() if "=" in p)
+    if "c64" not in name or "cmfma" not in name or "k" not in parts or "b" not in parts:
+        return 0.0
+    b, k = int(parts["b"]), int(parts["k"])
+    per = 16 * b if name.startswith("bwd") else 8 * b
+    return float(per) * k * elems
 
 
 def _sync():
@@ -341,11 +361,30 @@ def main():
     E = h["E"]
     value = E / (h["ms_per_step"] * 1e-3)
     traffic = load_traffic(h["dominant"], "c64_b8_n6_x256")
-    roof = {"bound": "hbm", "achieved": h["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": h["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+    t_dom = h["timing"][h["dominant"]]
+    flops = kernel_flops(h["dominant"], E)
+    achieved_tf = flops / (t_dom["avg_ms"] * 1e-3) / 1e12
+    hbm_view = {"achieved": h["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": h["achieved_GBs"] / HBM_PEAK_GBS}
+    mfma_view = {"achieved": achieved_tf, "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved_tf / MFMA_F32_PEAK_TFLOPS, "algorithmic_flops_per_launch": flops}
+    # the binding roofline: the larger of the two times at peak
+    t_hbm = h["bytes_per_launch"] / (HBM_PEAK_GBS * 1e9)
+    t_mfma = flops / (MFMA_F32_PEAK_TFLOPS * 1e12)
+    bound, view = ("mfma", mfma_view) if t_mfma > t_hbm else ("hbm", hbm_view)
+    roof = {"bound": bound, "achieved": view["achieved"], "peak": view["peak"], "unit": view["unit"],
+            "frac": view["frac"], "traffic": traffic,
             "kernel": h["dominant"], "algorithmic_bytes_per_launch": h["bytes_per_launch"],
+            "hbm_view": hbm_view, "mfma_view": mfma_view,
             "round_trips_measured_over_algorithmic": (traffic / h["bytes_per_launch"]) if traffic else None,
             "copy_ceiling_GBs": copy_ceiling_gbs()}
+    directions = {}
+    for d, pref in (("forward", "pass"), ("backward", "bwd")):
+        ks = [v for k, v in h["timing"].items() if k.startswith(pref) or (d == "backward" and k.startswith("reduce"))]
+        by = sum(v["bytes_per_launch"] * v["launches"] for v in ks)
+        ms_ = sum(v["total_ms"] for v in ks)
+        directions[d] = {"ms": ms_ / args.steps, "GBs": by / (ms_ * 1e-3) / 1e9,
+                         "frac_of_hbm_peak": by / (ms_ * 1e-3) / 1e9 / HBM_PEAK_GBS}
     cpu = None
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -361,7 +400,7 @@ def main():
         "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": "fwd+bwd: 256 x complex64, b=8, n=6 (N=262144), W 8x8 unitary, L=Re<g,y>",
                    "b": 8, "n": 6, "batch": 256, "elements": E, "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "directions": directions, "cpu_baseline": cpu,
         "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in v.items()}
                     for k, v in h["timing"].items()},
         "workloads": extra,
