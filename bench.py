@@ -263,6 +263,8 @@ def secondary(iters=10):
     p = G.Plan(b, n, batch, torch.complex64)
     y = torch.empty_like(x)
     xr = torch.empty_like(x)
+    p.forward(W, x, y), p.inverse(W, y, xr)   # first launches (code load) untimed
+    _sync()
     p.timing(True)
     ms, _ = time_calls(lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
     tm = p.timing_read()
@@ -279,6 +281,8 @@ def secondary(iters=10):
     W = torch.from_numpy(haar_unitary(3, 32, complex_=False).astype(np.float32)).to(dev)
     p = G.Plan(b, n, batch, torch.float32)
     y = torch.empty_like(x)
+    p.forward(W, x, y)
+    _sync()
     p.timing(True)
     ms, _ = time_calls(lambda: p.forward(W, x, y), iters, flush=flush)
     tm = p.timing_read()
@@ -296,6 +300,8 @@ def secondary(iters=10):
     H = torch.from_numpy(hadamard2(False)).to(torch.int32).to(dev)
     p = G.Plan(b, n, batch, torch.int32)
     y = torch.empty_like(xi)
+    p.forward(H, xi, y)
+    _sync()
     p.timing(True)
     ms, _ = time_calls(lambda: p.forward(H, xi, y), iters, flush=flush)
     tm = p.timing_read()

@@ -9,6 +9,33 @@ namespace gtt {
 
 enum class DT : int { F64 = 0, F32 = 1, C128 = 2, C64 = 3, BF16 = 4, F16 = 5, I32 = 6 };
 
+// compute units of the current device (cached per device)
+inline int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) cus[dev] = c;
+    }
+    return cus[dev];
+}
+
+// work-groups of a persistent launch over `tiles` tiles: as many as the
+// device holds at once (occupancy x compute units), at most one per tile
+template <typename K>
+inline unsigned resident_grid(K kernel, int threads, size_t lds, unsigned tiles) {
+    int occ = 0;
+    const int cus = device_cus();
+    if (cus <= 0 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kernel), threads, lds) !=
+            hipSuccess ||
+        occ < 1)
+        return tiles;
+    const unsigned long long g = (unsigned long long)occ * (unsigned long long)cus;
+    return g < tiles ? (unsigned)g : tiles;
+}
+
 // kernel families of a digit-group pass
 constexpr int kKindValu = 0;     // radix 2..8, register super-stages on the VALU
 constexpr int kKindGeneric = 1;  // any radix <= 64 and mixed radices, LDS sweeps

@@ -16,6 +16,8 @@
 // sets of positions that map onto themselves, so in-place (in == out) is safe.
 #pragma once
 
+#include <type_traits>
+
 #include "gtt_args.hpp"
 #include "gtt_types.hpp"
 
@@ -284,17 +286,149 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
     }
 }
 
+// Kernels with 32-bit compute lanes (float, int32, complex64) whose W fits
+// in scalar registers (at most 128 bytes) have the vector registers to spare
+// for a prefetch of the next tile; their launches use as many work-groups as
+// the device holds at once, each looping over tiles.  (The FP64 kernels
+// would spill.)
+template <typename C, int B>
+constexpr bool pass_prefetches() {
+    return B * B * (int)sizeof(C) <= 128 && (sizeof(C) == 4 || std::is_same<C, cf>::value);
+}
+
+// The prefetch buffer: 32 dwords per thread, eight 16-byte vectors (vector
+// modes) or 32 * 4 / sizeof(T) scalars packed into them (scalar modes, T of
+// 4, 8 or 16 bytes).  Item m is always a compile-time index.
+constexpr int kPfVec = 8;
+template <typename T>
+struct PfScalar {
+    static constexpr int N = (sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16) ? 32 * 4 / (int)sizeof(T) : 0;
+};
+template <typename T, int M>
+__device__ __forceinline__ T pf_get(const uint4 (&r)[kPfVec]) {
+    constexpr int per = 16 / (int)sizeof(T);
+    const uint4 q = r[M / per];
+    T out;
+    if constexpr (sizeof(T) == 16) {
+        out = *reinterpret_cast<const T*>(&q);
+    } else if constexpr (sizeof(T) == 8) {
+        const uint2 h = (M % 2 == 0) ? make_uint2(q.x, q.y) : make_uint2(q.z, q.w);
+        out = *reinterpret_cast<const T*>(&h);
+    } else {
+        const uint32_t w = (M % 4 == 0) ? q.x : (M % 4 == 1) ? q.y : (M % 4 == 2) ? q.z : q.w;
+        out = *reinterpret_cast<const T*>(&w);
+    }
+    return out;
+}
+template <typename T, int M>
+__device__ __forceinline__ void pf_set(uint4 (&r)[kPfVec], const T& v) {
+    constexpr int per = 16 / (int)sizeof(T);
+    uint4& q = r[M / per];
+    if constexpr (sizeof(T) == 16) {
+        q = *reinterpret_cast<const uint4*>(&v);
+    } else if constexpr (sizeof(T) == 8) {
+        const uint2 h = *reinterpret_cast<const uint2*>(&v);
+        if (M % 2 == 0) { q.x = h.x; q.y = h.y; } else { q.z = h.x; q.w = h.y; }
+    } else {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(&v);
+        if (M % 4 == 0) q.x = w; else if (M % 4 == 1) q.y = w; else if (M % 4 == 2) q.z = w; else q.w = w;
+    }
+}
+
+template <typename T, typename C, int M = 0>
+__device__ __forceinline__ void pf_fetch_scalar(uint4 (&r)[kPfVec], const PassArgs& a, const T* __restrict__ in,
+                                                int64_t t, uint32_t tid, int64_t hb, int64_t l, uint32_t tileE) {
+    if constexpr (M < PfScalar<T>::N) {
+        const uint32_t i = tid + M * kThreads;
+        if (i < tileE) {
+            const int64_t off = elem_offset(a, t, i, hb, l, tileE);
+            pf_set<T, M>(r, off >= 0 ? in[off] : from_c<T>(czero<C>()));
+        }
+        pf_fetch_scalar<T, C, M + 1>(r, a, in, t, tid, hb, l, tileE);
+    }
+}
+template <typename T, typename C, int M = 0>
+__device__ __forceinline__ void pf_commit_scalar(C* lds, const uint4 (&r)[kPfVec], const PassArgs& a, uint32_t tid,
+                                                 uint32_t tileE) {
+    if constexpr (M < PfScalar<T>::N) {
+        const uint32_t i = tid + M * kThreads;
+        if (i < tileE) lds[lds_phys(i, a.pad_shift)] = to_c(pf_get<T, M>(r));
+        pf_commit_scalar<T, C, M + 1>(lds, r, a, tid, tileE);
+    }
+}
+
 // Runs stages(lds, rows) on every tile of this work-group (t = blockIdx.x +
 // i * gridDim.x), loading and storing through the storage type T (compute
-// type C in LDS).
-template <typename T, typename C, typename Stages>
+// type C in LDS).  PF: when the work-group has more than one tile, the tile
+// fits the prefetch buffer and no filter mask applies, the loads of tile
+// t + gridDim.x are in flight into registers while tile t runs its stages
+// from LDS, so HBM stays busy through the LDS phases.
+template <typename T, typename C, bool PF = false, typename Stages>
 __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& stages) {
+    constexpr int V = Vec16<T>::V;
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
     const T* in = static_cast<const T*>(a.in);
     T* out = static_cast<T*>(a.out);
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(lds, a, in, t, rows);
+    const bool vec = a.mode == kContigVec || a.mode == kRowVec;
+    const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
+    int pf = 0;  // 0: none, 1: vectors, 2: scalars
+    if constexpr (PF) {
+        if (a.cut < 0 && (int64_t)gridDim.x < a.ntiles) {
+            if (vec && tileE / V <= (uint32_t)(kPfVec * kThreads)) pf = 1;
+            if (!vec && PfScalar<T>::N > 0 && tileE <= (uint32_t)(PfScalar<T>::N * kThreads)) pf = 2;
+        }
+    }
+    [[maybe_unused]] uint4 r[PF ? kPfVec : 1];
+    // the per-item offsets are recomputed for every tile (an opaque thread
+    // index): hoisted out of the tile loop they would hold registers per item
+    auto fetch = [&](int64_t t) {
+        if constexpr (PF) {
+            const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+            const int64_t l = contig ? 0 : t - hb * a.L;
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            if (pf == 1) {
+#pragma unroll
+                for (int v = 0; v < kPfVec; ++v) {
+                    const uint32_t i = tid + v * kThreads;
+                    if (i < tileE / V) r[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+                }
+            } else {
+                pf_fetch_scalar<T, C>(r, a, in, t, tid, hb, l, tileE);
+            }
+        }
+    };
+    auto commit = [&]() {
+        if constexpr (PF) {
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            if (pf == 1) {
+#pragma unroll
+                for (int v = 0; v < kPfVec; ++v) {
+                    const uint32_t i = tid + v * kThreads;
+                    if (i < tileE / V) {
+                        T vals[V];
+                        *reinterpret_cast<uint4*>(vals) = r[v];
+                        const uint32_t ph = lds_phys(i * V, a.pad_shift);
+#pragma unroll
+                        for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
+                    }
+                }
+            } else {
+                pf_commit_scalar<T, C>(lds, r, a, tid, tileE);
+            }
+        }
+    };
+    int64_t t = blockIdx.x;
+    if (pf && t < a.ntiles) fetch(t);
+    for (; t < a.ntiles; t += gridDim.x) {
+        if (pf)
+            commit();
+        else
+            tile_load<T, C>(lds, a, in, t, rows);
         __syncthreads();
+        if (pf && t + gridDim.x < a.ntiles) fetch(t + gridDim.x);
         stages(lds, rows);
         tile_store<T, C>(lds, a, out, t, rows);
         __syncthreads();
@@ -333,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     C* lds = reinterpret_cast<C*>(smem_raw);
     C w[B * B];
     load_w<C, B>(w, a);
-    tile_loop<T, C>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
+    tile_loop<T, C, pass_prefetches<C, B>()>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
 }
 
 }  // namespace gtt

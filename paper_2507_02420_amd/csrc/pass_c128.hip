@@ -21,20 +21,31 @@ hipError_t launch_pass_c128(int b, int kind, const PassArgs& a, unsigned grid, s
         if (e != hipSuccess) return e;                                        \
         hipLaunchKernelGGL(KER, dim3(grid), dim3(kThreads), lds, s, a);       \
     } while (0)
+    // the VALU pass kernels that prefetch run a persistent grid
+#define GTT_LAUNCH_VALU(B)                                                                    \
+    do {                                                                                      \
+        e = set_lds((gtt_pass_kernel<T, B>), lds);                                            \
+        if (e != hipSuccess) return e;                                                        \
+        const unsigned g = pass_prefetches<typename Tr<T>::C, B>()                            \
+                               ? resident_grid((gtt_pass_kernel<T, B>), kThreads, lds, grid)  \
+                               : grid;                                                        \
+        hipLaunchKernelGGL((gtt_pass_kernel<T, B>), dim3(g), dim3(kThreads), lds, s, a);      \
+    } while (0)
     if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
         return hipErrorInvalidValue;
     } else {
         switch (b) {
-            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
-            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3>)); break;
-            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4>)); break;
-            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5>)); break;
+            case 2: GTT_LAUNCH_VALU(2); break;
+            case 3: GTT_LAUNCH_VALU(3); break;
+            case 4: GTT_LAUNCH_VALU(4); break;
+            case 5: GTT_LAUNCH_VALU(5); break;
             default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
         }
     }
 #undef GTT_LAUNCH
+#undef GTT_LAUNCH_VALU
     return hipGetLastError();
 }
 

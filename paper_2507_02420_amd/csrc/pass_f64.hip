@@ -20,23 +20,34 @@ hipError_t launch_pass_f64(int b, int kind, const PassArgs& a, unsigned grid, si
         if (e != hipSuccess) return e;                                        \
         hipLaunchKernelGGL(KER, dim3(grid), dim3(kThreads), lds, s, a);       \
     } while (0)
+    // the VALU pass kernels that prefetch run a persistent grid
+#define GTT_LAUNCH_VALU(B)                                                                    \
+    do {                                                                                      \
+        e = set_lds((gtt_pass_kernel<T, B>), lds);                                            \
+        if (e != hipSuccess) return e;                                                        \
+        const unsigned g = pass_prefetches<typename Tr<T>::C, B>()                            \
+                               ? resident_grid((gtt_pass_kernel<T, B>), kThreads, lds, grid)  \
+                               : grid;                                                        \
+        hipLaunchKernelGGL((gtt_pass_kernel<T, B>), dim3(g), dim3(kThreads), lds, s, a);      \
+    } while (0)
     if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
         return hipErrorInvalidValue;
     } else {
         switch (b) {
-            case 2: GTT_LAUNCH((gtt_pass_kernel<T, 2>)); break;
-            case 3: GTT_LAUNCH((gtt_pass_kernel<T, 3>)); break;
-            case 4: GTT_LAUNCH((gtt_pass_kernel<T, 4>)); break;
-            case 5: GTT_LAUNCH((gtt_pass_kernel<T, 5>)); break;
-            case 6: GTT_LAUNCH((gtt_pass_kernel<T, 6>)); break;
-            case 7: GTT_LAUNCH((gtt_pass_kernel<T, 7>)); break;
-            case 8: GTT_LAUNCH((gtt_pass_kernel<T, 8>)); break;
+            case 2: GTT_LAUNCH_VALU(2); break;
+            case 3: GTT_LAUNCH_VALU(3); break;
+            case 4: GTT_LAUNCH_VALU(4); break;
+            case 5: GTT_LAUNCH_VALU(5); break;
+            case 6: GTT_LAUNCH_VALU(6); break;
+            case 7: GTT_LAUNCH_VALU(7); break;
+            case 8: GTT_LAUNCH_VALU(8); break;
             default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
         }
     }
 #undef GTT_LAUNCH
+#undef GTT_LAUNCH_VALU
     return hipGetLastError();
 }
 
