@@ -65,6 +65,33 @@ __device__ __forceinline__ void block_digit(C (&v)[(IPow<B, R>::value)], const C
     }
 }
 
+// The same for the integer radix-2 Hadamard W = [[1, 1], [1, -1]]: one add
+// and one subtract per pair (wrap-around arithmetic, so the result is the
+// same as with the multiplies, which are quarter-rate for 32-bit integers).
+template <typename C, int R, int D>
+__device__ __forceinline__ void block_digit_h2(C (&v)[(IPow<2, R>::value)]) {
+    constexpr int st = IPow<2, D>::value;
+    constexpr int n = IPow<2, R>::value;
+#pragma unroll
+    for (int base = 0; base < n; ++base) {
+        if ((base / st) % 2 != 0) continue;
+        const C x0 = v[base], x1 = v[base + st];
+        v[base] = x0 + x1;
+        v[base + st] = x0 - x1;
+    }
+}
+template <typename C, int R, int D>
+struct BlockAllH2 {
+    __device__ __forceinline__ static void run(C (&v)[(IPow<2, R>::value)]) {
+        block_digit_h2<C, R, D>(v);
+        BlockAllH2<C, R, D + 1>::run(v);
+    }
+};
+template <typename C, int R>
+struct BlockAllH2<C, R, R> {
+    __device__ __forceinline__ static void run(C (&)[(IPow<2, R>::value)]) {}
+};
+
 template <typename C, int B, int R, int D>
 struct BlockAll {
     __device__ __forceinline__ static void run(C (&v)[(IPow<B, R>::value)], const C (&w)[B * B]) {
@@ -102,7 +129,7 @@ __device__ __forceinline__ uint32_t lds_tile_elems(uint32_t tileE, int pad_shift
 // work-group-uniform offset; without padding positions are linear.
 template <typename C, int B, int R>
 __device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, uint32_t rows,
-                                           const C (&w)[B * B]) {
+                                           const C (&w)[B * B], bool h2 = false) {
     constexpr int NB = IPow<B, R>::value;
     constexpr bool kPow2 = (B & (B - 1)) == 0;
     const uint32_t Cm = (1u << a.logC) - 1u;
@@ -133,26 +160,34 @@ __device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, ui
         C v[NB];
 #pragma unroll
         for (int m = 0; m < NB; ++m) v[m] = lds[idx[m]];
-        BlockAll<C, B, R, 0>::run(v, w);
+        if constexpr (B == 2 && std::is_same<C, uint32_t>::value) {
+            if (h2)  // work-group uniform
+                BlockAllH2<C, R, 0>::run(v);
+            else
+                BlockAll<C, B, R, 0>::run(v, w);
+        } else {
+            BlockAll<C, B, R, 0>::run(v, w);
+        }
 #pragma unroll
         for (int m = 0; m < NB; ++m) lds[idx[m]] = v[m];
     }
 }
 
 template <typename C, int B, int RD>
-__device__ __forceinline__ void run_stages(C* lds, const PassArgs& a, uint32_t rows, const C (&w)[B * B]) {
+__device__ __forceinline__ void run_stages(C* lds, const PassArgs& a, uint32_t rows, const C (&w)[B * B],
+                                           bool h2 = false) {
     for (int j = 0; j < a.k; j += RD) {
         const int r = (a.k - j) < RD ? (a.k - j) : RD;
         if constexpr (RD >= 4) {
-            if (r == 4) { super_stage<C, B, 4>(lds, a, j, rows, w); __syncthreads(); continue; }
+            if (r == 4) { super_stage<C, B, 4>(lds, a, j, rows, w, h2); __syncthreads(); continue; }
         }
         if constexpr (RD >= 3) {
-            if (r == 3) { super_stage<C, B, 3>(lds, a, j, rows, w); __syncthreads(); continue; }
+            if (r == 3) { super_stage<C, B, 3>(lds, a, j, rows, w, h2); __syncthreads(); continue; }
         }
         if constexpr (RD >= 2) {
-            if (r == 2) { super_stage<C, B, 2>(lds, a, j, rows, w); __syncthreads(); continue; }
+            if (r == 2) { super_stage<C, B, 2>(lds, a, j, rows, w, h2); __syncthreads(); continue; }
         }
-        super_stage<C, B, 1>(lds, a, j, rows, w);
+        super_stage<C, B, 1>(lds, a, j, rows, w, h2);
         __syncthreads();
     }
 }
@@ -467,7 +502,12 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     C* lds = reinterpret_cast<C*>(smem_raw);
     C w[B * B];
     load_w<C, B>(w, a);
-    tile_loop<T, C, pass_prefetches<C, B>()>(lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w); });
+    // integer radix 2: the Hadamard W runs as butterflies
+    bool h2 = false;
+    if constexpr (B == 2 && std::is_same<C, uint32_t>::value)
+        h2 = w[0] == 1u && w[1] == 1u && w[2] == 1u && w[3] == 0xffffffffu;
+    tile_loop<T, C, pass_prefetches<C, B>()>(lds, a,
+                                             [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w, h2); });
 }
 
 }  // namespace gtt
