@@ -63,6 +63,27 @@ hipError_t ragged_occupancy_f16(size_t, int*);
 hipError_t launch_ragged_i32(const RaggedArgs&, unsigned, size_t, hipStream_t);
 hipError_t ragged_occupancy_i32(size_t, int*);
 
+hipError_t launch_ragged_cls_f64(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_f32(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_c128(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_c64(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_bf16(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_f16(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_ragged_cls_i32(int, const RaggedArgs&, unsigned, size_t, hipStream_t);
+
+hipError_t launch_ragged_cls(DT dt, int cls, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    switch (dt) {
+        case DT::F64: return launch_ragged_cls_f64(cls, a, grid, lds, s);
+        case DT::F32: return launch_ragged_cls_f32(cls, a, grid, lds, s);
+        case DT::C128: return launch_ragged_cls_c128(cls, a, grid, lds, s);
+        case DT::C64: return launch_ragged_cls_c64(cls, a, grid, lds, s);
+        case DT::BF16: return launch_ragged_cls_bf16(cls, a, grid, lds, s);
+        case DT::F16: return launch_ragged_cls_f16(cls, a, grid, lds, s);
+        case DT::I32: return launch_ragged_cls_i32(cls, a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     switch (dt) {
         case DT::F64: return launch_ragged_f64(a, grid, lds, s);

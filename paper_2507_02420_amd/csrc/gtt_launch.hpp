@@ -73,6 +73,8 @@ hipError_t launch_convert(DT from, DT to, const void* in, void* out, int64_t n, 
 struct RaggedArgs;
 // ragged-batch launch (all phases with grid barriers, or one phase)
 hipError_t launch_ragged(DT dt, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s);
+// the items [phase_start[0], phase_start[1]) of one item class
+hipError_t launch_ragged_cls(DT dt, int cls, const RaggedArgs& a, unsigned grid, size_t lds, hipStream_t s);
 // co-resident work-groups per compute unit of the ragged kernel
 hipError_t ragged_occupancy(DT dt, size_t lds, int* blocks_per_cu);
 

@@ -23,6 +23,15 @@ struct RaggedState {
     std::vector<RaggedDesc> desc;
     std::vector<RaggedItem> items;
     std::vector<int64_t> phase_start;
+    // per-phase launches: runs of items of one class (item range, LDS of the
+    // largest tile in the run, algorithmic bytes)
+    struct Seg {
+        int phase, cls;
+        int64_t start, end;
+        size_t lds;
+        double bytes;
+    };
+    std::vector<Seg> segs;
     size_t lds_max = 0;
     bool uploaded = false;
     RaggedDesc* d_desc = nullptr;
@@ -39,9 +48,11 @@ static void build_worklist(gtt_plan_s* p) {
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
     const int64_t E = p->total_elems;
     struct Tmp {
-        int phase;
+        int phase, cls;
         int64_t cost;
         RaggedItem it;
+        size_t lds;
+        double bytes;
     };
     std::vector<Tmp> tmp;
     for (const Instance& t : p->inst) {
@@ -89,20 +100,33 @@ static void build_worklist(gtt_plan_s* p) {
             // cost estimate of one tile: elements x digits x radix work
             const int64_t work = (G.kind == kKindMfma) ? 8 : t.b;
             const int64_t cost = G.tileE * G.k * work;
-            for (int64_t i = 0; i < G.ntiles; ++i) tmp.push_back(Tmp{g, cost, RaggedItem{di, 0, i}});
+            const int cls = ragged_class(d.kind, d.b);
+            const double bytes = 2.0 * (double)G.tileE * (double)p->esize;
+            for (int64_t i = 0; i < G.ntiles; ++i)
+                tmp.push_back(Tmp{g, cls, cost, RaggedItem{di, 0, i}, G.lds_bytes + extra, bytes});
         }
     }
-    // phase-major; within a phase the costliest tiles first, so that the
-    // round-robin assignment ends with the cheap ones (longest-processing-time
-    // order)
+    // phase-major, then by item class (one specialised launch per run of a
+    // class); within a run the costliest tiles first, so that the round-robin
+    // assignment ends with the cheap ones (longest-processing-time order)
     std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) {
         if (a.phase != b.phase) return a.phase < b.phase;
+        if (a.cls != b.cls) return a.cls < b.cls;
         return a.cost > b.cost;
     });
     rs->phase_start.assign(maxR + 1, 0);
     for (const Tmp& t : tmp) rs->phase_start[t.phase + 1]++;
     for (int ph = 0; ph < maxR; ++ph) rs->phase_start[ph + 1] += rs->phase_start[ph];
-    for (const Tmp& t : tmp) rs->items.push_back(t.it);
+    for (size_t i = 0; i < tmp.size(); ++i) {
+        const Tmp& t = tmp[i];
+        rs->items.push_back(t.it);
+        if (rs->segs.empty() || rs->segs.back().phase != t.phase || rs->segs.back().cls != t.cls)
+            rs->segs.push_back(RaggedState::Seg{t.phase, t.cls, (int64_t)i, (int64_t)i, 0, 0.0});
+        RaggedState::Seg& sg = rs->segs.back();
+        sg.end = (int64_t)i + 1;
+        sg.lds = std::max(sg.lds, t.lds);
+        sg.bytes += t.bytes;
+    }
 }
 
 static gtt_status upload_worklist(gtt_plan_s* p) {
@@ -251,15 +275,21 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
                    2.0 * (double)p->total_elems * (double)p->esize * (double)a.nphases);
         return GTT_OK;
     }
-    for (int ph = 0; ph < a.nphases; ++ph) {
-        const int64_t cnt = rs->phase_start[ph + 1] - rs->phase_start[ph];
-        if (cnt == 0) continue;
-        a.persistent = 0;
-        a.phase = ph;
-        const unsigned grid = (unsigned)std::min<int64_t>(cnt, (int64_t)rs->grid_persistent * 4);
+    // one launch per run of one item class in a phase (the phases follow each
+    // other on the stream; runs of one phase touch disjoint instances)
+    a.persistent = 0;
+    a.phase = 0;
+    for (const RaggedState::Seg& sg : rs->segs) {
+        a.phase_start[0] = sg.start;
+        a.phase_start[1] = sg.end;
+        const int64_t cnt = sg.end - sg.start;
+        const unsigned grid = (unsigned)std::min<int64_t>(cnt, (int64_t)0x7fffffff);
         timing_begin(p, s);
-        if (launch_ragged(dt, a, grid, rs->lds_max, s) != hipSuccess) return GTT_ERR_HIP;
-        timing_end(p, s, std::string("ragged phase ") + std::to_string(ph) + " " + dn[(int)p->dtype], 0.0);
+        if (launch_ragged_cls(dt, sg.cls, a, grid, sg.lds, s) != hipSuccess) return GTT_ERR_HIP;
+        timing_end(p, s,
+                   std::string("ragged phase ") + std::to_string(sg.phase) + " " + dn[(int)p->dtype] +
+                       (sg.cls == kClsGeneric ? " generic" : (sg.cls >= 16 ? " mfma b=" : " b=") + std::to_string(sg.cls)),
+                   sg.bytes);
     }
     return GTT_OK;
 }

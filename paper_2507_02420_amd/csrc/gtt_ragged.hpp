@@ -189,47 +189,76 @@ __device__ __forceinline__ void ragged_tile_generic(unsigned char* smem, const P
     __syncthreads();
 }
 
+// Item classes.  The per-phase launches run the items of one class with a
+// kernel specialised to it (its own registers and LDS, hence occupancy);
+// the persistent launch dispatches every item at run time.
+constexpr int kClsAny = -1;
+constexpr int kClsGeneric = 0;  // 2..5: VALU radix; 16, 32: matrix-core radix
+
+__host__ __device__ inline int ragged_class(int kind, int b) {
+    if (kind == kKindValu) return (b >= 2 && b <= 5) ? b : kClsGeneric;
+    if (kind == kKindMfma) return b;
+    return kClsGeneric;
+}
+
+template <typename T, int CLS>
+__device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArgs& r, const RaggedItem& it) {
+    using C = typename Tr<T>::C;
+    const RaggedDesc& d = r.desc[it.d];
+    const T* in;
+    T* out;
+    if (d.in_sel == 0) in = static_cast<const T*>(r.x) + d.in_off;
+    else if (d.in_sel == 1 || !r.saved) in = static_cast<const T*>(r.y) + d.in_off;
+    else in = static_cast<const T*>(r.saved) + d.in_off_saved;
+    if (d.out_sel == 1 || !r.saved) out = static_cast<T*>(r.y) + d.out_off;
+    else out = static_cast<T*>(r.saved) + d.mid_off_saved;
+    const C* W = static_cast<const C*>(r.W) + d.w_off;
+    if constexpr (CLS == kClsAny) {
+        if (d.kind == kKindValu) {
+            switch (d.b) {
+                case 2: ragged_tile_valu<T, 2>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
+                case 3: ragged_tile_valu<T, 3>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
+                case 4: ragged_tile_valu<T, 4>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
+                case 5: ragged_tile_valu<T, 5>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
+                default: ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
+            }
+        } else if (d.kind == kKindMfma) {
+            if constexpr (sizeof(T) == 2) {
+                if (d.b == 16)
+                    ragged_tile_mfma<T, 16>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
+                else
+                    ragged_tile_mfma<T, 32>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
+            }
+        } else {
+            ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile);
+        }
+    } else if constexpr (CLS == kClsGeneric) {
+        ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile);
+    } else if constexpr (CLS <= 5) {
+        ragged_tile_valu<T, CLS>(smem, d.a, in, out, W, r.adjoint, it.tile);
+    } else if constexpr (sizeof(T) == 2) {
+        ragged_tile_mfma<T, CLS>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gtt_ragged_kernel(RaggedArgs r) {
-    using C = typename Tr<T>::C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int p0 = r.persistent ? 0 : r.phase;
     const int p1 = r.persistent ? r.nphases : r.phase + 1;
     for (int p = p0; p < p1; ++p) {
-        for (int64_t i = r.phase_start[p] + blockIdx.x; i < r.phase_start[p + 1]; i += gridDim.x) {
-            const RaggedItem it = r.items[i];
-            const RaggedDesc& d = r.desc[it.d];
-            const T* in;
-            T* out;
-            if (d.in_sel == 0) in = static_cast<const T*>(r.x) + d.in_off;
-            else if (d.in_sel == 1 || !r.saved) in = static_cast<const T*>(r.y) + d.in_off;
-            else in = static_cast<const T*>(r.saved) + d.in_off_saved;
-            if (d.out_sel == 1 || !r.saved) out = static_cast<T*>(r.y) + d.out_off;
-            else out = static_cast<T*>(r.saved) + d.mid_off_saved;
-            const C* W = static_cast<const C*>(r.W) + d.w_off;
-            if (d.kind == kKindValu) {
-                switch (d.b) {
-                    case 2: ragged_tile_valu<T, 2>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
-                    case 3: ragged_tile_valu<T, 3>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
-                    case 4: ragged_tile_valu<T, 4>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
-                    case 5: ragged_tile_valu<T, 5>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
-                    default: ragged_tile_generic<T>(smem_raw, d.a, in, out, W, r.adjoint, it.tile); break;
-                }
-            } else if (d.kind == kKindMfma) {
-                if constexpr (sizeof(T) == 2) {
-                    if (d.b == 16)
-                        ragged_tile_mfma<T, 16>(smem_raw, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint,
-                                                it.tile);
-                    else
-                        ragged_tile_mfma<T, 32>(smem_raw, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint,
-                                                it.tile);
-                }
-            } else {
-                ragged_tile_generic<T>(smem_raw, d.a, in, out, W, r.adjoint, it.tile);
-            }
-        }
+        for (int64_t i = r.phase_start[p] + blockIdx.x; i < r.phase_start[p + 1]; i += gridDim.x)
+            ragged_item<T, kClsAny>(smem_raw, r, r.items[i]);
         if (r.persistent && p + 1 < p1) grid_barrier(r.bar, gridDim.x);
     }
+}
+
+// The items [phase_start[0], phase_start[1]) of one class.
+template <typename T, int CLS>
+__global__ __launch_bounds__(kThreads) void gtt_ragged_class_kernel(RaggedArgs r) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int64_t i = r.phase_start[0] + blockIdx.x; i < r.phase_start[1]; i += gridDim.x)
+        ragged_item<T, CLS>(smem_raw, r, r.items[i]);
 }
 
 }  // namespace gtt
