@@ -1,7 +1,8 @@
 """Ragged batches: instances of different radix and length in one buffer,
 run as one persistent launch (grid barrier between digit groups), as one
 launch per phase, or per instance; every instance checked against the FP64
-oracle.  Also graph capture and replay of the persistent launch."""
+oracle.  Also graph capture and replay of the persistent launch and of the
+per-phase launches (with their forked helper streams)."""
 import numpy as np
 import pytest
 import torch
@@ -142,11 +143,16 @@ def test_ragged_full_shape_list_bf16_persistent_sampled():
     say("  max rel err per radix: " + ", ".join(f"b={b}: {max(v):.2e}" for b, v in sorted(errs.items())))
 
 
-def test_ragged_persistent_graph_replay():
-    shapes = SMALL
+@pytest.mark.parametrize("mode", ["persistent", "phases"])
+def test_ragged_graph_replay(mode):
+    # per-phase mode: the runs of each phase fork onto helper streams and
+    # join back, which the capture must follow (several radix classes per
+    # phase: 2, 3, 4 on the VALU, 16 on the matrix cores)
+    shapes = SMALL if mode == "persistent" else [(2, 12), (16, 3), (4, 7), (3, 8), (2, 5), (16, 4), (4, 3)]
     dtype = torch.bfloat16
+    say(f"ragged graph replay, {mode}")
     xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=1100)
-    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=G.FLAG_PERSISTENT)
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, flags=MODES[mode])
     y_eager = torch.zeros_like(xt)           # the buffer tail past the last instance stays 0
     plan.forward(Wt, xt, y_eager)            # first call uploads the work list
     torch.cuda.synchronize()
