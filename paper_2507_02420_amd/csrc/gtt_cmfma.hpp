@@ -463,6 +463,18 @@ struct LayoutFixed {
     __device__ static uint64_t fmap(const PassArgs&) { return FMAP; }
 };
 
+// Non-temporal tile I/O for the compiled layouts where it measured faster:
+// strided tiles in the forward pass, every backward tile
+template <class LAY>
+constexpr bool nt_pass_io() {
+    if constexpr (LAY::kFixed) return LAY::kLogC > 0;
+    else return false;
+}
+template <class LAY>
+constexpr bool nt_bwd_io() {
+    return LAY::kFixed;
+}
+
 // Tile transfers: 16-byte global accesses (two elements per lane and
 // access), two 64-bit LDS accesses.  NV = tileE / 2048 vectors per thread.
 // A thread's global offsets relative to the tile origin and its LDS offsets
@@ -474,7 +486,29 @@ struct TileCursor {
     int64_t hb, l;   // strided tiles: hi block and column block
 };
 
-template <int NV>
+// 16-byte global accesses with the non-temporal hint: the tile streams are
+// read or written once per launch
+typedef unsigned int ntu32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ uint4 gload16(const void* p) {
+    if constexpr (NT) {
+        const ntu32x4 v = __builtin_nontemporal_load(reinterpret_cast<const ntu32x4*>(p));
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void gstore16(void* p, uint4 u) {
+    if constexpr (NT) {
+        ntu32x4 v = {u.x, u.y, u.z, u.w};
+        __builtin_nontemporal_store(v, reinterpret_cast<ntu32x4*>(p));
+    } else {
+        *reinterpret_cast<uint4*>(p) = u;
+    }
+}
+
+template <int NV, bool NT = false>
 struct TileWalk {
     int64_t goff[NV];   // elements from the tile origin to this thread's vector v
     uint32_t loff[NV];  // LDS byte offset of that vector's first element
@@ -523,7 +557,7 @@ struct TileWalk {
     }
     __device__ __forceinline__ void fetch(uint4 (&buf)[NV], const cf* __restrict__ in, const TileCursor& c) const {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) buf[v] = *reinterpret_cast<const uint4*>(in + c.origin + goff[v]);
+        for (int v = 0; v < NV; ++v) buf[v] = gload16<NT>(in + c.origin + goff[v]);
     }
     __device__ __forceinline__ void commit(unsigned char* lds, const uint4 (&buf)[NV]) const {
 #pragma unroll
@@ -541,7 +575,7 @@ struct TileWalk {
             cf vals[2];
             vals[0] = *reinterpret_cast<const cf*>(lds + loff[v]);
             vals[1] = *reinterpret_cast<const cf*>(lds + loff[v] + 8);
-            *reinterpret_cast<uint4*>(out + c.origin + goff[v]) = *reinterpret_cast<const uint4*>(vals);
+            gstore16<NT>(out + c.origin + goff[v], *reinterpret_cast<const uint4*>(vals));
         }
     }
 };
@@ -565,7 +599,7 @@ __global__ __launch_bounds__(kBwdThreads, 8) void gtt_c64_mfma8_pass_fast_kernel
     const cf* in = static_cast<const cf*>(a.in);
     cf* out = static_cast<cf*>(a.out);
     uint4 pa[NE];
-    TileWalk<NE> tw;
+    TileWalk<NE, nt_pass_io<LAY>()> tw;
     TileCursor cur = tw.init(a, tileE, pad);
     int64_t t = blockIdx.x;
     if (t < a.ntiles) tw.fetch(pa, in, cur);
@@ -722,7 +756,9 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fh.a[3], x1[it].im, acc, 0, 0, 0);
                 M = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[it][3], av[it][3], M, 0, 0, 0);
                 if constexpr (direct) {
-                    *reinterpret_cast<f32x4_c*>(gxo + origin + dpos[it]) = acc;
+                    gstore16<nt_bwd_io<LAY>()>(gxo + origin + dpos[it],
+                                               make_uint4(__float_as_uint(acc[0]), __float_as_uint(acc[1]),
+                                                          __float_as_uint(acc[2]), __float_as_uint(acc[3])));
                 } else {
                     *reinterpret_cast<cf*>(Cb + P0[j] + so) = cf{acc[0], acc[1]};
                     *reinterpret_cast<cf*>(Cb + P1[j] + so) = cf{acc[2], acc[3]};
@@ -739,13 +775,14 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     };
 
     uint4 pa[NE], pc[NE];
-    TileWalk<NE> tw;
+    constexpr bool NT = nt_bwd_io<LAY>();
+    TileWalk<NE, NT> tw;
     TileCursor cur = tw.init(a, tileE, pad);
     // the group input: tile layout, or (D0) the digit-0 pass layout
     auto fetch_a = [&](const TileCursor& c) {
         if constexpr (D0) {
 #pragma unroll
-            for (int it = 0; it < NI; ++it) pa[it] = *reinterpret_cast<const uint4*>(xin + c.origin + dpos[it]);
+            for (int it = 0; it < NI; ++it) pa[it] = gload16<NT>(xin + c.origin + dpos[it]);
         } else {
             tw.fetch(pa, xin, c);
         }
