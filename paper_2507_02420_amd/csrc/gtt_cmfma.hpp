@@ -486,28 +486,6 @@ struct TileCursor {
     int64_t hb, l;   // strided tiles: hi block and column block
 };
 
-// 16-byte global accesses with the non-temporal hint: the tile streams are
-// read or written once per launch
-typedef unsigned int ntu32x4 __attribute__((ext_vector_type(4)));
-template <bool NT>
-__device__ __forceinline__ uint4 gload16(const void* p) {
-    if constexpr (NT) {
-        const ntu32x4 v = __builtin_nontemporal_load(reinterpret_cast<const ntu32x4*>(p));
-        return make_uint4(v[0], v[1], v[2], v[3]);
-    } else {
-        return *reinterpret_cast<const uint4*>(p);
-    }
-}
-template <bool NT>
-__device__ __forceinline__ void gstore16(void* p, uint4 u) {
-    if constexpr (NT) {
-        ntu32x4 v = {u.x, u.y, u.z, u.w};
-        __builtin_nontemporal_store(v, reinterpret_cast<ntu32x4*>(p));
-    } else {
-        *reinterpret_cast<uint4*>(p) = u;
-    }
-}
-
 template <int NV, bool NT = false>
 struct TileWalk {
     int64_t goff[NV];   // elements from the tile origin to this thread's vector v

@@ -310,8 +310,7 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
             const uint32_t ph = lds_phys(i * V, a.pad_shift);
 #pragma unroll
             for (int e = 0; e < V; ++e) vals[e] = from_c<T>(lds[ph + e]);
-            *reinterpret_cast<uint4*>(out + vec_offset<T>(a, t, i, hb, l, tileE)) =
-                *reinterpret_cast<const uint4*>(vals);
+            gstore16<true>(out + vec_offset<T>(a, t, i, hb, l, tileE), *reinterpret_cast<const uint4*>(vals));
         }
     } else {
         for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
@@ -427,7 +426,7 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
 #pragma unroll
                 for (int v = 0; v < kPfVec; ++v) {
                     const uint32_t i = tid + v * kThreads;
-                    if (i < tileE / V) r[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+                    if (i < tileE / V) r[v] = gload16<true>(in + vec_offset<T>(a, t, i, hb, l, tileE));
                 }
             } else {
                 pf_fetch_scalar<T, C>(r, a, in, t, tid, hb, l, tileE);

@@ -195,4 +195,26 @@ __device__ __forceinline__ double cadd(double a, double b) { return a + b; }
 __device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
 
+// 16-byte global accesses with the non-temporal hint: tile streams that a
+// launch reads or writes once
+typedef unsigned int ntu32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ uint4 gload16(const void* p) {
+    if constexpr (NT) {
+        const ntu32x4 v = __builtin_nontemporal_load(reinterpret_cast<const ntu32x4*>(p));
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void gstore16(void* p, uint4 u) {
+    if constexpr (NT) {
+        ntu32x4 v = {u.x, u.y, u.z, u.w};
+        __builtin_nontemporal_store(v, reinterpret_cast<ntu32x4*>(p));
+    } else {
+        *reinterpret_cast<uint4*>(p) = u;
+    }
+}
+
 }  // namespace gtt
