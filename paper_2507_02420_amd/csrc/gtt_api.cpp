@@ -216,6 +216,10 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
             pad = p1 | (p2 << 8) | (p3 << 16);
         }
     }
+    // matrix-core passes: padding from the bank-conflict search over the
+    // tile transfers and the digit passes' fragment loads
+    if (gr->kind == kKindMfma && gr->tileE % 64 == 0)
+        pad = mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize));
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
         int64_t wtot = 0;

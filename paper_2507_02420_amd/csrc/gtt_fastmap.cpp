@@ -16,6 +16,7 @@
 // the other four the wave.  In the gradient sums, lane group k (0..3) sets
 // fibre bits kb0_j (k & 1) and kb1_j (k >> 1); the remaining two mask bits
 // are the loop over the four MFMAs of a block.
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -196,6 +197,103 @@ FastMap search(int K, int NI, int logC, bool gw) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// LDS padding of the bf16 / f16 matrix-core passes (FP32 tile, radix 16 /
+// 32).  The tile transfers move a 16-byte vector (eight elements) per
+// thread as eight 32-bit LDS accesses, so the lanes of one access sit eight
+// elements apart; a digit pass reads and writes element 16 h + 4 q + v of
+// the fibre of lane (q, i), 16 fibres by four q.  Each 32-bit access costs
+// its half-waves' worst bank degree (32 banks); the search takes the pad
+// triple (each level one element) with the least total cost over a sample
+// of the tile, LDS growth at most 1/8.
+// ---------------------------------------------------------------------------
+namespace {
+
+int conflict32(const uint32_t* e) {
+    uint32_t v[32];
+    for (int i = 0; i < 32; ++i) v[i] = e[i];
+    std::sort(v, v + 32);
+    int cnt[32] = {0};
+    int worst = 0;
+    for (int i = 0; i < 32; ++i) {
+        if (i && v[i] == v[i - 1]) continue;  // equal addresses broadcast
+        const int c = ++cnt[v[i] & 31u];
+        if (c > worst) worst = c;
+    }
+    return worst;
+}
+
+int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE) {
+    int tot = 0;
+    uint32_t e[32];
+    const uint32_t nvec = tileE / 8;
+    for (uint32_t w0 = 0; w0 + 64 <= nvec; w0 += 256)
+        for (uint32_t el = 0; el < 8; ++el)
+            for (uint32_t half = 0; half < 2; ++half) {
+                for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(8u * (w0 + 32u * half + l) + el);
+                tot += 2 * conflict32(e);  // load and store
+            }
+    const uint32_t F = tileE / (uint32_t)B;
+    const uint32_t Cm = (1u << logC) - 1u;
+    uint32_t bj = 1;
+    for (int j = 0; j < k; ++j, bj *= (uint32_t)B) {
+        const uint32_t bj1 = bj * (uint32_t)B, step = bj << logC;
+        for (uint32_t grp = 0; grp < (F + 15) / 16; grp += 4)
+            for (int h = 0; h < B / 16; ++h)
+                for (uint32_t v = 0; v < 4; ++v)
+                    for (uint32_t half = 0; half < 2; ++half) {
+                        for (uint32_t l = 0; l < 32; ++l) {
+                            const uint32_t lane = 32u * half + l, q = lane >> 4, lo = lane & 15u;
+                            const uint32_t f = (grp * 16u + lo) % F;
+                            const uint32_t c = f & Cm, f1 = f >> logC;
+                            const uint32_t Q = f1 / bj, glo = f1 % bj;
+                            const uint32_t lam0 = ((Q * bj1 + glo) << logC) | c;
+                            e[l] = pd.phys(lam0 + (16u * h + 4u * q + v) * step);
+                        }
+                        tot += 2 * conflict32(e);
+                    }
+    }
+    return tot;
+}
+
+int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift) {
+    Pads best{{31, 31, 31}, 0};
+    int best_cost = mfma_cost(best, B, k, logC, tileE);
+    uint32_t best_extra = 0;
+    std::vector<int> sh;
+    for (int p = min_shift; p <= 13; ++p) sh.push_back(p);
+    for (size_t a = 0; a < sh.size(); ++a)
+        for (size_t b = a; b <= sh.size(); ++b)
+            for (size_t c = b; c <= sh.size(); ++c) {
+                Pads pd{{sh[a], b < sh.size() ? sh[b] : 31, c < sh.size() ? sh[c] : 31}, 0};
+                pd.n = 1 + (b < sh.size()) + (c < sh.size());
+                if (b == sh.size() && c < sh.size()) continue;
+                const uint32_t extra = pd.phys(tileE) - tileE;
+                if (extra > tileE / 8) continue;
+                const int cst = mfma_cost(pd, B, k, logC, tileE);
+                if (cst < best_cost || (cst == best_cost && extra < best_extra)) {
+                    best = pd;
+                    best_cost = cst;
+                    best_extra = extra;
+                }
+            }
+    return best.packed();
+}
+
+}  // namespace
+
+int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int64_t, int>, int> cache;
+    const auto key = std::make_tuple(B, k, logC, tileE, min_shift);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int pad = mfma_search(B, k, logC, (uint32_t)tileE, min_shift);
+    cache[key] = pad;
+    return pad;
+}
 
 FastMap fast_map(int K, int NI, int logC, bool gw) {
     static std::mutex mu;
