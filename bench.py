@@ -230,7 +230,19 @@ def cpu_baseline_headline(tensors, budget_s=15.0):
         "sample": f"{done} of 256 instances (N=262144 c64 upcast to complex128): numpy staged forward + "
                   f"stage-wise gradient, {elapsed:.2f} s on one pinned host core",
         "gpu_rel_err_y_max": max(errs_y), "gpu_rel_err_gx_max": max(errs_gx),
+        "cpu_model": _cpu_model(), "cores_available": len(prev) if prev else os.cpu_count(),
     }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---------------------------------------------------------------------------

@@ -188,3 +188,61 @@ def test_fp32_intermediate_plan_sizes_and_limits():
     assert (G.Plan(b, n, batch, torch.float32, flags=F).workspace_size()
             == G.Plan(b, n, batch, torch.float32).workspace_size())
     assert "fp32_intermediate" not in G.Plan(b, n, batch, torch.int32, flags=F).describe()
+
+
+def _phys(x, pad):
+    return x + sum(x >> ((pad >> (8 * i)) & 31) for i in range(3))
+
+
+def _mfma_bank_cost(B, k, logC, pad, tileE):
+    # worst bank degree per half-wave (32 banks) of the 32-bit LDS accesses
+    # of a bf16 matrix-core pass: tile transfers (eight elements a thread),
+    # then per digit element 4q+v of the fibre of lane (q, i); a sample of
+    # the tile
+    def degree(addrs):
+        tot = 0
+        for h in (addrs[:32], addrs[32:]):
+            per = {}
+            for a in set(h):
+                per.setdefault(a & 31, set()).add(a)
+            tot += max(len(v) for v in per.values())
+        return tot
+    cost = 0
+    for w0 in range(0, tileE // 8 - 63, 256):
+        for e in range(8):
+            cost += degree([_phys(8 * (w0 + l) + e, pad) for l in range(64)])
+    F = tileE // B
+    for j in range(k):
+        bj = B ** j
+        step = bj << logC
+        for grp in range(0, (F + 15) // 16, 4):
+            for h in range(B // 16):
+                for v in range(4):
+                    addrs = []
+                    for lane in range(64):
+                        q, lo = lane >> 4, lane & 15
+                        f = (grp * 16 + lo) % F
+                        c, f1 = f & ((1 << logC) - 1), f >> logC
+                        lam0 = (((f1 // bj) * bj * B + f1 % bj) << logC) | c
+                        addrs.append(_phys(lam0 + (16 * h + 4 * q + v) * step, pad))
+                    cost += degree(addrs)
+    return cost
+
+
+@pytest.mark.parametrize("b,n,batch", [(16, 4, 4096), (32, 3, 64), (16, 5, 4)])
+def test_matrix_core_lds_padding(b, n, batch):
+    nopad = 31 | (31 << 8) | (31 << 16)
+    for g in G.Plan(b, n, batch, torch.bfloat16).describe()["groups"]:
+        assert g["kind"] == "mfma"
+        pad, tileE = g["pad_shift"], g["tile_elems"]
+        shifts = [(pad >> (8 * i)) & 31 for i in range(3)]
+        # a 16-byte vector (eight bf16) never straddles a pad; growth <= 1/8
+        assert all(s_ >= 3 for s_ in shifts)
+        assert _phys(tileE, pad) - tileE <= tileE // 8
+        assert g["lds_bytes"] == (_phys(tileE, pad) + 1) * 4
+        logC = g["C"].bit_length() - 1
+        chosen = _mfma_bank_cost(b, g["k"], logC, pad, tileE)
+        plain = _mfma_bank_cost(b, g["k"], logC, nopad, tileE)
+        assert chosen <= plain
+        if g["C"] > 1:  # strided tiles: the unpadded layout conflicts
+            assert chosen < plain
