@@ -116,17 +116,20 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     for (int h = 0; h < NB; ++h)
 #pragma unroll
         for (int v = 0; v < 4; ++v) off[h][v] = lds_phys((16u * h + v) * step, pad);
+    // The fibre's position is f with LB zero bits (digit j) inserted at bit
+    // hj = logC + LB j; for f = 16 grp + i (disjoint bits) the insertion and
+    // lds_phys are additive, so the lane part is fixed for the stage and the
+    // group part is work-group uniform.
+    constexpr uint32_t LB = B == 16 ? 4u : 5u;
+    const uint32_t hj = (uint32_t)a.logC + LB * (uint32_t)j;
+    auto ins = [&](uint32_t v) { return ((v >> hj) << (hj + LB)) | (v & ((1u << hj) - 1u)); };
+    const uint32_t lane_base = lds_phys(ins((uint32_t)(lane & 15)), pad) + qoff;
+    (void)Cm;
+    (void)bj1;
     for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
         const uint32_t f = grp * 16 + (lane & 15);
         const bool valid = f < F;
-        uint32_t base = 0;
-        if (valid) {
-            const uint32_t c = f & Cm;
-            const uint32_t f1 = f >> a.logC;
-            const uint32_t Q = fdiv(f1, a.divb[j]);
-            const uint32_t glo = f1 - Q * bj;
-            base = lds_phys(((Q * bj1 + glo) << a.logC) | c, pad) + qoff;
-        }
+        const uint32_t base = lds_phys(ins(__builtin_amdgcn_readfirstlane(grp) * 16u), pad) + lane_base;
         typename Op::V xb[NB];
 #pragma unroll
         for (int h = 0; h < NB; ++h) {
