@@ -3,6 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "gtt_args.hpp"
 
 namespace gtt {
@@ -23,15 +27,29 @@ inline int device_cus() {
 
 // work-groups of a persistent launch over `tiles` tiles: as many as the
 // device holds at once (occupancy x compute units), at most one per tile
+// work-groups of `kernel` one compute unit holds at once (cached per kernel,
+// block size and LDS size; 0 when the query fails)
+inline int occupancy_cached(const void* kernel, int threads, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, int, size_t>, int> cache;
+    const auto key = std::make_tuple(kernel, threads, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, lds) != hipSuccess) occ = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = occ;
+    return occ;
+}
+
 template <typename K>
 inline unsigned resident_grid(K kernel, int threads, size_t lds, unsigned tiles) {
-    int occ = 0;
     const int cus = device_cus();
-    if (cus <= 0 ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kernel), threads, lds) !=
-            hipSuccess ||
-        occ < 1)
-        return tiles;
+    const int occ = cus > 0 ? occupancy_cached(reinterpret_cast<const void*>(kernel), threads, lds) : 0;
+    if (occ < 1) return tiles;
     const unsigned long long g = (unsigned long long)occ * (unsigned long long)cus;
     return g < tiles ? (unsigned)g : tiles;
 }
