@@ -219,7 +219,7 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
     // matrix-core passes: padding from the bank-conflict search over the
     // tile transfers and the digit passes' fragment loads
     if (gr->kind == kKindMfma && gr->tileE % 64 == 0)
-        pad = mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize));
+        pad = mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize), (int)(16 / esize));
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
         int64_t wtot = 0;
@@ -263,12 +263,13 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     const size_t es = storage_size(dt), cs = compute_size(dt);
     const int b0 = rad[0];
     // specialised kernels: radix <= 8 on the VALU (complex double: <= 5,
-    // larger W would not fit in registers); radix 16 / 32 with 16-bit storage
-    // on the matrix cores; everything else on the runtime-radix kernel
+    // larger W would not fit in registers); radix 16 / 32 with 16-bit or
+    // FP32 storage on the matrix cores; everything else on the runtime-radix
+    // kernel
     int kind = kKindGeneric;
     // (the one-launch ragged kernel carries the VALU code for radix <= 5 only)
     if (uniform && (b0 <= 5 || (b0 <= 8 && dt != GTT_C128 && !ragged))) kind = kKindValu;
-    if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16)) kind = kKindMfma;
+    if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16 || dt == GTT_F32)) kind = kKindMfma;
     if (uniform && b0 == 8 && dt == GTT_C64 && !ragged) kind = kKindCMfma;
     const bool small_b = kind != kKindGeneric;
     int tb = 0, tr = 0, tk = 0;

@@ -199,10 +199,10 @@ FastMap search(int K, int NI, int logC, bool gw) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// LDS padding of the bf16 / f16 matrix-core passes (FP32 tile, radix 16 /
-// 32).  The tile transfers move a 16-byte vector (eight elements) per
-// thread as eight 32-bit LDS accesses, so the lanes of one access sit eight
-// elements apart; a digit pass reads and writes element 16 h + 4 q + v of
+// LDS padding of the matrix-core passes (FP32 tile, radix 16 / 32).  The
+// tile transfers move a 16-byte vector (vec = 8 elements of bf16 / f16, 4
+// of f32) per thread as vec 32-bit LDS accesses, so the lanes of one access
+// sit vec elements apart; a digit pass reads and writes element 16 h + 4 q + v of
 // the fibre of lane (q, i), 16 fibres by four q.  Each 32-bit access costs
 // its half-waves' worst bank degree (32 banks); the search takes the pad
 // triple (each level one element) with the least total cost over a sample
@@ -224,14 +224,14 @@ int conflict32(const uint32_t* e) {
     return worst;
 }
 
-int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE) {
+int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t vec) {
     int tot = 0;
     uint32_t e[32];
-    const uint32_t nvec = tileE / 8;
+    const uint32_t nvec = tileE / vec;
     for (uint32_t w0 = 0; w0 + 64 <= nvec; w0 += 256)
-        for (uint32_t el = 0; el < 8; ++el)
+        for (uint32_t el = 0; el < vec; ++el)
             for (uint32_t half = 0; half < 2; ++half) {
-                for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(8u * (w0 + 32u * half + l) + el);
+                for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(vec * (w0 + 32u * half + l) + el);
                 tot += 2 * conflict32(e);  // load and store
             }
     const uint32_t F = tileE / (uint32_t)B;
@@ -257,9 +257,9 @@ int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE) {
     return tot;
 }
 
-int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift) {
+int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift, uint32_t vec) {
     Pads best{{31, 31, 31}, 0};
-    int best_cost = mfma_cost(best, B, k, logC, tileE);
+    int best_cost = mfma_cost(best, B, k, logC, tileE, vec);
     uint32_t best_extra = 0;
     std::vector<int> sh;
     for (int p = min_shift; p <= 13; ++p) sh.push_back(p);
@@ -271,7 +271,7 @@ int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift) {
                 if (b == sh.size() && c < sh.size()) continue;
                 const uint32_t extra = pd.phys(tileE) - tileE;
                 if (extra > tileE / 8) continue;
-                const int cst = mfma_cost(pd, B, k, logC, tileE);
+                const int cst = mfma_cost(pd, B, k, logC, tileE, vec);
                 if (cst < best_cost || (cst == best_cost && extra < best_extra)) {
                     best = pd;
                     best_cost = cst;
@@ -283,14 +283,14 @@ int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift) {
 
 }  // namespace
 
-int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift) {
+int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int64_t, int>, int> cache;
-    const auto key = std::make_tuple(B, k, logC, tileE, min_shift);
+    static std::map<std::tuple<int, int, int, int64_t, int, int>, int> cache;
+    const auto key = std::make_tuple(B, k, logC, tileE, min_shift, vec);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    const int pad = mfma_search(B, k, logC, (uint32_t)tileE, min_shift);
+    const int pad = mfma_search(B, k, logC, (uint32_t)tileE, min_shift, (uint32_t)vec);
     cache[key] = pad;
     return pad;
 }

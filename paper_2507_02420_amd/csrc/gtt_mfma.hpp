@@ -1,5 +1,5 @@
 // Digit-group pass on the matrix cores for radix 16 and 32 with bf16 / f16
-// storage.  Each digit pass is the product Y = W X (§3: Y = X W^T in the
+// storage (and FP32 storage on the FP32 MFMA, see WFrag<float, B>).  Each digit pass is the product Y = W X (§3: Y = X W^T in the
 // paper's row layout) with X the b x F matrix whose columns are the fibres of
 // that digit, a dense contraction that maps onto the 16x16x16 MFMA:
 //   A operand (W, 16 x 16 block): lane l holds W[i = l%16][4*(l/16) + 0..3];
@@ -13,6 +13,8 @@
 // and a low 16-bit part (two MFMAs) so that its rounding adds no error, and
 // accumulation is FP32.
 #pragma once
+
+#include <type_traits>
 
 #include "gtt_args.hpp"
 #include "gtt_pass.hpp"
@@ -70,12 +72,21 @@ struct WFrag {
     typename MfmaOp<T>::V hi[NB][NB], lo[NB][NB];
 };
 
+// FP32 storage: W as FP32 operands of the 16x16x4 FP32 MFMA.  MFMA v of a
+// 16 x 16 block contracts the columns 4q + v (q = lane / 16): lane (q, i)
+// holds W[i][4q + v] and the fibre's element 4q + v, so the same fragment
+// layout (four consecutive digit values per lane) takes four FP32 MFMAs
+// instead of the 16-bit hi / lo pair.
+template <int B>
+struct WFrag<float, B> {
+    static constexpr int NB = B / 16;
+    float w[NB][NB][4];
+};
+
 template <typename T, int B>
-__device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) {
+__device__ __forceinline__ void load_w_frag16(WFrag<T, B>& wf, const float* __restrict__ Wg, int adjoint, int i,
+                                              int q) {
     using Op = MfmaOp<T>;
-    const float* __restrict__ Wg = static_cast<const float*>(a.W);
-    const int lane = threadIdx.x & 63;
-    const int i = lane & 15, q = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < WFrag<T, B>::NB; ++bi)
 #pragma unroll
@@ -83,7 +94,7 @@ __device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * bi + i, c = 16 * bk + 4 * q + v;
-                const float w = a.adjoint ? Wg[c * B + r] : Wg[r * B + c];
+                const float w = adjoint ? Wg[c * B + r] : Wg[r * B + c];
                 typename Op::E h, l;
                 Op::split(w, &h, &l);
                 wf.hi[bi][bk][v] = h;
@@ -91,11 +102,31 @@ __device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) 
             }
 }
 
+template <typename T, int B>
+__device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) {
+    const float* __restrict__ Wg = static_cast<const float*>(a.W);
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, q = lane >> 4;
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+        for (int bi = 0; bi < WFrag<T, B>::NB; ++bi)
+#pragma unroll
+            for (int bk = 0; bk < WFrag<T, B>::NB; ++bk)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * bi + i, c = 16 * bk + 4 * q + v;
+                    wf.w[bi][bk][v] = a.adjoint ? Wg[c * B + r] : Wg[r * B + c];
+                }
+        return;
+    } else {
+        load_w_frag16<T, B>(wf, Wg, a.adjoint, i, q);
+    }
+}
+
 // W along digit j of every fibre of the FP32 tile, in place, on MFMA.
 template <typename T, int B>
 __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j, uint32_t rows,
                                            const WFrag<T, B>& wf) {
-    using Op = MfmaOp<T>;
     constexpr int NB = B / 16;
     const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t F = (rows << a.logC) / B;
@@ -130,26 +161,42 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
         const uint32_t f = grp * 16 + (lane & 15);
         const bool valid = f < F;
         const uint32_t base = lds_phys(ins(__builtin_amdgcn_readfirstlane(grp) * 16u), pad) + lane_base;
-        typename Op::V xb[NB];
+        float x[NB][4];
 #pragma unroll
-        for (int h = 0; h < NB; ++h) {
-            float x[4];
+        for (int h = 0; h < NB; ++h)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = valid ? lds[base + off[h][v]] : 0.f;
-            xb[h] = Op::pack(x);
+            for (int v = 0; v < 4; ++v) x[h][v] = valid ? lds[base + off[h][v]] : 0.f;
+        f32x4 acc[NB];
+        if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+                acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int bk = 0; bk < NB; ++bk)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf.w[bi][bk][v], x[bk][v], acc[bi], 0, 0, 0);
+            }
+        } else {
+            using Op = MfmaOp<T>;
+            typename Op::V xb[NB];
+#pragma unroll
+            for (int h = 0; h < NB; ++h) xb[h] = Op::pack(x[h]);
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+                acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int bk = 0; bk < NB; ++bk) {
+                    acc[bi] = Op::mma(wf.hi[bi][bk], xb[bk], acc[bi]);
+                    acc[bi] = Op::mma(wf.lo[bi][bk], xb[bk], acc[bi]);
+                }
+            }
         }
+        if (valid) {
 #pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-            for (int bk = 0; bk < NB; ++bk) {
-                acc = Op::mma(wf.hi[bi][bk], xb[bk], acc);
-                acc = Op::mma(wf.lo[bi][bk], xb[bk], acc);
-            }
-            if (valid) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) lds[base + off[bi][v]] = acc[v];
-            }
+                for (int v = 0; v < 4; ++v) lds[base + off[bi][v]] = acc[bi][v];
         }
     }
 }

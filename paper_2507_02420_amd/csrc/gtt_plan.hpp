@@ -47,9 +47,10 @@ struct FastMap {
     int conflicts = 0;  // residual bank conflicts of the layout (0: none)
 };
 FastMap fast_map(int K, int NI, int logC, bool gw);
-// LDS padding (packed shifts) of a bf16 / f16 matrix-core pass: radix B, k
-// digits, 2^logC columns, tileE elements, no shift below min_shift
-int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift);
+// LDS padding (packed shifts) of a matrix-core pass (FP32 tile): radix B, k
+// digits, 2^logC columns, tileE elements, no shift below min_shift, vec
+// elements per 16-byte tile transfer
+int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec);
 
 enum class PlanKind { Uniform, Ragged, Mixed };
 

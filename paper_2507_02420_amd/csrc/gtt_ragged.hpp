@@ -223,7 +223,7 @@ __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArg
                 default: ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
             }
         } else if (d.kind == kKindMfma) {
-            if constexpr (sizeof(T) == 2) {
+            if constexpr (sizeof(T) == 2 || std::is_same<T, float>::value) {
                 if (d.b == 16)
                     ragged_tile_mfma<T, 16>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
                 else
@@ -236,7 +236,9 @@ __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArg
         ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile);
     } else if constexpr (CLS <= 5) {
         ragged_tile_valu<T, CLS>(smem, d.a, in, out, W, r.adjoint, it.tile);
-    } else if constexpr (sizeof(T) == 2) {
+    } else {
+        static_assert(sizeof(T) == 2 || std::is_same<T, float>::value,
+                      "matrix-core item classes exist for 16-bit and float storage only");
         ragged_tile_mfma<T, CLS>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
     }
 }

@@ -1,5 +1,6 @@
 // Instantiations of the digit-group pass kernels for storage type float.
 #include "gtt_launch.hpp"
+#include "gtt_mfma.hpp"
 #include "gtt_pass.hpp"
 
 namespace gtt {
@@ -33,7 +34,12 @@ hipError_t launch_pass_f32(int b, int kind, const PassArgs& a, unsigned grid, si
     if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
-        return hipErrorInvalidValue;
+        if (b == 16)
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 16>));
+        else if (b == 32)
+            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 32>));
+        else
+            return hipErrorInvalidValue;
     } else {
         switch (b) {
             case 2: GTT_LAUNCH_VALU(2); break;

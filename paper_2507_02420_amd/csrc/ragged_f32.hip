@@ -39,6 +39,8 @@ hipError_t launch_ragged_cls_f32(int cls, const RaggedArgs& a, unsigned grid, si
         case 3: K_(3); break;
         case 4: K_(4); break;
         case 5: K_(5); break;
+        case 16: K_(16); break;
+        case 32: K_(32); break;
         default: return hipErrorInvalidValue;
     }
 #undef K_

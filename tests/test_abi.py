@@ -194,7 +194,7 @@ def _phys(x, pad):
     return x + sum(x >> ((pad >> (8 * i)) & 31) for i in range(3))
 
 
-def _mfma_bank_cost(B, k, logC, pad, tileE):
+def _mfma_bank_cost(B, k, logC, pad, tileE, vec=8):
     # worst bank degree per half-wave (32 banks) of the 32-bit LDS accesses
     # of a bf16 matrix-core pass: tile transfers (eight elements a thread),
     # then per digit element 4q+v of the fibre of lane (q, i); a sample of
@@ -208,9 +208,9 @@ def _mfma_bank_cost(B, k, logC, pad, tileE):
             tot += max(len(v) for v in per.values())
         return tot
     cost = 0
-    for w0 in range(0, tileE // 8 - 63, 256):
-        for e in range(8):
-            cost += degree([_phys(8 * (w0 + l) + e, pad) for l in range(64)])
+    for w0 in range(0, tileE // vec - 63, 256):
+        for e in range(vec):
+            cost += degree([_phys(vec * (w0 + l) + e, pad) for l in range(64)])
     F = tileE // B
     for j in range(k):
         bj = B ** j
@@ -229,20 +229,22 @@ def _mfma_bank_cost(B, k, logC, pad, tileE):
     return cost
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32], ids=str)
 @pytest.mark.parametrize("b,n,batch", [(16, 4, 4096), (32, 3, 64), (16, 5, 4)])
-def test_matrix_core_lds_padding(b, n, batch):
+def test_matrix_core_lds_padding(b, n, batch, dtype):
     nopad = 31 | (31 << 8) | (31 << 16)
-    for g in G.Plan(b, n, batch, torch.bfloat16).describe()["groups"]:
+    vec = 16 // torch.empty(0, dtype=dtype).element_size()   # elements per 16-byte transfer
+    for g in G.Plan(b, n, batch, dtype).describe()["groups"]:
         assert g["kind"] == "mfma"
         pad, tileE = g["pad_shift"], g["tile_elems"]
         shifts = [(pad >> (8 * i)) & 31 for i in range(3)]
-        # a 16-byte vector (eight bf16) never straddles a pad; growth <= 1/8
-        assert all(s_ >= 3 for s_ in shifts)
+        # a 16-byte vector never straddles a pad; growth <= 1/8
+        assert all((1 << s_) >= vec for s_ in shifts)
         assert _phys(tileE, pad) - tileE <= tileE // 8
         assert g["lds_bytes"] == (_phys(tileE, pad) + 1) * 4
         logC = g["C"].bit_length() - 1
-        chosen = _mfma_bank_cost(b, g["k"], logC, pad, tileE)
-        plain = _mfma_bank_cost(b, g["k"], logC, nopad, tileE)
+        chosen = _mfma_bank_cost(b, g["k"], logC, pad, tileE, vec)
+        plain = _mfma_bank_cost(b, g["k"], logC, nopad, tileE, vec)
         assert chosen <= plain
         if g["C"] > 1:  # strided tiles: the unpadded layout conflicts
             assert chosen < plain
