@@ -218,8 +218,12 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
     }
     // matrix-core passes: padding from the bank-conflict search over the
     // tile transfers and the digit passes' fragment loads
+    // (a 16-bit tile, csize 2: pads count 32-bit words, a 16-byte vector is
+    // four of them)
+    const bool lds16 = gr->kind == kKindMfma && csize == 2;
     if (gr->kind == kKindMfma && gr->tileE % 64 == 0)
-        pad = mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize), (int)(16 / esize));
+        pad = lds16 ? mfma_pad(rad[s0], k, gr->logC, gr->tileE, 2, 8, true)
+                    : mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize), (int)(16 / esize), false);
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
         int64_t wtot = 0;
@@ -228,7 +232,7 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * tileE) * csize;
         gr->pad_shift = kNoPad;
     } else {
-        const int64_t phys = lds_tile_elems_host(tileE, pad);
+        const int64_t phys = lds16 ? 2 * lds_tile_elems_host((tileE + 1) / 2, pad) : lds_tile_elems_host(tileE, pad);
         gr->wtotal = 0;
         gr->lds_bytes = (size_t)phys * csize;
     }
@@ -272,6 +276,8 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     if (uniform && (b0 == 16 || b0 == 32) && (dt == GTT_BF16 || dt == GTT_F16 || dt == GTT_F32)) kind = kKindMfma;
     if (uniform && b0 == 8 && dt == GTT_C64 && !ragged) kind = kKindCMfma;
     const bool small_b = kind != kKindGeneric;
+    // the bf16 / f16 matrix-core pass keeps its tile in the storage type
+    const size_t cs_fwd = (kind == kKindMfma && es == 2) ? es : cs;
     int tb = 0, tr = 0, tk = 0;
     tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr, &tk);
     std::vector<int64_t> budgets;
@@ -287,7 +293,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     for (int64_t relax_row = min_row_bytes; relax_row >= (int64_t)es; relax_row /= 2) {
         for (int R = 1; R <= n; ++R) {
             for (int64_t bud : budgets) {
-                int64_t T = bud / (int64_t)cs;
+                int64_t T = bud / (int64_t)cs_fwd;
                 if (!small_b) T /= 2;  // the runtime-radix kernel double-buffers
                 const int64_t cmin = std::max<int64_t>(1, relax_row / (int64_t)es);
                 std::vector<int> ks;
@@ -297,7 +303,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                 int s = 0;
                 for (int k : ks) {
                     Group g;
-                    fill_group(&g, rad, s, k, total, T, es, cs, kind, cmin);
+                    fill_group(&g, rad, s, k, total, T, es, cs_fwd, kind, cmin);
                     groups->push_back(g);
                     s += k;
                 }

@@ -199,14 +199,18 @@ FastMap search(int K, int NI, int logC, bool gw) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// LDS padding of the matrix-core passes (FP32 tile, radix 16 / 32).  The
-// tile transfers move a 16-byte vector (vec = 8 elements of bf16 / f16, 4
-// of f32) per thread as vec 32-bit LDS accesses, so the lanes of one access
-// sit vec elements apart; a digit pass reads and writes element 16 h + 4 q + v of
-// the fibre of lane (q, i), 16 fibres by four q.  Each 32-bit access costs
-// its half-waves' worst bank degree (32 banks); the search takes the pad
-// triple (each level one element) with the least total cost over a sample
-// of the tile, LDS growth at most 1/8.
+// LDS padding of the matrix-core passes (radix 16 / 32).  FP32 tile (f32
+// storage): element x at word lds_phys(x); 16-bit tile (bf16 / f16): element
+// x in word lds_phys(x >> 1), the pads counting words.  The tile transfers
+// move a 16-byte vector per thread as 32-bit accesses, so the lanes of one
+// access sit four words apart; a digit pass reads and writes element
+// 16 h + 4 q + v of the fibre of lane (q, i), 16 fibres by four q: four
+// 32-bit accesses (FP32), two word accesses (16-bit, contiguous digit) or
+// four 16-bit accesses (16-bit, strided digit; two lanes in one word do not
+// conflict).  Each access costs its half-waves' worst bank degree (32
+// banks); the search takes the pad triple (each level one element or word)
+// with the least total cost over a sample of the tile, LDS growth at most
+// 1/8.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -224,14 +228,15 @@ int conflict32(const uint32_t* e) {
     return worst;
 }
 
-int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t vec) {
+int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t vec, bool lds16) {
     int tot = 0;
     uint32_t e[32];
     const uint32_t nvec = tileE / vec;
+    const uint32_t nw = lds16 ? vec / 2 : vec;  // words per vector
     for (uint32_t w0 = 0; w0 + 64 <= nvec; w0 += 256)
-        for (uint32_t el = 0; el < vec; ++el)
+        for (uint32_t el = 0; el < nw; ++el)
             for (uint32_t half = 0; half < 2; ++half) {
-                for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(vec * (w0 + 32u * half + l) + el);
+                for (uint32_t l = 0; l < 32; ++l) e[l] = pd.phys(nw * (w0 + 32u * half + l) + el);
                 tot += 2 * conflict32(e);  // load and store
             }
     const uint32_t F = tileE / (uint32_t)B;
@@ -239,9 +244,10 @@ int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t v
     uint32_t bj = 1;
     for (int j = 0; j < k; ++j, bj *= (uint32_t)B) {
         const uint32_t bj1 = bj * (uint32_t)B, step = bj << logC;
+        const bool pairs = lds16 && step == 1;
         for (uint32_t grp = 0; grp < (F + 15) / 16; grp += 4)
             for (int h = 0; h < B / 16; ++h)
-                for (uint32_t v = 0; v < 4; ++v)
+                for (uint32_t v = 0; v < 4; v += pairs ? 2 : 1)
                     for (uint32_t half = 0; half < 2; ++half) {
                         for (uint32_t l = 0; l < 32; ++l) {
                             const uint32_t lane = 32u * half + l, q = lane >> 4, lo = lane & 15u;
@@ -249,7 +255,8 @@ int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t v
                             const uint32_t c = f & Cm, f1 = f >> logC;
                             const uint32_t Q = f1 / bj, glo = f1 % bj;
                             const uint32_t lam0 = ((Q * bj1 + glo) << logC) | c;
-                            e[l] = pd.phys(lam0 + (16u * h + 4u * q + v) * step);
+                            const uint32_t x = lam0 + (16u * h + 4u * q + v) * step;
+                            e[l] = lds16 ? pd.phys(x >> 1) : pd.phys(x);
                         }
                         tot += 2 * conflict32(e);
                     }
@@ -257,9 +264,10 @@ int mfma_cost(const Pads& pd, int B, int k, int logC, uint32_t tileE, uint32_t v
     return tot;
 }
 
-int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift, uint32_t vec) {
+int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift, uint32_t vec, bool lds16) {
     Pads best{{31, 31, 31}, 0};
-    int best_cost = mfma_cost(best, B, k, logC, tileE, vec);
+    const uint32_t units = lds16 ? (tileE + 1) / 2 : tileE;  // padded elements or words
+    int best_cost = mfma_cost(best, B, k, logC, tileE, vec, lds16);
     uint32_t best_extra = 0;
     std::vector<int> sh;
     for (int p = min_shift; p <= 13; ++p) sh.push_back(p);
@@ -269,9 +277,9 @@ int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift, uint32_t 
                 Pads pd{{sh[a], b < sh.size() ? sh[b] : 31, c < sh.size() ? sh[c] : 31}, 0};
                 pd.n = 1 + (b < sh.size()) + (c < sh.size());
                 if (b == sh.size() && c < sh.size()) continue;
-                const uint32_t extra = pd.phys(tileE) - tileE;
-                if (extra > tileE / 8) continue;
-                const int cst = mfma_cost(pd, B, k, logC, tileE, vec);
+                const uint32_t extra = pd.phys(units) - units;
+                if (extra > units / 8) continue;
+                const int cst = mfma_cost(pd, B, k, logC, tileE, vec, lds16);
                 if (cst < best_cost || (cst == best_cost && extra < best_extra)) {
                     best = pd;
                     best_cost = cst;
@@ -283,14 +291,14 @@ int mfma_search(int B, int k, int logC, uint32_t tileE, int min_shift, uint32_t 
 
 }  // namespace
 
-int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec) {
+int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec, bool lds16) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int64_t, int, int>, int> cache;
-    const auto key = std::make_tuple(B, k, logC, tileE, min_shift, vec);
+    static std::map<std::tuple<int, int, int, int64_t, int, int, bool>, int> cache;
+    const auto key = std::make_tuple(B, k, logC, tileE, min_shift, vec, lds16);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    const int pad = mfma_search(B, k, logC, (uint32_t)tileE, min_shift, (uint32_t)vec);
+    const int pad = mfma_search(B, k, logC, (uint32_t)tileE, min_shift, (uint32_t)vec, lds16);
     cache[key] = pad;
     return pad;
 }

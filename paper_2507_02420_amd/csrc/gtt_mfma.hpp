@@ -1,17 +1,23 @@
-// Digit-group pass on the matrix cores for radix 16 and 32 with bf16 / f16
-// storage (and FP32 storage on the FP32 MFMA, see WFrag<float, B>).  Each digit pass is the product Y = W X (§3: Y = X W^T in the
-// paper's row layout) with X the b x F matrix whose columns are the fibres of
-// that digit, a dense contraction that maps onto the 16x16x16 MFMA:
+// Digit-group pass on the matrix cores for radix 16 and 32.  Each digit pass
+// is the product Y = W X (§3: Y = X W^T in the paper's row layout) with X the
+// b x F matrix whose columns are the fibres of that digit, a dense
+// contraction on 16 x 16 blocks of W:
 //   A operand (W, 16 x 16 block): lane l holds W[i = l%16][4*(l/16) + 0..3];
 //   B operand (X, 16 x 16 block): lane l holds X[4*(l/16) + 0..3][fibre l%16];
 //   result: lane l holds Y[4*(l/16) + 0..3][fibre l%16].
 // Input and output fragments have the same layout, so a wave reads four
 // consecutive elements of its fibre from LDS, runs the MFMAs and writes four
 // consecutive results back in place.  Radix 32 uses the 2 x 2 blocks of W.
-// The tile stays FP32 in LDS between digits; the operand of every MFMA is
-// rounded to the 16-bit type (round to nearest even), W is split into a high
-// and a low 16-bit part (two MFMAs) so that its rounding adds no error, and
-// accumulation is FP32.
+//
+// bf16 / f16 storage (16x16x16 MFMA): the tile stays in LDS in the storage
+// type.  Every MFMA operand is the 16-bit rounding (nearest even) of the
+// previous digit's FP32 result, so rounding each result once as it is
+// written back is the same arithmetic as keeping it FP32 in LDS and
+// rounding it on the next read, at half the LDS bytes per element (twice the
+// elements per tile for the same LDS).  W is split into a high and a low
+// 16-bit part (two MFMAs) so that its rounding adds no error; accumulation
+// is FP32.
+// FP32 storage (16x16x4 FP32 MFMA, see WFrag<float, B>): FP32 tile, W unsplit.
 #pragma once
 
 #include <type_traits>
@@ -123,10 +129,11 @@ __device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) 
     }
 }
 
-// W along digit j of every fibre of the FP32 tile, in place, on MFMA.
+// W along digit j of every fibre of the FP32 tile, in place, on the FP32 MFMA.
 template <typename T, int B>
 __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j, uint32_t rows,
                                            const WFrag<T, B>& wf) {
+    static_assert(std::is_same<T, float>::value, "16-bit storage runs mfma_stage16");
     constexpr int NB = B / 16;
     const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t F = (rows << a.logC) / B;
@@ -167,30 +174,14 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
 #pragma unroll
             for (int v = 0; v < 4; ++v) x[h][v] = valid ? lds[base + off[h][v]] : 0.f;
         f32x4 acc[NB];
-        if constexpr (std::is_same<T, float>::value) {
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-                acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int bi = 0; bi < NB; ++bi) {
+            acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int bk = 0; bk < NB; ++bk)
+            for (int bk = 0; bk < NB; ++bk)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf.w[bi][bk][v], x[bk][v], acc[bi], 0, 0, 0);
-            }
-        } else {
-            using Op = MfmaOp<T>;
-            typename Op::V xb[NB];
-#pragma unroll
-            for (int h = 0; h < NB; ++h) xb[h] = Op::pack(x[h]);
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
-                acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int bk = 0; bk < NB; ++bk) {
-                    acc[bi] = Op::mma(wf.hi[bi][bk], xb[bk], acc[bi]);
-                    acc[bi] = Op::mma(wf.lo[bi][bk], xb[bk], acc[bi]);
-                }
-            }
+                for (int v = 0; v < 4; ++v)
+                    acc[bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(wf.w[bi][bk][v], x[bk][v], acc[bi], 0, 0, 0);
         }
         if (valid) {
 #pragma unroll
@@ -201,18 +192,208 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     }
 }
 
+// ---- 16-bit tiles ----------------------------------------------------------
+// Element x of a 16-bit tile sits at 16-bit position
+// 2 * lds_phys(x >> 1, pad) + (x & 1): the pads count 32-bit words, so an
+// aligned element pair is one word and a 16-byte vector (eight elements)
+// four consecutive words (pad shifts >= 2).  Like lds_phys, the map is
+// additive over disjoint bits.
+__device__ __forceinline__ uint32_t lds_phys16(uint32_t x, int pad) { return 2u * lds_phys(x >> 1, pad) + (x & 1u); }
+
+template <typename T>
+__device__ __forceinline__ void tile_load16(uint16_t* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
+                                            uint32_t rows) {
+    static_assert(sizeof(T) == 2, "16-bit storage");
+    const uint32_t tileE = rows << a.logC;
+    const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    const uint16_t* __restrict__ src = reinterpret_cast<const uint16_t*>(in);
+    uint32_t* w = reinterpret_cast<uint32_t*>(lds);
+    if (a.mode == kContigVec || a.mode == kRowVec) {
+        const uint32_t nvec = tileE / 8;
+        for (uint32_t i0 = 0; i0 < nvec; i0 += kLoadBatch * kThreads) {
+            uint4 buf[kLoadBatch];
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < nvec) buf[v] = *reinterpret_cast<const uint4*>(src + vec_offset<T>(a, t, i, hb, l, tileE));
+            }
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < nvec) {
+                    uint32_t d[4] = {buf[v].x, buf[v].y, buf[v].z, buf[v].w};
+                    if (a.cut >= 0) {  // natural-order mask of the filter
+                        const int64_t off = vec_offset<T>(a, t, i, hb, l, tileE);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const bool low = (off + e) % a.N < a.cut;
+                            if (low == (a.cut_keep_high != 0)) d[e >> 1] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
+                        }
+                    }
+                    const uint32_t ph = lds_phys(4u * i, a.pad_shift);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w[ph + e] = d[e];
+                }
+            }
+        }
+    } else {
+        for (uint32_t i0 = 0; i0 < tileE; i0 += kLoadBatch * kThreads) {
+            uint16_t buf[kLoadBatch];
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < tileE) {
+                    const int64_t off = elem_offset(a, t, i, hb, l, tileE);
+                    if (off >= 0 && (a.cut < 0 || ((off % a.N < a.cut) != (a.cut_keep_high != 0))))
+                        buf[v] = src[off];
+                    else
+                        buf[v] = 0;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                if (i < tileE) lds[lds_phys16(i, a.pad_shift)] = buf[v];
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_store16(const uint16_t* lds, const PassArgs& a, T* __restrict__ out, int64_t t,
+                                             uint32_t rows) {
+    static_assert(sizeof(T) == 2, "16-bit storage");
+    const uint32_t tileE = rows << a.logC;
+    const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
+    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t l = contig ? 0 : t - hb * a.L;
+    uint16_t* __restrict__ dst = reinterpret_cast<uint16_t*>(out);
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(lds);
+    if (a.mode == kContigVec || a.mode == kRowVec) {
+        const uint32_t nvec = tileE / 8;
+        for (uint32_t i = threadIdx.x; i < nvec; i += kThreads) {
+            const uint32_t ph = lds_phys(4u * i, a.pad_shift);
+            const uint4 d = make_uint4(w[ph], w[ph + 1], w[ph + 2], w[ph + 3]);
+            gstore16<true>(dst + vec_offset<T>(a, t, i, hb, l, tileE), d);
+        }
+    } else {
+        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+            const int64_t off = elem_offset(a, t, i, hb, l, tileE);
+            if (off >= 0) dst[off] = lds[lds_phys16(i, a.pad_shift)];
+        }
+    }
+}
+
+// W along digit j of every fibre of a 16-bit tile, in place: the values
+// read are the MFMA operands as they stand, the FP32 results are rounded to
+// the storage type as they are written back.  A contiguous digit (step 1)
+// moves the four elements of a fragment as two 32-bit words.
+template <typename T, int B>
+__device__ __forceinline__ void mfma_stage16(uint16_t* lds, const PassArgs& a, int j, uint32_t rows,
+                                             const WFrag<T, B>& wf) {
+    using Op = MfmaOp<T>;
+    using V = typename Op::V;
+    constexpr int NB = B / 16;
+    const uint32_t F = (rows << a.logC) / B;
+    const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int q = lane >> 4;
+    const uint32_t ngrp = (F + 15) / 16;
+    const int pad = a.pad_shift;
+    const uint32_t qoff = lds_phys16(4u * q * step, pad);
+    uint32_t off[NB][4];
+#pragma unroll
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) off[h][v] = lds_phys16((16u * h + v) * step, pad);
+    constexpr uint32_t LB = B == 16 ? 4u : 5u;
+    const uint32_t hj = (uint32_t)a.logC + LB * (uint32_t)j;
+    auto ins = [&](uint32_t v) { return ((v >> hj) << (hj + LB)) | (v & ((1u << hj) - 1u)); };
+    const uint32_t lane_base = lds_phys16(ins((uint32_t)(lane & 15)), pad) + qoff;
+    // step 1: every fragment starts at an even position (all address terms
+    // are even), so elements (0, 1) and (2, 3) are words
+    const bool pairs = step == 1u;
+    uint32_t* w32 = reinterpret_cast<uint32_t*>(lds);
+    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+        const uint32_t f = grp * 16 + (lane & 15);
+        const bool valid = f < F;
+        const uint32_t base = lds_phys16(ins(__builtin_amdgcn_readfirstlane(grp) * 16u), pad) + lane_base;
+        V xb[NB];
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            uint32_t d0 = 0, d1 = 0;
+            if (valid) {
+                if (pairs) {
+                    d0 = w32[(base + off[h][0]) >> 1];
+                    d1 = w32[(base + off[h][2]) >> 1];
+                } else {
+                    d0 = (uint32_t)lds[base + off[h][0]] | ((uint32_t)lds[base + off[h][1]] << 16);
+                    d1 = (uint32_t)lds[base + off[h][2]] | ((uint32_t)lds[base + off[h][3]] << 16);
+                }
+            }
+            xb[h] = __builtin_bit_cast(V, make_uint2(d0, d1));
+        }
+        f32x4 acc[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int bk = 0; bk < NB; ++bk) {
+                acc[bi] = Op::mma(wf.hi[bi][bk], xb[bk], acc[bi]);
+                acc[bi] = Op::mma(wf.lo[bi][bk], xb[bk], acc[bi]);
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) {
+                const float r[4] = {acc[bi][0], acc[bi][1], acc[bi][2], acc[bi][3]};
+                const uint2 d = __builtin_bit_cast(uint2, Op::pack(r));
+                if (pairs) {
+                    w32[(base + off[bi][0]) >> 1] = d.x;
+                    w32[(base + off[bi][2]) >> 1] = d.y;
+                } else {
+                    lds[base + off[bi][0]] = (uint16_t)d.x;
+                    lds[base + off[bi][1]] = (uint16_t)(d.x >> 16);
+                    lds[base + off[bi][2]] = (uint16_t)d.y;
+                    lds[base + off[bi][3]] = (uint16_t)(d.y >> 16);
+                }
+            }
+        }
+    }
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float* lds = reinterpret_cast<float*>(smem_raw);
     WFrag<T, B> wf;
     load_w_frag<T, B>(wf, a);
-    tile_loop<T, float>(lds, a, [&](float* t, uint32_t rows) {
-        for (int j = 0; j < a.k; ++j) {
-            mfma_stage<T, B>(t, a, j, rows, wf);
+    if constexpr (std::is_same<T, float>::value) {
+        float* lds = reinterpret_cast<float*>(smem_raw);
+        tile_loop<T, float>(lds, a, [&](float* t, uint32_t rows) {
+            for (int j = 0; j < a.k; ++j) {
+                mfma_stage<T, B>(t, a, j, rows, wf);
+                __syncthreads();
+            }
+        });
+    } else {
+        uint16_t* lds = reinterpret_cast<uint16_t*>(smem_raw);
+        const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+        const T* in = static_cast<const T*>(a.in);
+        T* out = static_cast<T*>(a.out);
+        for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+            tile_load16<T>(lds, a, in, t, rows);
+            __syncthreads();
+            for (int j = 0; j < a.k; ++j) {
+                mfma_stage16<T, B>(lds, a, j, rows, wf);
+                __syncthreads();
+            }
+            tile_store16<T>(lds, a, out, t, rows);
             __syncthreads();
         }
-    });
+    }
 }
 
 }  // namespace gtt

@@ -47,10 +47,11 @@ struct FastMap {
     int conflicts = 0;  // residual bank conflicts of the layout (0: none)
 };
 FastMap fast_map(int K, int NI, int logC, bool gw);
-// LDS padding (packed shifts) of a matrix-core pass (FP32 tile): radix B, k
-// digits, 2^logC columns, tileE elements, no shift below min_shift, vec
-// elements per 16-byte tile transfer
-int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec);
+// LDS padding (packed shifts) of a matrix-core pass: radix B, k digits,
+// 2^logC columns, tileE elements, no shift below min_shift, vec elements per
+// 16-byte tile transfer; lds16: a 16-bit tile whose pads count 32-bit words
+// (else an FP32 tile, pads in elements)
+int mfma_pad(int B, int k, int logC, int64_t tileE, int min_shift, int vec, bool lds16);
 
 enum class PlanKind { Uniform, Ragged, Mixed };
 

@@ -124,20 +124,31 @@ __device__ __forceinline__ void ragged_tile_valu(unsigned char* smem, const Pass
 template <typename T, int B>
 __device__ __forceinline__ void ragged_tile_mfma(unsigned char* smem, const PassArgs& a, const T* in, T* out,
                                               const float* W, int adjoint, int64_t t) {
-    float* lds = reinterpret_cast<float*>(smem) + 64;
     PassArgs aw;  // only W / adjoint are read by the fragment loader
     aw.W = W;
     aw.adjoint = adjoint;
     WFrag<T, B> wf;
     load_w_frag<T, B>(wf, aw);
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    tile_load<T, float>(lds, a, in, t, rows);
-    __syncthreads();
-    for (int j = 0; j < a.k; ++j) {
-        mfma_stage<T, B>(lds, a, j, rows, wf);
+    if constexpr (std::is_same<T, float>::value) {
+        float* lds = reinterpret_cast<float*>(smem + 256);
+        tile_load<T, float>(lds, a, in, t, rows);
         __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            mfma_stage<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        tile_store<T, float>(lds, a, out, t, rows);
+    } else {
+        uint16_t* lds = reinterpret_cast<uint16_t*>(smem + 256);
+        tile_load16<T>(lds, a, in, t, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            mfma_stage16<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        tile_store16<T>(lds, a, out, t, rows);
     }
-    tile_store<T, float>(lds, a, out, t, rows);
     __syncthreads();
 }
 

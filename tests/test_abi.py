@@ -194,11 +194,13 @@ def _phys(x, pad):
     return x + sum(x >> ((pad >> (8 * i)) & 31) for i in range(3))
 
 
-def _mfma_bank_cost(B, k, logC, pad, tileE, vec=8):
-    # worst bank degree per half-wave (32 banks) of the 32-bit LDS accesses
-    # of a bf16 matrix-core pass: tile transfers (eight elements a thread),
-    # then per digit element 4q+v of the fibre of lane (q, i); a sample of
-    # the tile
+def _mfma_bank_cost(B, k, logC, pad, tileE, lds16):
+    # worst bank degree per half-wave (32 banks) of the LDS accesses of a
+    # matrix-core pass, in 32-bit words: an FP32 tile holds element x in
+    # word _phys(x), a 16-bit tile in word _phys(x >> 1).  Tile transfers move
+    # four words a thread; per digit, element 4q+v of the fibre of lane
+    # (q, i): four accesses, or two word accesses for a contiguous digit of
+    # a 16-bit tile.  Lanes on one word do not conflict.  A sample of the tile.
     def degree(addrs):
         tot = 0
         for h in (addrs[:32], addrs[32:]):
@@ -207,44 +209,50 @@ def _mfma_bank_cost(B, k, logC, pad, tileE, vec=8):
                 per.setdefault(a & 31, set()).add(a)
             tot += max(len(v) for v in per.values())
         return tot
+    word = (lambda x: _phys(x >> 1, pad)) if lds16 else (lambda x: _phys(x, pad))
+    vec = 8 if lds16 else 4
     cost = 0
     for w0 in range(0, tileE // vec - 63, 256):
-        for e in range(vec):
-            cost += degree([_phys(vec * (w0 + l) + e, pad) for l in range(64)])
+        for e in range(4):
+            cost += degree([_phys(4 * (w0 + l) + e, pad) for l in range(64)])
     F = tileE // B
     for j in range(k):
         bj = B ** j
         step = bj << logC
+        vs = (0, 2) if lds16 and step == 1 else (0, 1, 2, 3)
         for grp in range(0, (F + 15) // 16, 4):
             for h in range(B // 16):
-                for v in range(4):
+                for v in vs:
                     addrs = []
                     for lane in range(64):
                         q, lo = lane >> 4, lane & 15
                         f = (grp * 16 + lo) % F
                         c, f1 = f & ((1 << logC) - 1), f >> logC
                         lam0 = (((f1 // bj) * bj * B + f1 % bj) << logC) | c
-                        addrs.append(_phys(lam0 + (16 * h + 4 * q + v) * step, pad))
+                        addrs.append(word(lam0 + (16 * h + 4 * q + v) * step))
                     cost += degree(addrs)
     return cost
 
 
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32], ids=str)
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16, torch.float32], ids=str)
 @pytest.mark.parametrize("b,n,batch", [(16, 4, 4096), (32, 3, 64), (16, 5, 4)])
 def test_matrix_core_lds_padding(b, n, batch, dtype):
     nopad = 31 | (31 << 8) | (31 << 16)
-    vec = 16 // torch.empty(0, dtype=dtype).element_size()   # elements per 16-byte transfer
+    lds16 = dtype != torch.float32   # 16-bit storage keeps a 16-bit tile; pads count words
     for g in G.Plan(b, n, batch, dtype).describe()["groups"]:
         assert g["kind"] == "mfma"
         pad, tileE = g["pad_shift"], g["tile_elems"]
+        units = (tileE + 1) // 2 if lds16 else tileE
         shifts = [(pad >> (8 * i)) & 31 for i in range(3)]
-        # a 16-byte vector never straddles a pad; growth <= 1/8
-        assert all((1 << s_) >= vec for s_ in shifts)
-        assert _phys(tileE, pad) - tileE <= tileE // 8
-        assert g["lds_bytes"] == (_phys(tileE, pad) + 1) * 4
+        # a 16-byte vector (four words) never straddles a pad; growth <= 1/8
+        assert all((1 << s_) >= 4 for s_ in shifts)
+        assert _phys(units, pad) - units <= units // 8
+        assert g["lds_bytes"] == (_phys(units, pad) + 1) * 4
+        # 16-bit tiles hold twice the elements of FP32 ones in the same LDS
+        assert tileE * (2 if lds16 else 4) in (32768, 65536) or tileE < 8192
         logC = g["C"].bit_length() - 1
-        chosen = _mfma_bank_cost(b, g["k"], logC, pad, tileE, vec)
-        plain = _mfma_bank_cost(b, g["k"], logC, nopad, tileE, vec)
+        chosen = _mfma_bank_cost(b, g["k"], logC, pad, tileE, lds16)
+        plain = _mfma_bank_cost(b, g["k"], logC, nopad, tileE, lds16)
         assert chosen <= plain
         if g["C"] > 1:  # strided tiles: the unpadded layout conflicts
             assert chosen < plain
