@@ -379,13 +379,58 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
             }
         });
     } else {
+        // The work-groups loop over tiles (the launch is as large as the
+        // device holds at once).  Vector tiles of up to 16384 elements have
+        // the next tile's loads in flight into 32 registers per thread while
+        // the current one runs its digits: occupancy is set by LDS here, and
+        // those registers fit under its limit.
         uint16_t* lds = reinterpret_cast<uint16_t*>(smem_raw);
         const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+        const uint32_t tileE = rows << a.logC;
         const T* in = static_cast<const T*>(a.in);
         T* out = static_cast<T*>(a.out);
-        for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-            tile_load16<T>(lds, a, in, t, rows);
+        const bool vec = a.mode == kContigVec || a.mode == kRowVec;
+        const bool pf = vec && a.cut < 0 && (int64_t)gridDim.x < a.ntiles && tileE / 8 <= (uint32_t)(kPfVec * kThreads);
+        uint4 r[kPfVec];
+        // offsets recomputed per tile behind an opaque thread index, so that
+        // they do not stay live in registers across the loop
+        auto fetch = [&](int64_t t) {
+            const bool contig = a.mode == kContigVec;
+            const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+            const int64_t l = contig ? 0 : t - hb * a.L;
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+#pragma unroll
+            for (int v = 0; v < kPfVec; ++v) {
+                const uint32_t i = tid + v * kThreads;
+                if (i < tileE / 8) r[v] = gload16<true>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+            }
+        };
+        auto commit = [&]() {
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            uint32_t* w = reinterpret_cast<uint32_t*>(lds);
+#pragma unroll
+            for (int v = 0; v < kPfVec; ++v) {
+                const uint32_t i = tid + v * kThreads;
+                if (i < tileE / 8) {
+                    const uint32_t ph = lds_phys(4u * i, a.pad_shift);
+                    w[ph] = r[v].x;
+                    w[ph + 1] = r[v].y;
+                    w[ph + 2] = r[v].z;
+                    w[ph + 3] = r[v].w;
+                }
+            }
+        };
+        int64_t t = blockIdx.x;
+        if (pf && t < a.ntiles) fetch(t);
+        for (; t < a.ntiles; t += gridDim.x) {
+            if (pf)
+                commit();
+            else
+                tile_load16<T>(lds, a, in, t, rows);
             __syncthreads();
+            if (pf && t + gridDim.x < a.ntiles) fetch(t + gridDim.x);
             for (int j = 0; j < a.k; ++j) {
                 mfma_stage16<T, B>(lds, a, j, rows, wf);
                 __syncthreads();
