@@ -117,18 +117,14 @@ typedef struct gtt_plan_s* gtt_plan_t;
  * w_idx / x_off), GTT_ERR_UNSUPPORTED (GTT_FLAG_FP32_INTERMEDIATE with
  * count > 1).  On error *out is set to NULL.
  * The plan holds host memory and, for ragged batches, a device work list
- * (one descriptor per instance and digit group, one entry per tile), the
- * grid-barrier words and three helper streams with their events, created
- * and uploaded by the first forward / inverse call on the current device
- * (synchronously: do not make that first call inside a graph capture) and
- * freed by gtt_plan_destroy.  Without GTT_FLAG_PERSISTENT a ragged call
- * launches each phase's runs of one tile class concurrently: it forks them
- * onto the helper streams after an event recorded on the caller's stream and
- * joins them back with events before returning, so the work stays ordered
- * on the caller's stream (graph capture follows the fork and join).  Calls
- * with GTT_FLAG_PERSISTENT share the plan's barrier words, and ragged calls
- * share its helper streams: do not run one ragged plan on two streams at
- * once.
+ * (one descriptor per instance and digit group, one entry per tile) and the
+ * grid-barrier words, created and uploaded by the first forward / inverse
+ * call on the current device (synchronously: do not make that first call
+ * inside a graph capture) and freed by gtt_plan_destroy.  Without
+ * GTT_FLAG_PERSISTENT a ragged call launches, in order on the caller's
+ * stream, one kernel per phase and tile class.  Calls with
+ * GTT_FLAG_PERSISTENT share the plan's barrier words: do not run one such
+ * plan on two streams at once.
  */
 gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n,
                     int64_t batch, const int64_t* x_off, const int32_t* w_idx,

@@ -400,10 +400,14 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
             const int64_t l = contig ? 0 : t - hb * a.L;
             uint32_t tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
+            // every register written (zero past the tile), so that the old
+            // contents are dead here
 #pragma unroll
             for (int v = 0; v < kPfVec; ++v) {
                 const uint32_t i = tid + v * kThreads;
-                if (i < tileE / 8) r[v] = gload16<true>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+                uint4 q = make_uint4(0u, 0u, 0u, 0u);
+                if (i < tileE / 8) q = gload16<true>(in + vec_offset<T>(a, t, i, hb, l, tileE));
+                r[v] = q;
             }
         };
         auto commit = [&]() {

@@ -37,12 +37,6 @@ struct RaggedState {
     RaggedDesc* d_desc = nullptr;
     RaggedItem* d_items = nullptr;
     unsigned* d_bar = nullptr;
-    // the runs of one phase work on disjoint instances: all but the first go
-    // to helper streams forked from (and joined back into) the caller's
-    static constexpr int kAux = 3;
-    hipStream_t aux[kAux] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kAux] = {};
     int grid_persistent = 0;
     int cus = 0;
 };
@@ -159,12 +153,6 @@ static gtt_status upload_worklist(gtt_plan_s* p) {
     int per_cu = 0;
     if (ragged_occupancy(dt, rs->lds_max, &per_cu) != hipSuccess || per_cu < 1) return GTT_ERR_HIP;
     rs->grid_persistent = per_cu * rs->cus;
-    // default priority; no implicit synchronisation with the null stream
-    for (int i = 0; i < RaggedState::kAux; ++i) {
-        if (hipStreamCreateWithFlags(&rs->aux[i], hipStreamNonBlocking) != hipSuccess) return GTT_ERR_HIP;
-        if (hipEventCreateWithFlags(&rs->join[i], hipEventDisableTiming) != hipSuccess) return GTT_ERR_HIP;
-    }
-    if (hipEventCreateWithFlags(&rs->fork, hipEventDisableTiming) != hipSuccess) return GTT_ERR_HIP;
     rs->uploaded = true;
     return GTT_OK;
 }
@@ -244,11 +232,6 @@ void destroy_ragged(gtt_plan_s* p) {
         if (p->rs->d_desc) (void)hipFree(p->rs->d_desc);
         if (p->rs->d_items) (void)hipFree(p->rs->d_items);
         if (p->rs->d_bar) (void)hipFree(p->rs->d_bar);
-        for (int i = 0; i < RaggedState::kAux; ++i) {
-            if (p->rs->aux[i]) (void)hipStreamDestroy(p->rs->aux[i]);
-            if (p->rs->join[i]) (void)hipEventDestroy(p->rs->join[i]);
-        }
-        if (p->rs->fork) (void)hipEventDestroy(p->rs->fork);
     }
     delete p->rs;
     p->rs = nullptr;
@@ -292,43 +275,22 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
                    2.0 * (double)p->total_elems * (double)p->esize * (double)a.nphases);
         return GTT_OK;
     }
-    // one launch per run of one item class in a phase.  The runs of a phase
-    // touch disjoint instances and run concurrently: the first on the
-    // caller's stream, the others on helper streams forked from it after the
-    // previous phase and joined back before the next one (graph capture
-    // follows the fork and the join).
+    // one launch per run of one item class in a phase, in order on the
+    // caller's stream.  (The runs of a phase touch disjoint instances, but
+    // the matrix-core runs fill the device with resident work-groups, and
+    // concurrent runs on helper streams measured slower.)
     a.persistent = 0;
     a.phase = 0;
-    const size_t nseg = rs->segs.size();
-    for (size_t i = 0; i < nseg;) {
-        size_t j = i;
-        while (j < nseg && rs->segs[j].phase == rs->segs[i].phase) ++j;
-        const int nrun = (int)(j - i);
-        const int naux = std::min(nrun - 1, RaggedState::kAux);
-        if (naux > 0) {
-            if (hipEventRecord(rs->fork, s) != hipSuccess) return GTT_ERR_HIP;
-            for (int q = 0; q < naux; ++q)
-                if (hipStreamWaitEvent(rs->aux[q], rs->fork, 0) != hipSuccess) return GTT_ERR_HIP;
-        }
-        for (int k = 0; k < nrun; ++k) {
-            const RaggedState::Seg& sg = rs->segs[i + k];
-            hipStream_t st = (k == 0) ? s : rs->aux[(k - 1) % RaggedState::kAux];
-            a.phase_start[0] = sg.start;
-            a.phase_start[1] = sg.end;
-            const unsigned grid = (unsigned)std::min<int64_t>(sg.end - sg.start, (int64_t)0x7fffffff);
-            timing_begin(p, st);
-            if (launch_ragged_cls(dt, sg.cls, a, grid, sg.lds, st) != hipSuccess) return GTT_ERR_HIP;
-            timing_end(p, st,
-                       std::string("ragged phase ") + std::to_string(sg.phase) + " " + dn[(int)p->dtype] +
-                           (sg.cls == kClsGeneric ? " generic"
-                                                  : (sg.cls >= 16 ? " mfma b=" : " b=") + std::to_string(sg.cls)),
-                       sg.bytes);
-        }
-        for (int q = 0; q < naux; ++q) {
-            if (hipEventRecord(rs->join[q], rs->aux[q]) != hipSuccess) return GTT_ERR_HIP;
-            if (hipStreamWaitEvent(s, rs->join[q], 0) != hipSuccess) return GTT_ERR_HIP;
-        }
-        i = j;
+    for (const RaggedState::Seg& sg : rs->segs) {
+        a.phase_start[0] = sg.start;
+        a.phase_start[1] = sg.end;
+        const unsigned grid = (unsigned)std::min<int64_t>(sg.end - sg.start, (int64_t)0x7fffffff);
+        timing_begin(p, s);
+        if (launch_ragged_cls(dt, sg.cls, a, grid, sg.lds, s) != hipSuccess) return GTT_ERR_HIP;
+        timing_end(p, s,
+                   std::string("ragged phase ") + std::to_string(sg.phase) + " " + dn[(int)p->dtype] +
+                       (sg.cls == kClsGeneric ? " generic" : (sg.cls >= 16 ? " mfma b=" : " b=") + std::to_string(sg.cls)),
+                   sg.bytes);
     }
     return GTT_OK;
 }

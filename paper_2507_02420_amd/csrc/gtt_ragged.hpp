@@ -212,17 +212,25 @@ __host__ __device__ inline int ragged_class(int kind, int b) {
     return kClsGeneric;
 }
 
+// input and output of an item's group (x / y / the saved intermediates)
+template <typename T>
+__device__ __forceinline__ const T* ragged_in(const RaggedArgs& r, const RaggedDesc& d) {
+    if (d.in_sel == 0) return static_cast<const T*>(r.x) + d.in_off;
+    if (d.in_sel == 1 || !r.saved) return static_cast<const T*>(r.y) + d.in_off;
+    return static_cast<const T*>(r.saved) + d.in_off_saved;
+}
+template <typename T>
+__device__ __forceinline__ T* ragged_out(const RaggedArgs& r, const RaggedDesc& d) {
+    if (d.out_sel == 1 || !r.saved) return static_cast<T*>(r.y) + d.out_off;
+    return static_cast<T*>(r.saved) + d.mid_off_saved;
+}
+
 template <typename T, int CLS>
 __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArgs& r, const RaggedItem& it) {
     using C = typename Tr<T>::C;
     const RaggedDesc& d = r.desc[it.d];
-    const T* in;
-    T* out;
-    if (d.in_sel == 0) in = static_cast<const T*>(r.x) + d.in_off;
-    else if (d.in_sel == 1 || !r.saved) in = static_cast<const T*>(r.y) + d.in_off;
-    else in = static_cast<const T*>(r.saved) + d.in_off_saved;
-    if (d.out_sel == 1 || !r.saved) out = static_cast<T*>(r.y) + d.out_off;
-    else out = static_cast<T*>(r.saved) + d.mid_off_saved;
+    const T* in = ragged_in<T>(r, d);
+    T* out = ragged_out<T>(r, d);
     const C* W = static_cast<const C*>(r.W) + d.w_off;
     if constexpr (CLS == kClsAny) {
         if (d.kind == kKindValu) {
@@ -248,9 +256,7 @@ __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArg
     } else if constexpr (CLS <= 5) {
         ragged_tile_valu<T, CLS>(smem, d.a, in, out, W, r.adjoint, it.tile);
     } else {
-        static_assert(sizeof(T) == 2 || std::is_same<T, float>::value,
-                      "matrix-core item classes exist for 16-bit and float storage only");
-        ragged_tile_mfma<T, CLS>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
+        static_assert(CLS <= 5, "matrix-core classes run ragged_mfma_items");
     }
 }
 
@@ -266,12 +272,61 @@ __global__ __launch_bounds__(kThreads) void gtt_ragged_kernel(RaggedArgs r) {
     }
 }
 
+// Matrix-core items (one class, one phase): the work-groups loop over the
+// items and keep W's fragments while consecutive items share W.  (A
+// register prefetch of the next item, as in the uniform pass, lowers the
+// occupancy of these kernels and was slower.)
+template <typename T, int B>
+__device__ __forceinline__ void ragged_mfma_items(unsigned char* smem, const RaggedArgs& r) {
+    constexpr bool k16 = sizeof(T) == 2;
+    using L = typename std::conditional<k16, uint16_t, float>::type;
+    L* lds = reinterpret_cast<L*>(smem + 256);
+    WFrag<T, B> wf;
+    int64_t wcur = -1;
+    for (int64_t i = r.phase_start[0] + blockIdx.x; i < r.phase_start[1]; i += gridDim.x) {
+        const RaggedItem it = r.items[i];
+        const RaggedDesc& d = r.desc[it.d];
+        const PassArgs& a = d.a;
+        if (d.w_off != wcur) {
+            PassArgs aw;  // only W / adjoint are read by the fragment loader
+            aw.W = static_cast<const float*>(r.W) + d.w_off;
+            aw.adjoint = r.adjoint;
+            load_w_frag<T, B>(wf, aw);
+            wcur = d.w_off;
+        }
+        const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+        if constexpr (k16)
+            tile_load16<T>(lds, a, ragged_in<T>(r, d), it.tile, rows);
+        else
+            tile_load<T, float>(lds, a, ragged_in<T>(r, d), it.tile, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            if constexpr (k16)
+                mfma_stage16<T, B>(lds, a, j, rows, wf);
+            else
+                mfma_stage<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        if constexpr (k16)
+            tile_store16<T>(lds, a, ragged_out<T>(r, d), it.tile, rows);
+        else
+            tile_store<T, float>(lds, a, ragged_out<T>(r, d), it.tile, rows);
+        __syncthreads();
+    }
+}
+
 // The items [phase_start[0], phase_start[1]) of one class.
 template <typename T, int CLS>
 __global__ __launch_bounds__(kThreads) void gtt_ragged_class_kernel(RaggedArgs r) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int64_t i = r.phase_start[0] + blockIdx.x; i < r.phase_start[1]; i += gridDim.x)
-        ragged_item<T, CLS>(smem_raw, r, r.items[i]);
+    if constexpr (CLS >= 16) {
+        static_assert(sizeof(T) == 2 || std::is_same<T, float>::value,
+                      "matrix-core item classes exist for 16-bit and float storage only");
+        ragged_mfma_items<T, CLS>(smem_raw, r);
+    } else {
+        for (int64_t i = r.phase_start[0] + blockIdx.x; i < r.phase_start[1]; i += gridDim.x)
+            ragged_item<T, CLS>(smem_raw, r, r.items[i]);
+    }
 }
 
 }  // namespace gtt

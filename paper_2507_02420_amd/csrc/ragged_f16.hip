@@ -31,7 +31,9 @@ hipError_t launch_ragged_cls_f16(int cls, const RaggedArgs& a, unsigned grid, si
         const void* k = reinterpret_cast<const void*>(gtt_ragged_class_kernel<f16, CLS>);                  \
         if (lds > 65536) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((gtt_ragged_class_kernel<f16, CLS>), dim3(grid), dim3(kThreads), lds, s, a);    \
+        /* matrix-core classes loop over their items on a resident grid */                        \
+        const unsigned g = CLS >= 16 ? resident_grid((gtt_ragged_class_kernel<f16, CLS>), kThreads, lds, grid) : grid; \
+        hipLaunchKernelGGL((gtt_ragged_class_kernel<f16, CLS>), dim3(g), dim3(kThreads), lds, s, a);    \
     } while (0)
     switch (cls) {
         case 0: K_(0); break;
