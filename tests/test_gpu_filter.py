@@ -42,3 +42,22 @@ def test_filter_matches_oracle(b, n, batch, cut, dtype):
         scale = np.linalg.norm(x64[i])
         assert np.linalg.norm(host64(lo[i]) - rlo) / scale < 3 * TOL[dtype]
         assert np.linalg.norm(host64(hi[i]) - rhi) / scale < 3 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16, torch.float32], ids=str)
+@pytest.mark.parametrize("b,n,batch,cut", [(16, 3, 2, 1000), (32, 2, 3, 1), (16, 4, 1, 40000), (32, 3, 1, 0),
+                                           (32, 2, 2, 1 << 20)])
+def test_filter_matrix_core(b, n, batch, cut, dtype):
+    # radix 16 / 32: the natural-order mask is applied while the first
+    # inverse group loads its tile on the matrix-core path
+    say(f"filter mfma b={b} n={n} cut={cut} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=1400 + b + n)
+    plan = G.Plan(b, n, batch, dtype)
+    assert all(g["kind"] == "mfma" for g in plan.describe()["groups"])
+    lo, hi = plan.filter(W, x, cut)
+    torch.cuda.synchronize()
+    for i in range(batch):
+        rlo, rhi = O.natural_filter(W64, x64[i], n, cut)
+        scale = np.linalg.norm(x64[i])
+        assert np.linalg.norm(host64(lo[i]) - rlo) / scale < 3 * TOL[dtype]
+        assert np.linalg.norm(host64(hi[i]) - rhi) / scale < 3 * TOL[dtype]

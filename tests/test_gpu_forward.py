@@ -9,6 +9,7 @@ import torch
 from gpu_util import COMPLEX, TOL, host64, make_inputs, rel_err, say
 from oracle import gtt_oracle as O
 from paper_2507_02420_amd import gtt as G
+from paper_2507_02420_amd.inputs import gaussian
 
 pytestmark = pytest.mark.gpu
 
@@ -184,6 +185,51 @@ def test_mfma_radix_16_32(b, n, batch, dtype):
     say(f"  rel err {err:.3e}")
     assert err < 1e-2
     assert rel_err(host64(xi), x64) < 2e-2
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32], ids=str)
+@pytest.mark.parametrize("b,n,batch", [(16, 4, 600), (32, 3, 1100)])
+def test_mfma_many_tiles_sampled(b, n, batch, dtype):
+    # more tiles than the device holds work-groups at once: the 16-bit pass
+    # loops over tiles with the next one prefetched; rows checked against
+    # the oracle on a sample that includes the first and the last tile
+    say(f"mfma many tiles b={b} n={n} batch={batch} dtype={dtype}")
+    N = b ** n
+    x, W, _, W64 = make_inputs(b, 1, 1, dtype, seed=7100 + b)  # W only
+    x = torch.from_numpy(gaussian((batch, N), seed=7200 + b)).to(dtype).cuda()
+    plan = G.Plan(b, n, batch, dtype)
+    assert plan.describe()["groups"][0]["tiles"] > 2048
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, y)
+    torch.cuda.synchronize()
+    rows = sorted({0, 1, batch // 3, batch // 2, batch - 2, batch - 1})
+    x64 = host64(x[rows])
+    err = rel_err(host64(y[rows]), O.staged(W64, x64, n))
+    say(f"  rel err {err:.3e}")
+    assert err < TOL[dtype]
+    assert rel_err(host64(xi[rows]), x64) < 3 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32], ids=str)
+@pytest.mark.parametrize("b,n,batch", [(32, 3, 2), (16, 3, 3)])
+def test_mfma_small_tiles_scalar_rows(b, n, batch, dtype):
+    # tiles of 128 LDS bytes (tuning override): strided groups get rows of a
+    # few elements, moved element by element instead of as 16-byte vectors
+    say(f"mfma small tiles b={b} n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=7300 + b + n)
+    G.set_tuning(b, dtype, 128, 0, 0)
+    try:
+        plan = G.Plan(b, n, batch, dtype)
+    finally:
+        G.set_tuning(b, dtype, 0, 0, 0)
+    groups = plan.describe()["groups"]
+    assert all(g["kind"] == "mfma" for g in groups)
+    assert any(g["mode"] in (1, 3) for g in groups), groups  # a scalar mode
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, y)
+    torch.cuda.synchronize()
+    assert rel_err(host64(y), O.staged(W64, x64, n)) < TOL[dtype]
+    assert rel_err(host64(xi), x64) < 3 * TOL[dtype]
 
 
 def test_strided_or_conjugate_views_are_refused():

@@ -2,7 +2,7 @@
 run as one persistent launch (grid barrier between digit groups), as one
 launch per phase, or per instance; every instance checked against the FP64
 oracle.  Also graph capture and replay of the persistent launch and of the
-per-phase launches (with their forked helper streams)."""
+per-phase launches."""
 import numpy as np
 import pytest
 import torch
@@ -174,3 +174,28 @@ def test_ragged_graph_replay(mode):
         # eager work between replays
         _ = plan.forward(Wt, xt)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32], ids=str)
+def test_ragged_matrix_core_items_loop_and_w_changes(dtype):
+    # more matrix-core items per phase (18 instances x 64 or 128 tiles) than
+    # one resident grid holds, so work-groups run several items; W drawn per
+    # instance from two of each radix, so consecutive items of a work-group
+    # both keep and change W (the class kernels reload W's fragments only
+    # when it changes)
+    shapes = [(16, 5)] * 18 + [(32, 4)] * 18
+    rng = np.random.default_rng(951)
+    w_idx = rng.integers(0, 2, 18).tolist() + (2 + rng.integers(0, 2, 18)).tolist()
+    say(f"ragged matrix-core loop {dtype}")
+    xt, Wt, W64, widx, offs = _ragged_inputs(shapes, dtype, seed=950, w_idx=w_idx)
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype, w_idx=w_idx)
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    x64, y64, xi64 = host64(xt), host64(y), host64(xi)
+    tol = TOL[dtype]
+    for t, ((b, n), o) in enumerate(zip(shapes, offs)):
+        N = b ** n
+        e = rel_err(y64[o:o + N], O.staged(W64[widx[t]], x64[o:o + N], n))
+        assert e < tol, (t, b, n, e)
+        assert rel_err(xi64[o:o + N], x64[o:o + N]) < 3 * tol
