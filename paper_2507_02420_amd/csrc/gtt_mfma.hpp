@@ -371,8 +371,9 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
     WFrag<T, B> wf;
     load_w_frag<T, B>(wf, a);
     if constexpr (std::is_same<T, float>::value) {
+        // persistent grid, next tile prefetched into registers (tile_loop)
         float* lds = reinterpret_cast<float*>(smem_raw);
-        tile_loop<T, float>(lds, a, [&](float* t, uint32_t rows) {
+        tile_loop<T, float, true>(lds, a, [&](float* t, uint32_t rows) {
             for (int j = 0; j < a.k; ++j) {
                 mfma_stage<T, B>(t, a, j, rows, wf);
                 __syncthreads();

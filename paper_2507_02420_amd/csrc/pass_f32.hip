@@ -31,13 +31,21 @@ hipError_t launch_pass_f32(int b, int kind, const PassArgs& a, unsigned grid, si
                                : grid;                                                        \
         hipLaunchKernelGGL((gtt_pass_kernel<T, B>), dim3(g), dim3(kThreads), lds, s, a);      \
     } while (0)
+#define GTT_LAUNCH_MFMA(B)                                                                        \
+    do {                                                                                          \
+        e = set_lds((gtt_pass_mfma_kernel<T, B>), lds);                                           \
+        if (e != hipSuccess) return e;                                                            \
+        const unsigned g = resident_grid((gtt_pass_mfma_kernel<T, B>), kThreads, lds, grid);     \
+        hipLaunchKernelGGL((gtt_pass_mfma_kernel<T, B>), dim3(g), dim3(kThreads), lds, s, a);     \
+    } while (0)
     if (kind == kKindGeneric) {
         GTT_LAUNCH(gtt_pass_generic_kernel<T>);
     } else if (kind == kKindMfma) {
+        // persistent grid: the kernel prefetches the next tile
         if (b == 16)
-            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 16>));
+            GTT_LAUNCH_MFMA(16);
         else if (b == 32)
-            GTT_LAUNCH((gtt_pass_mfma_kernel<T, 32>));
+            GTT_LAUNCH_MFMA(32);
         else
             return hipErrorInvalidValue;
     } else {
@@ -54,6 +62,7 @@ hipError_t launch_pass_f32(int b, int kind, const PassArgs& a, unsigned grid, si
     }
 #undef GTT_LAUNCH
 #undef GTT_LAUNCH_VALU
+#undef GTT_LAUNCH_MFMA
     return hipGetLastError();
 }
 
