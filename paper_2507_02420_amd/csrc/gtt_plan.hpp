@@ -99,6 +99,7 @@ struct gtt_plan_s {
     std::vector<int> w_b;         // radix of W table entry
     std::vector<int64_t> w_off;   // element offset of W table entry
     gtt::RaggedState* rs = nullptr;
+    int ragged_scalar_instances = 0;  // instances off a 16-byte boundary (element-wise tile I/O)
     gtt::Timing timing;
     // GTT_FLAG_FP32_INTERMEDIATE on a 16-bit storage dtype: the same
     // transform planned in float32; calls convert at the boundaries and run it

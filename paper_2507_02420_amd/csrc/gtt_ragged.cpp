@@ -217,6 +217,17 @@ gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int
         std::vector<int> rad(n[t], b[t]);
         gtt_status st = plan_groups(rad, 1, p->dtype, p->flags, true, &in.groups, &in.bwd_groups, true);
         if (st != GTT_OK) return st;
+        // packed instances may start off a 16-byte boundary (a previous
+        // instance of a length that is not a multiple of 16 bytes): their
+        // tiles move element by element
+        if ((in.off * (int64_t)p->esize) % 16) {
+            for (std::vector<Group>* gs : {&in.groups, &in.bwd_groups})
+                for (Group& g : *gs) {
+                    if (g.mode == kContigVec) g.mode = kContigScalar;
+                    if (g.mode == kRowVec) g.mode = kRowScalar;
+                }
+            ++p->ragged_scalar_instances;
+        }
     }
     p->total_elems = end;
     int maxR = 0;
@@ -459,9 +470,9 @@ std::string describe_plan(const gtt_plan_s* p) {
         }
         s += "]";
     } else {
-        char b[128];
-        std::snprintf(b, sizeof b, "\"instances\":%zu,\"w_table\":%zu,\"max_groups\":%d", p->inst.size(),
-                      p->w_b.size(), max_groups(p));
+        char b[192];
+        std::snprintf(b, sizeof b, "\"instances\":%zu,\"w_table\":%zu,\"max_groups\":%d,\"scalar_instances\":%d",
+                      p->inst.size(), p->w_b.size(), max_groups(p), p->ragged_scalar_instances);
         s += b;
     }
     s += "}";

@@ -256,3 +256,15 @@ def test_matrix_core_lds_padding(b, n, batch, dtype):
         assert chosen <= plain
         if g["C"] > 1:  # strided tiles: the unpadded layout conflicts
             assert chosen < plain
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.complex64], ids=str)
+def test_ragged_packed_instances_off_16_byte_boundary(dtype):
+    # packed back to back, the instances after one of 3 elements start off
+    # a 16-byte boundary and must move their tiles element by element
+    shapes = [(3, 1), (2, 5), (16, 3), (4, 2)]
+    p = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, dtype)
+    assert p.describe()["scalar_instances"] == 3
+    aligned = [(2, 5), (16, 3), (4, 2)]
+    p = G.Plan([b for b, _ in aligned], [n for _, n in aligned], 1, dtype)
+    assert p.describe()["scalar_instances"] == 0
