@@ -438,7 +438,7 @@ static gtt_status run_groups(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Gro
     const void* src = in;
     for (size_t i = 0; i < groups.size(); ++i) {
         void* dst = out;
-        if (i + 1 < groups.size() && saved) dst = saved + i * elems * es;
+        if (i + 1 < groups.size() && saved) dst = saved + i * (size_t)tp->slot * es;
         gtt_status st = launch_group(tp, dt, groups[i], rad, wofs, N, W, adjoint, src, dst, s, i == 0 ? cut : -1,
                                      keep_high);
         if (st != GTT_OK) return st;
@@ -557,6 +557,7 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
         p->wofs.assign(n[0], 0);
         st = plan_groups(p->rad, batch, dtype, flags, true, &p->groups, &p->bwd_groups);
         p->total_elems = p->N * batch;
+        p->slot = slot_elems(p->total_elems, p->esize);
         p->w_elems = (int64_t)b[0] * b[0];
         // float32 between digit groups: only the 16-bit storage types keep
         // less (the other dtypes already compute and store in >= 32 bits)
@@ -600,6 +601,7 @@ gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, in
     p->batch = batch;
     p->n = m;
     p->total_elems = N * batch;
+    p->slot = slot_elems(p->total_elems, p->esize);
     // digit d (least significant first) is factor m-1-d
     p->rad.resize(m);
     p->wofs.resize(m);

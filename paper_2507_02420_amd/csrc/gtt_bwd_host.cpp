@@ -111,9 +111,10 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
     char* partials = wsb;
     char* extra = wsb + part_bytes;
     size_t extra_bytes = ws_bytes - part_bytes;
+    // elems: elements of the buffers; slot: stride of the boundary slots
     auto uniform_like = [&](const std::vector<Group>& fg, const std::vector<Group>& bg, int b, int64_t N,
-                            size_t elems, const char* xin, const char* sv_in, const char* gyin, char* gxout,
-                            char* part, char* sv_tmp, char* cb) -> gtt_status {
+                            size_t elems, size_t slot, const char* xin, const char* sv_in, const char* gyin,
+                            char* gxout, char* part, char* sv_tmp, char* cb) -> gtt_status {
         const int R = (int)fg.size();
         if (R == 0) {  // n == 0: gx = gy, gW = 0 (no factor of W)
             if (gxout && gxout != gyin && hipMemcpyAsync(gxout, gyin, elems * es, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -125,29 +126,29 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
             // recompute the activations at the group boundaries
             const void* cur = xin;
             for (int g = 0; g + 1 < R; ++g) {
-                char* dst = sv_tmp + (size_t)g * elems * es;
+                char* dst = sv_tmp + (size_t)g * slot * es;
                 gtt_status st = launch_group_inst(p, p->dtype, fg[g], b, N, W, false, cur, dst, s);
                 if (st != GTT_OK) return st;
                 cur = dst;
             }
             svp = sv_tmp;
         }
-        return bwd_run(p, p->dtype, fg, bg, b, N, elems, W, xin, svp, gyin, gxout, cb, part, s);
+        return bwd_run(p, p->dtype, fg, bg, b, N, slot, W, xin, svp, gyin, gxout, cb, part, s);
     };
     if (p->kind == PlanKind::Uniform) {
-        const size_t E = (size_t)p->total_elems;
+        const size_t E = (size_t)p->total_elems, SL = (size_t)p->slot;
         const int R = (int)p->groups.size();
         // cotangent buffer between groups: gx when given and not aliasing gy,
         // else workspace
         char* cb = nullptr;
         size_t need = 0;
-        if (R > 1 && !saved) need += (size_t)(R - 1) * E * es;
+        if (R > 1 && !saved) need += (size_t)(R - 1) * SL * es;
         const bool cb_in_gx = gx && gx != gy;
         if (R > 1 && !cb_in_gx) need += E * es;
         if (extra_bytes < need) return GTT_ERR_WORKSPACE;
         char* sv_tmp = extra;
-        cb = cb_in_gx ? static_cast<char*>(gx) : extra + ((R > 1 && !saved) ? (size_t)(R - 1) * E * es : 0);
-        gtt_status st = uniform_like(p->groups, p->bwd_groups, p->b, p->N, E, (const char*)x, (const char*)saved,
+        cb = cb_in_gx ? static_cast<char*>(gx) : extra + ((R > 1 && !saved) ? (size_t)(R - 1) * SL * es : 0);
+        gtt_status st = uniform_like(p->groups, p->bwd_groups, p->b, p->N, E, SL, (const char*)x, (const char*)saved,
                                      (const char*)gy, (char*)gx, partials, sv_tmp, cb);
         if (st != GTT_OK) return st;
         if (gW) {
@@ -162,8 +163,9 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
         }
         return GTT_OK;
     }
-    // ragged: instances one by one; partial sums laid out grouped by W index
-    const size_t E = (size_t)p->total_elems;
+    // ragged: instances one by one; partial sums laid out grouped by W index;
+    // boundary slots of stride E (total elements rounded up to 256 bytes)
+    const size_t E = (size_t)p->slot;
     int maxR = 0;
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
     size_t need = 0;

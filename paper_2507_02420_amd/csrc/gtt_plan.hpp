@@ -89,6 +89,8 @@ struct gtt_plan_s {
     int b = 2, n = 0;
     int64_t N = 1, batch = 1;
     int64_t total_elems = 0;  // elements in a data buffer
+    int64_t slot = 0;         // element stride of the boundary slots in saved / workspace buffers
+                              // (total_elems rounded up to 256 bytes: every slot 16-byte aligned)
     int64_t w_elems = 0;      // elements of W (or of the W table)
     std::vector<int> rad;     // radix per digit, least significant first
     std::vector<int64_t> wofs;// W offset per digit (elements)
@@ -107,6 +109,11 @@ struct gtt_plan_s {
 };
 
 namespace gtt {
+
+inline int64_t slot_elems(int64_t total, size_t esize) {
+    const int64_t bytes = (total * (int64_t)esize + 255) & ~(int64_t)255;
+    return bytes / (int64_t)esize;
+}
 
 FastDiv make_fastdiv(uint32_t d);
 uint32_t host_fdiv(uint32_t n, const FastDiv& f);

@@ -46,7 +46,7 @@ static void build_worklist(gtt_plan_s* p) {
     p->rs = rs;
     int maxR = 1;
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
-    const int64_t E = p->total_elems;
+    const int64_t E = p->slot;  // stride of the boundary slots in `saved`
     struct Tmp {
         int phase, cls;
         int64_t cost;
@@ -230,6 +230,7 @@ gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int
         }
     }
     p->total_elems = end;
+    p->slot = slot_elems(end, p->esize);
     int maxR = 0;
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
     if (maxR > kMaxPhases) return GTT_ERR_UNSUPPORTED;
@@ -323,7 +324,7 @@ static gtt_status ragged_per_instance(gtt_plan_s* p, const void* W, const void* 
         for (size_t i = 0; i < t.groups.size(); ++i) {
             void* nxt = dst;
             if (saved && i + 1 < t.groups.size())
-                nxt = saved + ((int64_t)i * p->total_elems + t.off) * es;
+                nxt = saved + ((int64_t)i * p->slot + t.off) * es;
             gtt_status st = launch_group_inst(p, p->dtype, t.groups[i], t.b, t.N, w, adjoint, cur, nxt, s);
             if (st != GTT_OK) return st;
             cur = nxt;
@@ -355,15 +356,14 @@ size_t bwd_partial_bytes(const gtt_plan_s* p) {
 
 void workspace_sizes(const gtt_plan_s* p, size_t* fwd, size_t* bwd, size_t* saved) {
     const int R = max_groups(p);
-    const size_t E = (size_t)p->total_elems;
     *fwd = 0;
-    *saved = (R > 1) ? (size_t)(R - 1) * E * p->esize : 0;
+    *saved = (R > 1) ? (size_t)(R - 1) * (size_t)p->slot * p->esize : 0;
     // backward: per-tile partial sums of the weight gradient (compute dtype,
     // b*b per tile and group) plus room to recompute the saved activations
     const size_t partial = bwd_partial_bytes(p);
     // + a cotangent buffer between digit groups (used when gx is NULL or
     // aliases gy)
-    const size_t cbuf = (R > 1 || p->kind == PlanKind::Ragged) ? E * p->esize : 0;
+    const size_t cbuf = (R > 1 || p->kind == PlanKind::Ragged) ? (size_t)p->slot * p->esize : 0;
     *bwd = partial + *saved + cbuf;
 }
 

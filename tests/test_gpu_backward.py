@@ -52,6 +52,24 @@ def test_backward_without_saved_recomputes(b, n, dtype):
     assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64], ids=str)
+@pytest.mark.parametrize("use_saved", [True, False])
+def test_backward_boundary_slots_of_odd_length(dtype, use_saved):
+    # 3^7 = 2187 elements (not a multiple of 16 bytes) in four digit groups
+    # (tuning override): the activations between groups sit in slots of the
+    # saved / workspace buffer whose stride is rounded up to 256 bytes
+    b, n = 3, 7
+    say(f"backward odd-length slots dtype={dtype} saved={use_saved}")
+    G.set_tuning(b, dtype, 0, 0, 2)
+    try:
+        gx, gW, rgx, rgW = _grad_case(b, n, 1, dtype, seed=6100, use_saved=use_saved)
+        assert len(G.Plan(b, n, 1, dtype).describe()["groups"]) == 4
+    finally:
+        G.set_tuning(b, dtype, 0, 0, 0)
+    assert rel_err(gx, rgx) < TOL[dtype]
+    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+
+
 def test_backward_c128_b8_n3_tight():
     # the finite-difference case of the oracle pins, on the GPU in FP64
     say("backward c128 b=8 n=3")
