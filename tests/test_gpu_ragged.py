@@ -114,12 +114,14 @@ def test_ragged_backward_per_w():
         pos += w.size
 
 
-def test_ragged_full_shape_list_bf16_persistent_sampled():
+@pytest.mark.parametrize("mode", ["phases", "persistent"])
+def test_ragged_full_shape_list_bf16_sampled(mode):
     # the 1024-instance shape list (b in {2,4,16,32}, N in [2^10, 2^20],
-    # 268,417,024 elements) in bf16, one persistent launch; sampled instances
-    # against the FP64 oracle on the stored bf16 values
+    # 268,417,024 elements) in bf16, per-phase launches (the default, as
+    # benchmarked) and one persistent launch; sampled instances against the
+    # FP64 oracle on the stored bf16 values
     shapes = ragged_shapes(1024, seed=52)
-    say("ragged 1024 bf16 persistent")
+    say(f"ragged 1024 bf16 {mode}")
     Ns = [b ** n for b, n in shapes]
     offs = np.cumsum([0] + Ns[:-1])
     total = int(sum(Ns))
@@ -128,11 +130,12 @@ def test_ragged_full_shape_list_bf16_persistent_sampled():
     Ws = [haar_unitary(r, 54 + i, complex_=False).astype(np.float32) for i, r in enumerate((2, 4, 16, 32))]
     Wt = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).cuda()
     ridx = {2: 0, 4: 1, 16: 2, 32: 3}
-    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, torch.bfloat16, flags=G.FLAG_PERSISTENT)
+    plan = G.Plan([b for b, _ in shapes], [n for _, n in shapes], 1, torch.bfloat16, flags=MODES[mode])
     y = plan.forward(Wt, xt)
     torch.cuda.synchronize()
     errs = {}
-    for t in list(range(0, 1024, 37)) + [int(np.argmax(Ns))]:
+    largest = [max((t for t in range(1024) if shapes[t][0] == b), key=lambda t: Ns[t]) for b in (2, 4, 16, 32)]
+    for t in list(range(0, 1024, 37)) + largest:
         b, n = shapes[t]
         o, N = int(offs[t]), Ns[t]
         x64 = xt[o:o + N].float().cpu().double().numpy()
