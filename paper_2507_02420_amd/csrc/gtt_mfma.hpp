@@ -135,11 +135,8 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
                                            const WFrag<T, B>& wf) {
     static_assert(std::is_same<T, float>::value, "16-bit storage runs mfma_stage16");
     constexpr int NB = B / 16;
-    const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t F = (rows << a.logC) / B;
-    const uint32_t bj = (uint32_t)a.bpow[j];
-    const uint32_t bj1 = (uint32_t)a.bpow[j + 1];
-    const uint32_t step = bj << a.logC;
+    const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int q = lane >> 4;
@@ -162,8 +159,6 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     const uint32_t hj = (uint32_t)a.logC + LB * (uint32_t)j;
     auto ins = [&](uint32_t v) { return ((v >> hj) << (hj + LB)) | (v & ((1u << hj) - 1u)); };
     const uint32_t lane_base = lds_phys(ins((uint32_t)(lane & 15)), pad) + qoff;
-    (void)Cm;
-    (void)bj1;
     for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
         const uint32_t f = grp * 16 + (lane & 15);
         const bool valid = f < F;

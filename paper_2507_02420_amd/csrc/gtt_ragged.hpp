@@ -1,12 +1,17 @@
-// Ragged batches in one launch: instances of different radix and length (each
-// its own GTT, Def. 2.4) packed in one buffer.  The host lays out a device
-// work list of (descriptor, tile) items, one descriptor per (instance, digit
-// group); phase p holds the tiles of digit group p of every instance.  A
-// work-group takes items of the current phase round-robin and dispatches on
-// the radix to the VALU, matrix-core or runtime-radix tile code.
+// Ragged batches: instances of different radix and length (each its own GTT,
+// Def. 2.4) packed in one buffer.  The host lays out a device work list of
+// (descriptor, tile) items, one descriptor per (instance, digit group);
+// phase p holds the tiles of digit group p of every instance, sorted by item
+// class (VALU radix 2..5, runtime radix, matrix-core radix 16 / 32).
 //
-// Persistent mode runs every phase in ONE launch and separates the phases by
-// a grid barrier (the next digit group of an instance needs all tiles of the
+// Per-phase mode (the default) launches one kernel per run of one class in a
+// phase, specialised to that class: VALU and runtime-radix classes take one
+// tile per work-group; matrix-core classes loop over their items on a
+// resident grid, keeping W's fragments while consecutive items share W.
+//
+// Persistent mode runs every phase in ONE launch of the all-class kernel (a
+// work-group takes the items of the current phase round-robin and dispatches
+// on the class) and separates the phases by a grid barrier (the next digit group of an instance needs all tiles of the
 // previous one).  The barrier counts arrivals with a device-scope atomic; the
 // last work-group to arrive resets the count and advances a generation word
 // the others wait on, so the state returns to zero after every barrier and the
