@@ -89,7 +89,8 @@ typedef enum gtt_dtype {
                                            of every instance in ONE persistent
                                            launch, grid barrier between digit
                                            groups (default: one launch per
-                                           digit-group phase) */
+                                           digit-group phase and tile class,
+                                           with class-specialised kernels) */
 #define GTT_FLAG_PER_INSTANCE 0x8u      /* ragged batch: one launch per digit
                                            group per instance (the plain path) */
 
