@@ -245,6 +245,7 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
 static void make_fast(Group* g, size_t csize, bool bwd) {
     g->fast_ni = 0;
     g->fmap = 0;
+    g->pmap = 0;
     if (g->kind != kKindCMfma || g->k < 1 || g->k > 4) return;
     if (g->mode != kContigVec && g->mode != kRowVec) return;
     const int ni = g->tileE == 2048 ? 1 : g->tileE == 4096 ? 2 : 0;
@@ -252,6 +253,7 @@ static void make_fast(Group* g, size_t csize, bool bwd) {
     const FastMap m = fast_map(g->k, ni, g->logC, bwd);
     g->fast_ni = ni;
     g->fmap = m.map;
+    g->pmap = m.pmap;
     g->fast_conflicts = m.conflicts;
     g->pad_shift = m.pad;
     g->lds_bytes = (size_t)lds_tile_elems_host(g->tileE, m.pad) * csize;
@@ -369,6 +371,7 @@ void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, co
     }
     a->wtotal = g.wtotal;
     a->fmap = g.fmap;
+    a->pmap = g.pmap;
 }
 }  // namespace gtt
 

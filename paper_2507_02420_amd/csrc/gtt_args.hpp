@@ -61,6 +61,9 @@ struct PassArgs {
     // bits 16j..16j+7 = fibre-bit mask of the lane index, then the two
     // gradient lane-group bits (3 bits each)
     uint64_t fmap;
+    // paired four-digit backward layouts: fibre-bit masks of the recomputing
+    // passes of digits 1 (bits 0..7) and 2 (bits 8..15); 0 otherwise
+    uint32_t pmap;
 };
 
 // backward of one group, complex64 radix 8 on the matrix cores

@@ -449,15 +449,17 @@ __device__ __forceinline__ void cpass8_lane_offsets(uint32_t (&P0)[K], uint32_t 
 // every uniform LDS offset becomes an instruction immediate
 struct LayoutArgs {
     static constexpr bool kFixed = false;
+    static constexpr uint32_t kPmap = 0;  // runtime layouts keep every barrier
     __device__ static int pad(const PassArgs& a) { return a.pad_shift; }
     __device__ static int logc(const PassArgs& a) { return a.logC; }
     __device__ static uint64_t fmap(const PassArgs& a) { return a.fmap; }
 };
-template <int PAD, int LOGC, uint64_t FMAP>
+template <int PAD, int LOGC, uint64_t FMAP, uint32_t PMAP = 0>
 struct LayoutFixed {
     static constexpr bool kFixed = true;
     static constexpr int kPad = PAD, kLogC = LOGC;
     static constexpr uint64_t kFmap = FMAP;
+    static constexpr uint32_t kPmap = PMAP;  // paired layout: pass-only maps of digits 1, 2
     __device__ static int pad(const PassArgs&) { return PAD; }
     __device__ static int logc(const PassArgs&) { return LOGC; }
     __device__ static uint64_t fmap(const PassArgs&) { return FMAP; }
@@ -639,6 +641,33 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
     const uint32_t hi = (uint32_t)(lane >> 4), lo = (uint32_t)(lane & 15);
     uint32_t P0[K], P1[K], GB[K];
     cpass8_lane_offsets<K>(P0, P1, fmap, logC, pad);
+    // Paired layout (four digits, direct digit-0 I/O): the recomputing passes
+    // of digits 1 and 2 run on their own maps, under which every wave owns
+    // whole digit-1 x digit-2 blocks, and the fused phases of digits 1 and 0
+    // on maps under which every wave owns whole digit-0 x digit-1 blocks.
+    // The second phase of each pair reads only what its own wave wrote in
+    // the first, so the pair needs no work-group barrier in between: five
+    // barriers per tile instead of seven.
+    constexpr bool kPair = D0 && K == 4 && LAY::kPmap != 0;
+    [[maybe_unused]] uint32_t Q0[2], Q1[2];
+    if constexpr (kPair) {
+        const int lane_ = threadIdx.x & 63, wave_ = threadIdx.x >> 6;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t mask = (LAY::kPmap >> (8 * i)) & 0xffu, h = 3u * (uint32_t)(i + 1);
+            const uint32_t f = deposit8((uint32_t)wave_, ~mask & 0xffu) | deposit8((uint32_t)(lane_ & 15), mask);
+            const uint32_t L0 = digit_deposit(f, h) | ((2u * (uint32_t)(lane_ >> 4)) << h);
+            Q0[i] = lds_phys(L0, pad) * 8u;
+            Q1[i] = lds_phys(L0 | (1u << h), pad) * 8u;
+        }
+    }
+    // between the two phases of a pair: the wave's own LDS writes ordered
+    // before its reads (no other wave's data is involved)
+    auto wave_sync = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const DigitMap d = digit_map(fmap, j);
@@ -805,15 +834,22 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             pass(IntC<0>{}, Ab, T1b, fw);  // a_1
             __syncthreads();
         }
-        if constexpr (K >= 3) {
+        if constexpr (kPair) {
+            cpass8<NI>(T1b, T2b, Q0[0], Q1[0], 3u, pad, fw);  // a_2
+            wave_sync();
+            cpass8<NI>(T2b, T1b, Q0[1], Q1[1], 6u, pad, fw);  // a_3 (replaces a_1)
+            __syncthreads();
+        } else if constexpr (K >= 3) {
             pass(IntC<1>{}, T1b, T2b, fw);  // a_2
             __syncthreads();
         }
         if constexpr (K == 4) {
             // a_3 replaces a_1 (recomputed from A once digit 3 is done); the
             // recompute shares the phase of digit 2, which reads only T2 and Ct
-            pass(IntC<2>{}, T2b, T1b, fw);  // a_3
-            __syncthreads();
+            if constexpr (!kPair) {
+                pass(IntC<2>{}, T2b, T1b, fw);  // a_3
+                __syncthreads();
+            }
             fused(IntC<3>{}, T1b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
             __syncthreads();
             if constexpr (D0) {
@@ -836,7 +872,10 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
         }
         if constexpr (K >= 2) {
             fused(IntC<1>{}, T1b, IntC<1>{}, IntC<0>{}, IntC<0>{}, cur.origin);
-            __syncthreads();
+            if constexpr (kPair)
+                wave_sync();
+            else
+                __syncthreads();
         }
         // out is null for the first digit group when only gW is wanted
         if (want_gx)

@@ -16,6 +16,18 @@
 // the other four the wave.  In the gradient sums, lane group k (0..3) sets
 // fibre bits kb0_j (k & 1) and kb1_j (k >> 1); the remaining two mask bits
 // are the loop over the four MFMAs of a block.
+//
+// Paired phases (backward, four digits, 4096-element contiguous tiles): two
+// consecutive phases on digits x and y need no work-group barrier when every
+// wave owns the same positions in both, i.e. when the four tile-position
+// bits that carry the wave index lie outside digits x and y and are the same
+// set for both digits' maps; a wave then reads back only what it wrote
+// itself.  The adjoint phases of digits 1 and 0 are paired this way (wave
+// bits in digits 2 and 3), and so are the recomputing forward passes of
+// digits 1 and 2 (wave bits in digits 0 and 3), which get pass-only maps of
+// their own (PassArgs::pmap).  (Pairing the phases of digits 3 and 2 too,
+// wave bits in digits 0 and 1, leaves no conflict-free maps for digits 0
+// and 3 and measured slower.)
 #include <algorithm>
 #include <cstdint>
 #include <map>
@@ -132,7 +144,114 @@ struct Best {
     FastMap m;
 };
 
+// fibre-index mask (8 bits) of digit j whose wave bits are the tile-position
+// bits in S (logC = 0: fibre bit b is position bit b below digit j, b + 3
+// above it); 0 when some bit of S is not a fibre bit below 8
+uint32_t mask_for_wave_bits(uint32_t S, int j) {
+    uint32_t wave = 0;
+    for (int b = 0; b < 8; ++b) {
+        const int p = b < 3 * j ? b : b + 3;
+        if (S >> p & 1u) wave |= 1u << b;
+    }
+    if (__builtin_popcount(wave) != 4 || (uint32_t)__builtin_popcount(S) != 4u) return 0;
+    return ~wave & 0xffu;
+}
+
+// least conflict cost of a fused (pass + gradient) map of digit j with the
+// given mask, and its code (mask | kb0 << 8 | kb1 << 11)
+int fused_cost(const Pads& pd, int j, uint32_t mask, uint64_t* code) {
+    const uint32_t h = 3u * (uint32_t)j;
+    const int sc = stage_cost(pd, h, mask);
+    int best = 1 << 30;
+    for (int kb0 = 0; kb0 < 8; ++kb0)
+        for (int kb1 = 0; kb1 < 8; ++kb1) {
+            if (kb0 == kb1 || !(mask >> kb0 & 1u) || !(mask >> kb1 & 1u)) continue;
+            const int c = sc + gw_cost(pd, h, mask, kb0, kb1);
+            if (c < best) {
+                best = c;
+                *code = mask | ((uint64_t)kb0 << 8) | ((uint64_t)kb1 << 11);
+            }
+        }
+    return best;
+}
+
+// the paired layout of the four-digit backward on 4096-element tiles
+FastMap search_paired() {
+    const uint32_t tileE = 4096u;
+    Best best;
+    for (int n = 0; n <= 3; ++n) {
+        int p[3];
+        for (p[0] = 4; p[0] <= 12; ++p[0])
+            for (p[1] = (n > 1 ? p[0] + 1 : 13); p[1] <= (n > 1 ? 12 : 13); ++p[1])
+                for (p[2] = (n > 2 ? p[1] + 1 : 13); p[2] <= (n > 2 ? 12 : 13); ++p[2]) {
+                    Pads pd{{p[0], p[1], p[2]}, n};
+                    if (n == 0 && p[0] != 4) continue;
+                    uint32_t extra = 0;
+                    for (int i = 0; i < n; ++i) extra += tileE >> pd.p[i];
+                    if (extra > tileE / 8) continue;  // LDS budget of the four backward tiles
+                    int total = io_cost(pd, tileE);
+                    if (total >= best.cost) continue;
+                    FastMap m;
+                    m.pad = pd.packed();
+                    // digits 0 and 1 (adjoint pair): wave bits among positions 6..10
+                    int bc = 1 << 30;
+                    uint64_t c01 = 0;
+                    for (uint32_t S = 0; S < 4096u; ++S) {
+                        if ((S & ~0x7c0u) || __builtin_popcount(S) != 4) continue;
+                        uint64_t k0 = 0, k1 = 0;
+                        const int c = fused_cost(pd, 0, mask_for_wave_bits(S, 0), &k0) +
+                                      fused_cost(pd, 1, mask_for_wave_bits(S, 1), &k1);
+                        if (c < bc) {
+                            bc = c;
+                            c01 = k0 | (k1 << 16);
+                        }
+                    }
+                    total += bc;
+                    // digits 2 and 3: free
+                    uint64_t c23 = 0;
+                    for (int j = 2; j < 4; ++j) {
+                        int bj = 1 << 30;
+                        uint64_t cj = 0;
+                        for (uint32_t mask = 0; mask < 256; ++mask) {
+                            if (__builtin_popcount(mask) != 4) continue;
+                            uint64_t k = 0;
+                            const int c = fused_cost(pd, j, mask, &k);
+                            if (c < bj) {
+                                bj = c;
+                                cj = k;
+                            }
+                        }
+                        total += bj;
+                        c23 |= cj << (16 * (j - 2));
+                    }
+                    // pass maps of digits 1 and 2 (recompute pair): wave bits
+                    // among positions 0..2, 9, 10
+                    int bp = 1 << 30;
+                    uint32_t pm = 0;
+                    for (uint32_t S = 0; S < 4096u; ++S) {
+                        if ((S & ~0x607u) || __builtin_popcount(S) != 4) continue;
+                        const uint32_t m1 = mask_for_wave_bits(S, 1), m2 = mask_for_wave_bits(S, 2);
+                        const int c = stage_cost(pd, 3u, m1) + stage_cost(pd, 6u, m2);
+                        if (c < bp) {
+                            bp = c;
+                            pm = m1 | (m2 << 8);
+                        }
+                    }
+                    total += bp;
+                    m.map = c01 | (c23 << 32);
+                    m.pmap = pm;
+                    if (total < best.cost) {
+                        best.cost = total;
+                        best.m = m;
+                    }
+                }
+    }
+    best.m.conflicts = best.cost;
+    return best.m;
+}
+
 FastMap search(int K, int NI, int logC, bool gw) {
+    if (gw && K == 4 && NI == 2 && logC == 0) return search_paired();
     const uint32_t tileE = 2048u * (uint32_t)NI;
     // candidate paddings, fewest extra elements first
     std::vector<std::pair<uint32_t, Pads>> cands;

@@ -36,6 +36,7 @@ struct Group {
     int64_t elems = 0;  // elements covered by one launch of this group
     int fast_ni = 0;     // > 0: radix-8 matrix-core kernel with per-lane addresses, tile 2048 * fast_ni
     uint64_t fmap = 0;   // its fibre-to-lane maps (PassArgs::fmap)
+    uint32_t pmap = 0;   // pass-only maps of a paired backward layout (PassArgs::pmap)
     int fast_conflicts = 0;  // residual LDS bank conflicts of that layout (model)
 };
 
@@ -44,6 +45,7 @@ struct Group {
 struct FastMap {
     int pad = kNoPad;   // packed pad shifts
     uint64_t map = 0;   // PassArgs::fmap
+    uint32_t pmap = 0;  // PassArgs::pmap (paired layouts; 0: none)
     int conflicts = 0;  // residual bank conflicts of the layout (0: none)
 };
 FastMap fast_map(int K, int NI, int logC, bool gw);

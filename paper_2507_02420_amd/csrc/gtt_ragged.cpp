@@ -443,10 +443,10 @@ std::string describe_plan(const gtt_plan_s* p) {
         std::snprintf(b, sizeof b,
                       "{\"s0\":%d,\"k\":%d,\"S\":%lld,\"G\":%lld,\"C\":%d,\"P\":%d,\"L\":%lld,\"tiles\":%lld,"
                       "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"kind\":\"%s\",\"lds_bytes\":%zu,"
-                      "\"fast_ni\":%d,\"fmap\":%llu,\"fast_conflicts\":%d}",
+                      "\"fast_ni\":%d,\"fmap\":%llu,\"pmap\":%u,\"fast_conflicts\":%d}",
                       g.s0, g.k, (long long)g.S, (long long)g.G, g.C, g.P, (long long)g.L, (long long)g.ntiles,
                       (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : g.kind == 2 ? "mfma" : "cmfma",
-                      g.lds_bytes, g.fast_ni, (unsigned long long)g.fmap, g.fast_conflicts);
+                      g.lds_bytes, g.fast_ni, (unsigned long long)g.fmap, g.pmap, g.fast_conflicts);
         return std::string(b);
     };
     std::string s = "{";

@@ -77,12 +77,12 @@ static hipError_t launch_fast(const CBwdArgs& a, unsigned grid, size_t lds, hipS
 // checks that the planner still produces exactly these layouts.
 using FwdLay4 = LayoutFixed<0x1f0a05, 0, 0x1e001b00270017ull>;
 using FwdLay2 = LayoutFixed<0x1f0a05, 6, 0x1e001bull>;
-using BwdLay4 = LayoutFixed<0x1f0905, 0, 0x31d081b01270817ull>;
+using BwdLay4 = LayoutFixed<0x1f0805, 0, 0x81b031b01870887ull, 0x7878u>;
 using BwdLay2 = LayoutFixed<0x1f0905, 6, 0x31d081bull>;
 
 template <class LAY>
 static bool layout_is(const PassArgs& a) {
-    return a.pad_shift == LAY::kPad && a.logC == LAY::kLogC && a.fmap == LAY::kFmap;
+    return a.pad_shift == LAY::kPad && a.logC == LAY::kLogC && a.fmap == LAY::kFmap && a.pmap == LAY::kPmap;
 }
 
 template <int K, int NI, class LAY>

@@ -151,9 +151,35 @@ def test_planner_layouts_match_compiled_specializations():
     # that workload silently falls back to run-time offsets
     d = G.Plan(8, 6, 256, torch.complex64).describe()
     fwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"]) for g in d["groups"]]
-    bwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"]) for g in d["bwd_groups"]]
+    bwd = [(g["k"], g["fast_ni"], g["C"], g["pad_shift"], g["fmap"], g["pmap"]) for g in d["bwd_groups"]]
     assert fwd == [(4, 2, 1, 0x1f0a05, 0x1e001b00270017), (2, 2, 64, 0x1f0a05, 0x1e001b)]
-    assert bwd == [(4, 2, 1, 0x1f0905, 0x31d081b01270817), (2, 2, 64, 0x1f0905, 0x31d081b)]
+    assert bwd == [(4, 2, 1, 0x1f0805, 0x81b031b01870887, 0x7878), (2, 2, 64, 0x1f0905, 0x31d081b, 0)]
+
+
+def _wave_positions(mask, j):
+    # tile-position bits (logC = 0, three bits per digit) that carry the wave
+    # index under fibre-bit mask `mask` of digit j
+    return {b if b < 3 * j else b + 3 for b in range(8) if not mask >> b & 1}
+
+
+def test_paired_backward_layout_keeps_each_pair_inside_a_wave():
+    # four-digit backward on 4096-element tiles: the fused phases of digits 1
+    # and 0, and the recomputing passes of digits 1 and 2, run without a
+    # barrier in between; that is sound when both phases of a pair give every
+    # wave the same positions, i.e. the same four wave position bits, none in
+    # the pair's digits
+    g = G.Plan(8, 6, 256, torch.complex64).describe()["bwd_groups"][0]
+    assert (g["k"], g["fast_ni"], g["C"]) == (4, 2, 1)
+    fm, pm = g["fmap"], g["pmap"]
+    w0 = _wave_positions(fm & 0xff, 0)
+    w1 = _wave_positions((fm >> 16) & 0xff, 1)
+    assert w0 == w1 and len(w0) == 4 and w0 <= set(range(6, 12))
+    p1 = _wave_positions(pm & 0xff, 1)
+    p2 = _wave_positions((pm >> 8) & 0xff, 2)
+    assert p1 == p2 and len(p1) == 4 and p1 <= {0, 1, 2, 9, 10, 11}
+    # the loop-step bit (fibre bit 8) is not a wave bit: it is position 11
+    # for digits 0..2
+    assert 11 not in w0 and 11 not in p1
 
 
 def test_fp32_intermediate_plan_sizes_and_limits():
