@@ -343,6 +343,26 @@ def secondary(iters=10):
     yf = torch.empty_like(xf)
     msb, _ = time_calls(lambda: pb.forward(Wt, xb, yb), 3)
     msf, _ = time_calls(lambda: pf.forward(Wt, xf, yf), 3)
+    # the same batch as ONE persistent launch (grid barriers between phases)
+    pp = G.Plan(bs, ns, 1, torch.bfloat16, flags=G.FLAG_PERSISTENT)
+    yp = torch.empty_like(xb)
+    pp.forward(Wt, xb, yp)   # the first call uploads the work list
+    msp, _ = time_calls(lambda: pp.forward(Wt, xb, yp), 3)
+    # the default per-phase launches captured in a HIP graph: one launch
+    # for the caller
+    yg = torch.empty_like(xb)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pb.forward(Wt, xb, yg)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pb.forward(Wt, xb, yg)
+    yg.zero_()
+    msg, _ = time_calls(graph.replay, 5)
+    _sync()
+    same = bool(torch.equal(yp, yb)) and bool(torch.equal(yg, yb))
     # per-instance error of the bf16 path against the plain FP32 path
     offs = np.cumsum([0] + [b_ ** n_ for b_, n_ in shapes])
     yb32 = yb.to(torch.float32)
@@ -351,6 +371,8 @@ def secondary(iters=10):
         a, c = int(offs[t]), int(offs[t + 1])
         errs.append(float((torch.linalg.vector_norm(yb32[a:c] - yf[a:c]) / torch.linalg.vector_norm(yf[a:c])).item()))
     res["ragged_bf16_1024"] = {"elements": Ntot, "ms_bf16": msb, "elements_per_s_bf16": Ntot / (msb * 1e-3),
+                               "ms_bf16_persistent_launch": msp, "ms_bf16_graph_replay": msg,
+                               "persistent_and_graph_equal_phases": same,
                                "ms_plain_fp32": msf, "elements_per_s_plain_fp32": Ntot / (msf * 1e-3),
                                "rel_err_vs_fp32_max": max(errs), "rel_err_vs_fp32_median": float(np.median(errs)),
                                "instances_checked": len(errs)}

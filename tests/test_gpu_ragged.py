@@ -148,9 +148,8 @@ def test_ragged_full_shape_list_bf16_sampled(mode):
 
 @pytest.mark.parametrize("mode", ["persistent", "phases"])
 def test_ragged_graph_replay(mode):
-    # per-phase mode: the runs of each phase fork onto helper streams and
-    # join back, which the capture must follow (several radix classes per
-    # phase: 2, 3, 4 on the VALU, 16 on the matrix cores)
+    # per-phase mode: one launch per phase and radix class, several classes
+    # per phase (2, 3, 4 on the VALU, 16 on the matrix cores), all captured
     shapes = SMALL if mode == "persistent" else [(2, 12), (16, 3), (4, 7), (3, 8), (2, 5), (16, 4), (4, 3)]
     dtype = torch.bfloat16
     say(f"ragged graph replay, {mode}")
