@@ -126,37 +126,6 @@ __device__ __forceinline__ void ragged_tile_valu(unsigned char* smem, const Pass
     __syncthreads();
 }
 
-template <typename T, int B>
-__device__ __forceinline__ void ragged_tile_mfma(unsigned char* smem, const PassArgs& a, const T* in, T* out,
-                                              const float* W, int adjoint, int64_t t) {
-    PassArgs aw;  // only W / adjoint are read by the fragment loader
-    aw.W = W;
-    aw.adjoint = adjoint;
-    WFrag<T, B> wf;
-    load_w_frag<T, B>(wf, aw);
-    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
-    if constexpr (std::is_same<T, float>::value) {
-        float* lds = reinterpret_cast<float*>(smem + 256);
-        tile_load<T, float>(lds, a, in, t, rows);
-        __syncthreads();
-        for (int j = 0; j < a.k; ++j) {
-            mfma_stage<T, B>(lds, a, j, rows, wf);
-            __syncthreads();
-        }
-        tile_store<T, float>(lds, a, out, t, rows);
-    } else {
-        uint16_t* lds = reinterpret_cast<uint16_t*>(smem + 256);
-        tile_load16<T>(lds, a, in, t, rows);
-        __syncthreads();
-        for (int j = 0; j < a.k; ++j) {
-            mfma_stage16<T, B>(lds, a, j, rows, wf);
-            __syncthreads();
-        }
-        tile_store16<T>(lds, a, out, t, rows);
-    }
-    __syncthreads();
-}
-
 template <typename T>
 __device__ __forceinline__ void ragged_tile_generic(unsigned char* smem, const PassArgs& a, const T* in, T* out,
                                                  const typename Tr<T>::C* W, int adjoint, int64_t t) {
@@ -246,13 +215,6 @@ __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArg
                 case 5: ragged_tile_valu<T, 5>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
                 default: ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile); break;
             }
-        } else if (d.kind == kKindMfma) {
-            if constexpr (sizeof(T) == 2 || std::is_same<T, float>::value) {
-                if (d.b == 16)
-                    ragged_tile_mfma<T, 16>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
-                else
-                    ragged_tile_mfma<T, 32>(smem, d.a, in, out, reinterpret_cast<const float*>(W), r.adjoint, it.tile);
-            }
         } else {
             ragged_tile_generic<T>(smem, d.a, in, out, W, r.adjoint, it.tile);
         }
@@ -265,14 +227,69 @@ __device__ __forceinline__ void ragged_item(unsigned char* smem, const RaggedArg
     }
 }
 
+template <typename T, int B>
+__device__ __forceinline__ void ragged_tile_mfma_wf(unsigned char* smem, const PassArgs& a, const T* in, T* out,
+                                                    const WFrag<T, B>& wf, int64_t t) {
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    if constexpr (std::is_same<T, float>::value) {
+        float* lds = reinterpret_cast<float*>(smem + 256);
+        tile_load<T, float>(lds, a, in, t, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            mfma_stage<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        tile_store<T, float>(lds, a, out, t, rows);
+    } else {
+        uint16_t* lds = reinterpret_cast<uint16_t*>(smem + 256);
+        tile_load16<T>(lds, a, in, t, rows);
+        __syncthreads();
+        for (int j = 0; j < a.k; ++j) {
+            mfma_stage16<T, B>(lds, a, j, rows, wf);
+            __syncthreads();
+        }
+        tile_store16<T>(lds, a, out, t, rows);
+    }
+    __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gtt_ragged_kernel(RaggedArgs r) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr bool kMfma = sizeof(T) == 2 || std::is_same<T, float>::value;
     const int p0 = r.persistent ? 0 : r.phase;
     const int p1 = r.persistent ? r.nphases : r.phase + 1;
+    // matrix-core items keep W's fragments while consecutive items share W
+    [[maybe_unused]] typename std::conditional<kMfma, WFrag<T, 16>, char>::type wf16;
+    [[maybe_unused]] typename std::conditional<kMfma, WFrag<T, 32>, char>::type wf32;
+    [[maybe_unused]] int64_t w16 = -1, w32 = -1;
     for (int p = p0; p < p1; ++p) {
-        for (int64_t i = r.phase_start[p] + blockIdx.x; i < r.phase_start[p + 1]; i += gridDim.x)
-            ragged_item<T, kClsAny>(smem_raw, r, r.items[i]);
+        for (int64_t i = r.phase_start[p] + blockIdx.x; i < r.phase_start[p + 1]; i += gridDim.x) {
+            const RaggedItem it = r.items[i];
+            if constexpr (kMfma) {
+                const RaggedDesc& d = r.desc[it.d];
+                if (d.kind == kKindMfma) {
+                    PassArgs aw;  // only W / adjoint are read by the fragment loader
+                    aw.W = static_cast<const float*>(r.W) + d.w_off;
+                    aw.adjoint = r.adjoint;
+                    if (d.b == 16) {
+                        if (d.w_off != w16) {
+                            load_w_frag<T, 16>(wf16, aw);
+                            w16 = d.w_off;
+                        }
+                        ragged_tile_mfma_wf<T, 16>(smem_raw, d.a, ragged_in<T>(r, d), ragged_out<T>(r, d), wf16, it.tile);
+                    } else {
+                        if (d.w_off != w32) {
+                            load_w_frag<T, 32>(wf32, aw);
+                            w32 = d.w_off;
+                        }
+                        ragged_tile_mfma_wf<T, 32>(smem_raw, d.a, ragged_in<T>(r, d), ragged_out<T>(r, d), wf32, it.tile);
+                    }
+                    continue;
+                }
+            }
+            ragged_item<T, kClsAny>(smem_raw, r, it);
+        }
         if (r.persistent && p + 1 < p1) grid_barrier(r.bar, gridDim.x);
     }
 }
