@@ -163,8 +163,8 @@ int fused_cost(const Pads& pd, int j, uint32_t mask, uint64_t* code) {
     const uint32_t h = 3u * (uint32_t)j;
     const int sc = stage_cost(pd, h, mask);
     int best = 1 << 30;
-    for (int kb0 = 0; kb0 < 8; ++kb0)
-        for (int kb1 = 0; kb1 < 8; ++kb1) {
+    for (int kb0 = 0; kb0 < 8 && best > 0; ++kb0)
+        for (int kb1 = 0; kb1 < 8 && best > 0; ++kb1) {
             if (kb0 == kb1 || !(mask >> kb0 & 1u) || !(mask >> kb1 & 1u)) continue;
             const int c = sc + gw_cost(pd, h, mask, kb0, kb1);
             if (c < best) {
@@ -212,7 +212,7 @@ FastMap search_paired() {
                     for (int j = 2; j < 4; ++j) {
                         int bj = 1 << 30;
                         uint64_t cj = 0;
-                        for (uint32_t mask = 0; mask < 256; ++mask) {
+                        for (uint32_t mask = 0; mask < 256 && bj > 0; ++mask) {
                             if (__builtin_popcount(mask) != 4) continue;
                             uint64_t k = 0;
                             const int c = fused_cost(pd, j, mask, &k);
