@@ -357,6 +357,7 @@ void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, co
     a->ntiles = g.ntiles;
     a->N = N;
     a->divG = make_fastdiv((uint32_t)g.G);
+    a->divL = make_fastdiv(g.L < (int64_t(1) << 31) ? (uint32_t)g.L : 1u);
     int64_t pv = 1;
     for (int j = 0; j <= g.k; ++j) {
         a->bpow[j] = (int32_t)pv;

@@ -48,6 +48,7 @@ struct PassArgs {
     int64_t ntiles;     // tiles in this launch
     int64_t N;          // elements per instance (masking by natural index)
     FastDiv divG;       // division by G (row -> hi block within the tile)
+    FastDiv divL;       // division by L (tile -> hi block), valid when L < 2^31
     FastDiv divb[kMaxDigits + 1];  // division by b^j, j = 0..k
     int32_t bpow[kMaxDigits + 1];  // b^j, j = 0..k (fits: G <= 2^24); for a
                                    // mixed-radix group, the place value of

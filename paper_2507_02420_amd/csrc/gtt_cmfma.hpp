@@ -156,7 +156,7 @@ template <int NV = kBwdVec, bool FULL = false>
 __device__ __forceinline__ void bwd_fetch(uint4 (&buf)[NV], const PassArgs& a, const cf* __restrict__ in,
                                           int64_t t, uint32_t tileE) {
     const bool contig = a.mode == kContigVec;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     const uint32_t nvec = tileE / 2;
 #pragma unroll
@@ -185,7 +185,7 @@ __device__ __forceinline__ void bwd_commit(cf* lds, const uint4 (&buf)[NV], cons
 __device__ __forceinline__ void bwd_store(const cf* lds, const PassArgs& a, cf* __restrict__ out, int64_t t,
                                           uint32_t tileE) {
     const bool contig = a.mode == kContigVec;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     const uint32_t nvec = tileE / 2;
     for (uint32_t i = threadIdx.x; i < nvec; i += kBwdThreads) {

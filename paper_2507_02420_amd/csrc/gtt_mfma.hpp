@@ -201,7 +201,7 @@ __device__ __forceinline__ void tile_load16(uint16_t* lds, const PassArgs& a, co
     static_assert(sizeof(T) == 2, "16-bit storage");
     const uint32_t tileE = rows << a.logC;
     const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     const uint16_t* __restrict__ src = reinterpret_cast<const uint16_t*>(in);
     uint32_t* w = reinterpret_cast<uint32_t*>(lds);
@@ -262,7 +262,7 @@ __device__ __forceinline__ void tile_store16(const uint16_t* lds, const PassArgs
     static_assert(sizeof(T) == 2, "16-bit storage");
     const uint32_t tileE = rows << a.logC;
     const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     uint16_t* __restrict__ dst = reinterpret_cast<uint16_t*>(out);
     const uint32_t* w = reinterpret_cast<const uint32_t*>(lds);
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
         // they do not stay live in registers across the loop
         auto fetch = [&](int64_t t) {
             const bool contig = a.mode == kContigVec;
-            const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+            const int64_t hb = contig ? 0 : tile_hb(a, t);
             const int64_t l = contig ? 0 : t - hb * a.L;
             uint32_t tid = threadIdx.x;
             asm volatile("" : "+v"(tid));

@@ -27,6 +27,14 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
     return (__umulhi(n, f.m) + n) >> f.s;
 }
 
+// hi block of tile t (t = hb * L + l, the tile's column block l < L): one
+// multiply-high while t and L are below 2^31, a 64-bit division beyond
+__device__ __forceinline__ int64_t tile_hb(const PassArgs& a, int64_t t) {
+    if (a.L == 1) return t;
+    if (t < 0x80000000LL && a.L < 0x80000000LL) return (int64_t)fdiv((uint32_t)t, a.divL);
+    return t / a.L;
+}
+
 template <int B, int R>
 struct IPow {
     static constexpr int value = B * IPow<B, R - 1>::value;
@@ -234,13 +242,54 @@ __device__ __forceinline__ int64_t elem_offset(const PassArgs& a, int64_t t, uin
     return row_offset(a, hb, l, r) + c;
 }
 
+// Vector-mode addresses of a tile as a walk: vector i = tid + m * kThreads
+// of tile t lies at global element g0 + m * gstep and at LDS element
+// l0 + m * lstep.  This holds for contiguous tiles, and for row tiles of one
+// hi block (P == 1) whose rows have at most kThreads vectors; on the LDS
+// side lds_phys is additive over the step when every pad period divides
+// kThreads * V (vec_walk_ok checks both).
+struct VecWalk {
+    int64_t g0, gstep;
+    uint32_t l0, lstep;
+};
+template <typename T>
+__device__ __forceinline__ bool vec_walk_ok(const PassArgs& a) {
+    constexpr int lv = __builtin_ctz(Vec16<T>::V);
+    constexpr int lim = __builtin_ctz(kThreads) + lv;
+    for (int k = 0; k < 3; ++k) {
+        const int sh = (a.pad_shift >> (8 * k)) & 31;
+        if (sh != 31 && sh > lim) return false;
+    }
+    if (a.mode == kContigVec) return true;
+    return a.mode == kRowVec && a.P == 1 && a.logC >= lv && a.logC - lv <= __builtin_ctz(kThreads);
+}
+template <typename T>
+__device__ __forceinline__ VecWalk vec_walk(const PassArgs& a, int64_t t, uint32_t tid, uint32_t tileE) {
+    constexpr int V = Vec16<T>::V;
+    VecWalk w;
+    if (a.mode == kContigVec) {
+        w.g0 = t * (int64_t)tileE + (int64_t)tid * V;
+        w.gstep = (int64_t)kThreads * V;
+    } else {
+        const int lcv = a.logC - __builtin_ctz(V);
+        const int64_t hb = tile_hb(a, t);
+        const int64_t l = t - hb * a.L;
+        w.g0 = hb * ((int64_t)a.G * a.S) + (l << a.logC) + (int64_t)(tid >> lcv) * a.S +
+               (int64_t)(tid & ((1u << lcv) - 1u)) * V;
+        w.gstep = (int64_t)(kThreads >> lcv) * a.S;
+    }
+    w.l0 = lds_phys(tid * V, a.pad_shift);
+    w.lstep = lds_phys(kThreads * V, a.pad_shift);
+    return w;
+}
+
 template <typename T, typename C>
 __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
                                           uint32_t rows) {
     constexpr int V = Vec16<T>::V;
     const uint32_t tileE = rows << a.logC;
     const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     if (a.mode == kContigVec || a.mode == kRowVec) {
         const uint32_t nvec = tileE / V;
@@ -295,16 +344,28 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
     }
 }
 
-template <typename T, typename C>
+template <typename T, typename C, bool WALK = false>
 __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* __restrict__ out, int64_t t,
                                            uint32_t rows) {
     constexpr int V = Vec16<T>::V;
     const uint32_t tileE = rows << a.logC;
     const bool contig = a.mode == kContigVec || a.mode == kContigScalar;
-    const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+    const int64_t hb = contig ? 0 : tile_hb(a, t);
     const int64_t l = contig ? 0 : t - hb * a.L;
     if (a.mode == kContigVec || a.mode == kRowVec) {
         const uint32_t nvec = tileE / V;
+        if (WALK && vec_walk_ok<T>(a)) {
+            const VecWalk w = vec_walk<T>(a, t, threadIdx.x, tileE);
+            uint32_t m = 0;
+            for (uint32_t i = threadIdx.x; i < nvec; i += kThreads, ++m) {
+                T vals[V];
+                const uint32_t ph = w.l0 + m * w.lstep;
+#pragma unroll
+                for (int e = 0; e < V; ++e) vals[e] = from_c<T>(lds[ph + e]);
+                gstore16<true>(out + w.g0 + (int64_t)m * w.gstep, *reinterpret_cast<const uint4*>(vals));
+            }
+            return;
+        }
         for (uint32_t i = threadIdx.x; i < nvec; i += kThreads) {
             T vals[V];
             const uint32_t ph = lds_phys(i * V, a.pad_shift);
@@ -396,8 +457,10 @@ __device__ __forceinline__ void pf_commit_scalar(C* lds, const uint4 (&r)[kPfVec
 // type C in LDS).  PF: when the work-group has more than one tile, the tile
 // fits the prefetch buffer and no filter mask applies, the loads of tile
 // t + gridDim.x are in flight into registers while tile t runs its stages
-// from LDS, so HBM stays busy through the LDS phases.
-template <typename T, typename C, bool PF = false, typename Stages>
+// from LDS, so HBM stays busy through the LDS phases.  WALK: vector tiles
+// take their addresses from a VecWalk where vec_walk_ok allows it (costs
+// registers in every mode, so only kernels that meet vector tiles enable it).
+template <typename T, typename C, bool PF = false, bool WALK = false, typename Stages>
 __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& stages) {
     constexpr int V = Vec16<T>::V;
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
@@ -414,15 +477,23 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
         }
     }
     [[maybe_unused]] uint4 r[PF ? kPfVec : 1];
+    [[maybe_unused]] const bool walk = WALK && vec && vec_walk_ok<T>(a);
     // the per-item offsets are recomputed for every tile (an opaque thread
     // index): hoisted out of the tile loop they would hold registers per item
     auto fetch = [&](int64_t t) {
         if constexpr (PF) {
-            const int64_t hb = contig ? 0 : ((a.L == 1) ? t : t / a.L);
+            const int64_t hb = contig ? 0 : tile_hb(a, t);
             const int64_t l = contig ? 0 : t - hb * a.L;
             uint32_t tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
-            if (pf == 1) {
+            if (pf == 1 && walk) {
+                const VecWalk w = vec_walk<T>(a, t, tid, tileE);
+#pragma unroll
+                for (int v = 0; v < kPfVec; ++v) {
+                    const uint32_t i = tid + v * kThreads;
+                    if (i < tileE / V) r[v] = gload16<true>(in + w.g0 + (int64_t)v * w.gstep);
+                }
+            } else if (pf == 1) {
 #pragma unroll
                 for (int v = 0; v < kPfVec; ++v) {
                     const uint32_t i = tid + v * kThreads;
@@ -438,13 +509,15 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
             uint32_t tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
             if (pf == 1) {
+                const uint32_t l0 = walk ? lds_phys(tid * V, a.pad_shift) : 0u;
+                const uint32_t lstep = lds_phys(kThreads * V, a.pad_shift);
 #pragma unroll
                 for (int v = 0; v < kPfVec; ++v) {
                     const uint32_t i = tid + v * kThreads;
                     if (i < tileE / V) {
                         T vals[V];
                         *reinterpret_cast<uint4*>(vals) = r[v];
-                        const uint32_t ph = lds_phys(i * V, a.pad_shift);
+                        const uint32_t ph = walk ? l0 + v * lstep : lds_phys(i * V, a.pad_shift);
 #pragma unroll
                         for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
                     }
@@ -464,7 +537,7 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
         __syncthreads();
         if (pf && t + gridDim.x < a.ntiles) fetch(t + gridDim.x);
         stages(lds, rows);
-        tile_store<T, C>(lds, a, out, t, rows);
+        tile_store<T, C, WALK>(lds, a, out, t, rows);
         __syncthreads();
     }
 }
@@ -505,8 +578,9 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     bool h2 = false;
     if constexpr (B == 2 && std::is_same<C, uint32_t>::value)
         h2 = w[0] == 1u && w[1] == 1u && w[2] == 1u && w[3] == 0xffffffffu;
-    tile_loop<T, C, pass_prefetches<C, B>()>(lds, a,
-                                             [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w, h2); });
+    // the address walk only pays where vector tiles occur: power-of-two radices
+    tile_loop<T, C, pass_prefetches<C, B>(), (B & (B - 1)) == 0>(
+        lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w, h2); });
 }
 
 }  // namespace gtt

@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch
 
 from conftest import ROOT
 
@@ -294,3 +295,67 @@ def test_ragged_packed_instances_off_16_byte_boundary(dtype):
     aligned = [(2, 5), (16, 3), (4, 2)]
     p = G.Plan([b for b, _ in aligned], [n for _, n in aligned], 1, dtype)
     assert p.describe()["scalar_instances"] == 0
+
+
+# element sizes of the storage dtypes (vector-mode tiles move 16 bytes a lane)
+_ES = {torch.float64: 8, torch.float32: 4, torch.complex64: 8, torch.complex128: 16, torch.int32: 4}
+
+
+@pytest.mark.parametrize("dtype", list(_ES))
+def test_vector_tile_address_walk(dtype):
+    """The VALU pass kernels of power-of-two radices take the addresses of a
+    vector-mode tile as a walk: lane tid's m-th 16-byte vector at global
+    element g0 + m * gstep and at LDS element l0 + m * lstep, when the pads'
+    periods divide 256 vectors and row tiles hold one hi block with rows of at
+    most 256 vectors.  This re-derives both address maps from the plan's
+    geometry and checks that, wherever that condition holds, the walk equals
+    the per-vector formulas (row decomposition, lds_phys)."""
+    KT = 256
+    V = 16 // _ES[dtype]
+    lv = V.bit_length() - 1
+
+    def lds_phys(x, ps):
+        return x + sum(x >> ((ps >> (8 * k)) & 31) for k in range(3))
+
+    def per_vector(g, t, i):
+        tileE = g["tile_elems"]
+        if g["mode"] == 0:
+            return t * tileE + i * V
+        lcv = g["logC"] - lv
+        hb, l = divmod(t, g["L"])
+        r, cc = i >> lcv, i & ((1 << lcv) - 1)
+        p, gg = divmod(r, g["G"]) if g["P"] != 1 else (0, r)
+        return (hb * g["P"] + p) * (g["G"] * g["S"]) + gg * g["S"] + (l << g["logC"]) + cc * V
+
+    walked = 0
+    for b in (2, 4, 8):
+        for n in range(4, 15):
+            for batch in (1, 5):
+                if b ** n * batch > 2 ** 20:
+                    continue
+                for g in G.Plan(b, n, batch, dtype).describe()["groups"]:
+                    if g["mode"] not in (0, 2):
+                        continue
+                    g["logC"] = g["C"].bit_length() - 1
+                    shifts = [(g["pad_shift"] >> (8 * k)) & 31 for k in range(3)]
+                    ok = all(s == 31 or s <= 8 + lv for s in shifts) and (
+                        g["mode"] == 0 or (g["P"] == 1 and lv <= g["logC"] <= 8 + lv))
+                    if not ok:
+                        continue
+                    walked += 1
+                    lcv = g["logC"] - lv
+                    nvec = g["tile_elems"] // V
+                    for t in sorted({0, g["tiles"] // 2, g["tiles"] - 1}):
+                        hb, l = divmod(t, g["L"])
+                        for tid in range(0, KT, 7):
+                            if g["mode"] == 0:
+                                g0, gs = t * g["tile_elems"] + tid * V, KT * V
+                            else:
+                                g0 = (hb * g["G"] * g["S"] + (l << g["logC"]) + (tid >> lcv) * g["S"]
+                                      + (tid & ((1 << lcv) - 1)) * V)
+                                gs = (KT >> lcv) * g["S"]
+                            l0, ls = lds_phys(tid * V, g["pad_shift"]), lds_phys(KT * V, g["pad_shift"])
+                            for m, i in enumerate(range(tid, nvec, KT)):
+                                assert g0 + m * gs == per_vector(g, t, i)
+                                assert l0 + m * ls == lds_phys(i * V, g["pad_shift"])
+    assert walked > 0
