@@ -23,8 +23,10 @@
  *      double, GTT_I32 -> int32 (arithmetic mod 2^32, two's complement).
  *  - Complex data is interleaved (re, im), as in torch.complex64/complex128.
  *  - Pointers named x, y, W, gy, gx, gW, saved and ws are DEVICE pointers
- *    owned by the caller; the library never frees them and never allocates
- *    device memory inside forward / inverse / backward.
+ *    owned by the caller; the library never frees them.  Forward / inverse
+ *    / backward allocate no device memory, with one exception: the first
+ *    call on a ragged plan uploads its work list into device memory that
+ *    lives until gtt_plan_destroy (make one call before capturing a graph).
  *  - All device work is enqueued on `stream` (a hipStream_t; NULL is the
  *    null stream).  Calls return as soon as the work is enqueued.
  *  - Argument checks run on the host, before any HIP call, and report a
