@@ -129,11 +129,12 @@ __global__ __launch_bounds__(kThreads) void gtt_c64_mfma8_pass_kernel(PassArgs a
     cf* lds = reinterpret_cast<cf*>(smem_raw);
     CFrag8 fr;
     load_cfrag8(fr, static_cast<const cf*>(a.W), a.adjoint);
-    tile_loop<cf, cf>(lds, a, [&](cf* t, uint32_t rows) {
+    tile_loop<cf, cf>(lds, a, [&](cf* t, uint32_t rows, int64_t) {
         for (int j = 0; j < a.k; ++j) {
             cmfma_stage8(t, t, a, j, rows, fr);
             __syncthreads();
         }
+        return false;
     });
 }
 

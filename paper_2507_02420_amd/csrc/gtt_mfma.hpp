@@ -368,11 +368,12 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_mfma_kernel(PassArgs a) {
     if constexpr (std::is_same<T, float>::value) {
         // persistent grid, next tile prefetched into registers (tile_loop)
         float* lds = reinterpret_cast<float*>(smem_raw);
-        tile_loop<T, float, true>(lds, a, [&](float* t, uint32_t rows) {
+        tile_loop<T, float, true>(lds, a, [&](float* t, uint32_t rows, int64_t) {
             for (int j = 0; j < a.k; ++j) {
                 mfma_stage<T, B>(t, a, j, rows, wf);
                 __syncthreads();
             }
+            return false;
         });
     } else {
         // The work-groups loop over tiles (the launch is as large as the

@@ -135,9 +135,16 @@ __device__ __forceinline__ uint32_t lds_tile_elems(uint32_t tileE, int pad_shift
 // register digits in bits where lam0 is zero, and lds_phys is additive over
 // numbers with disjoint bits, so every position costs one add of a
 // work-group-uniform offset; without padding positions are linear.
-template <typename C, int B, int R>
+//
+// GOUT: the group's last super-stage writes its results straight to global
+// memory at gout instead of back to LDS (contiguous tiles, or row tiles of
+// one hi block; gt0 = the tile's first global element).  Lanes with
+// consecutive fibres hold consecutive tile positions, so each store of a
+// wave covers whole runs of contiguous elements.
+template <typename C, int B, int R, bool GOUT = false>
 __device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, uint32_t rows,
-                                           const C (&w)[B * B], bool h2 = false) {
+                                           const C (&w)[B * B], bool h2 = false, C* gout = nullptr,
+                                           int64_t gt0 = 0) {
     constexpr int NB = IPow<B, R>::value;
     constexpr bool kPow2 = (B & (B - 1)) == 0;
     const uint32_t Cm = (1u << a.logC) - 1u;
@@ -176,16 +183,46 @@ __device__ __forceinline__ void super_stage(C* lds, const PassArgs& a, int j, ui
         } else {
             BlockAll<C, B, R, 0>::run(v, w);
         }
+        if constexpr (GOUT) {
+            // position lam0 + m * step: element lam0 + m * step of a
+            // contiguous tile, row (lam0 >> logC) + m * b^j of a row tile
+            // (byte offsets from the tile's base fit 32 bits: checked by the caller)
+            const bool row = a.mode == kRowVec;
+            const uint32_t S32 = (uint32_t)a.S;
+            const uint32_t o0 = row ? (lam0 >> a.logC) * S32 + (lam0 & Cm) : lam0;
+            const uint32_t om = row ? bj * S32 : step;
+            char* gb = reinterpret_cast<char*>(gout + gt0);
 #pragma unroll
-        for (int m = 0; m < NB; ++m) lds[idx[m]] = v[m];
+            for (int m = 0; m < NB; ++m)
+                *reinterpret_cast<C*>(gb + (uint32_t)((o0 + (uint32_t)m * om) * (uint32_t)sizeof(C))) = v[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) lds[idx[m]] = v[m];
+        }
     }
 }
 
+// With gout, the last super-stage stores to global memory (see super_stage)
+// and no barrier follows it: the caller's barrier after the tile orders its
+// LDS reads before the next tile's LDS writes.
 template <typename C, int B, int RD>
 __device__ __forceinline__ void run_stages(C* lds, const PassArgs& a, uint32_t rows, const C (&w)[B * B],
-                                           bool h2 = false) {
+                                           bool h2 = false, C* gout = nullptr, int64_t gt0 = 0) {
     for (int j = 0; j < a.k; j += RD) {
         const int r = (a.k - j) < RD ? (a.k - j) : RD;
+        if (gout && j + r == a.k) {
+            if constexpr (RD >= 4) {
+                if (r == 4) { super_stage<C, B, 4, true>(lds, a, j, rows, w, h2, gout, gt0); return; }
+            }
+            if constexpr (RD >= 3) {
+                if (r == 3) { super_stage<C, B, 3, true>(lds, a, j, rows, w, h2, gout, gt0); return; }
+            }
+            if constexpr (RD >= 2) {
+                if (r == 2) { super_stage<C, B, 2, true>(lds, a, j, rows, w, h2, gout, gt0); return; }
+            }
+            super_stage<C, B, 1, true>(lds, a, j, rows, w, h2, gout, gt0);
+            return;
+        }
         if constexpr (RD >= 4) {
             if (r == 4) { super_stage<C, B, 4>(lds, a, j, rows, w, h2); __syncthreads(); continue; }
         }
@@ -536,8 +573,7 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
             tile_load<T, C>(lds, a, in, t, rows);
         __syncthreads();
         if (pf && t + gridDim.x < a.ntiles) fetch(t + gridDim.x);
-        stages(lds, rows);
-        tile_store<T, C, WALK>(lds, a, out, t, rows);
+        if (!stages(lds, rows, t)) tile_store<T, C, WALK>(lds, a, out, t, rows);
         __syncthreads();
     }
 }
@@ -578,9 +614,30 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     bool h2 = false;
     if constexpr (B == 2 && std::is_same<C, uint32_t>::value)
         h2 = w[0] == 1u && w[1] == 1u && w[2] == 1u && w[3] == 0xffffffffu;
-    // the address walk only pays where vector tiles occur: power-of-two radices
-    tile_loop<T, C, pass_prefetches<C, B>(), (B & (B - 1)) == 0>(
-        lds, a, [&](C* t, uint32_t rows) { run_stages<C, B, RD>(t, a, rows, w, h2); });
+    // the address walk and the direct store of the last super-stage only pay
+    // where vector tiles occur: power-of-two radices
+    constexpr bool kPow2 = (B & (B - 1)) == 0;
+    constexpr bool kDirect = kPow2 && std::is_same<T, C>::value;
+    [[maybe_unused]] const bool direct =
+        kDirect && a.k > 0 &&
+        (a.mode == kContigVec ||
+         (a.mode == kRowVec && a.P == 1 && (int64_t)a.G * a.S * (int64_t)sizeof(C) < (int64_t(1) << 31))) &&
+        (int64_t)a.P * a.G * ((int64_t)sizeof(C) << a.logC) < (int64_t(1) << 31);
+    tile_loop<T, C, pass_prefetches<C, B>(), kPow2>(lds, a, [&](C* t, uint32_t rows, int64_t tile) {
+        if constexpr (kDirect) {
+            if (direct) {
+                int64_t gt0 = tile * (int64_t)(rows << a.logC);
+                if (a.mode == kRowVec) {
+                    const int64_t hb = tile_hb(a, tile);
+                    gt0 = hb * ((int64_t)a.G * a.S) + ((tile - hb * a.L) << a.logC);
+                }
+                run_stages<C, B, RD>(t, a, rows, w, h2, reinterpret_cast<C*>(a.out), gt0);
+                return true;
+            }
+        }
+        run_stages<C, B, RD>(t, a, rows, w, h2);
+        return false;
+    });
 }
 
 }  // namespace gtt

@@ -359,3 +359,44 @@ def test_vector_tile_address_walk(dtype):
                                 assert g0 + m * gs == per_vector(g, t, i)
                                 assert l0 + m * ls == lds_phys(i * V, g["pad_shift"])
     assert walked > 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.int32])
+def test_last_stage_direct_store_covers_tile(dtype):
+    """Power-of-two-radix VALU pass kernels store the group's last
+    super-stage straight to global memory (contiguous tiles, and row tiles
+    of one hi block).  Re-derive each lane's fibre and its 32-bit element
+    offsets from the plan's geometry: every tile element is written exactly
+    once, at the address of the tile-to-memory map, within 2^31 bytes."""
+    es = _ES[dtype]
+    checked = 0
+    for b, rd in ((2, 4), (4, 2), (8, 1)):
+        for n in range(1, 13):
+            for batch in (1, 3):
+                if b ** n * batch > 2 ** 18:
+                    continue
+                for g in G.Plan(b, n, batch, dtype).describe()["groups"]:
+                    k, logc = g["k"], g["C"].bit_length() - 1
+                    if g["kind"] != "valu" or k == 0 or not (g["mode"] == 0 or (g["mode"] == 2 and g["P"] == 1)):
+                        continue
+                    checked += 1
+                    j = rd * ((k - 1) // rd)
+                    nb, bj, bjr, cm = b ** (k - j), b ** j, b ** k, (1 << logc) - 1
+                    tile_e, step, row = g["tile_elems"], bj << logc, g["mode"] == 2
+                    for t in sorted({0, g["tiles"] - 1}):
+                        hb, l = divmod(t, g["L"])
+                        gt0 = hb * g["G"] * g["S"] + (l << logc) if row else t * tile_e
+                        seen = set()
+                        for f in range(tile_e // nb):
+                            q, glo = divmod(f >> logc, bj)
+                            lam0 = ((q * bjr + glo) << logc) | (f & cm)
+                            o0 = (lam0 >> logc) * g["S"] + (lam0 & cm) if row else lam0
+                            om = bj * g["S"] if row else step
+                            for m in range(nb):
+                                lam = lam0 + m * step
+                                want = (gt0 + (lam >> logc) * g["S"] + (lam & cm)) if row else gt0 + lam
+                                assert gt0 + o0 + m * om == want
+                                assert (o0 + m * om) * es < 2 ** 31
+                                seen.add(lam)
+                        assert seen == set(range(tile_e))
+    assert checked > 0
