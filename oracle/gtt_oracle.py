@@ -46,6 +46,8 @@ __all__ = [
     "adjoint",
     "grad",
     "fd_grad",
+    "grad_mixed",
+    "fd_grad_mixed",
     "staged_int32",
     "adjoint_int32",
     "sylvester_hadamard",
@@ -328,6 +330,75 @@ def fd_grad(W: np.ndarray, x: np.ndarray, g: np.ndarray, n: int, h: float = 1e-6
                 d = (loss(Wp, x) - loss(Wm, x)) / (2 * h)
                 gW[i, j] += d * unit
     return gx, gW
+
+
+def grad_mixed(Ws: Sequence[np.ndarray], x: np.ndarray, g: np.ndarray):
+    """Gradients of L = Re <g, y> for the heterogeneous transform
+    y = (W_0 kron ... kron W_{m-1}) x (§2.6, remark on distinct factors), in the
+    convention of `grad`: gx = G^H g and, for every factor k separately,
+    gW_k = sum over the fibres of factor k's digit of c_k a_k^H, where a_k is
+    the input of the stage of factor k and c_k the cotangent at its output.
+    The stages run in factor order 0..m-1, as in `staged_mixed` (factor k
+    acts on the digit whose place value is prod_{m>k} b_m).
+    Returns (gx, [gW_0, ..., gW_{m-1}])."""
+    x = np.asarray(x)
+    g = np.asarray(g)
+    one = x.ndim == 1
+    X = x.reshape(1, -1) if one else x
+    Gc = g.reshape(1, -1) if one else g
+    batch, N = X.shape
+    bs = [np.asarray(Wk).shape[0] for Wk in Ws]
+    assert N == int(np.prod(bs))
+    Wc = [np.asarray(Wk, dtype=np.complex128) for Wk in Ws]
+
+    def view(a, k):
+        hi = int(np.prod(bs[:k])) if k else 1
+        lo = int(np.prod(bs[k + 1:])) if k + 1 < len(bs) else 1
+        return a.reshape(batch, hi, bs[k], lo)
+
+    acts = []
+    a = X.astype(np.complex128)
+    for k in range(len(Ws)):
+        acts.append(a.copy())
+        a = np.einsum("ij,zajk->zaik", Wc[k], view(a, k)).reshape(batch, N)
+    gWs = [None] * len(Ws)
+    c = Gc.astype(np.complex128)
+    for k in reversed(range(len(Ws))):
+        c4 = view(c, k)
+        gWs[k] = np.einsum("zaik,zajk->ij", c4, np.conj(view(acts[k], k)))
+        c = np.einsum("ij,zajk->zaik", np.conj(Wc[k]).T, c4).reshape(batch, N)
+    return (c[0] if one else c), gWs
+
+
+def fd_grad_mixed(Ws: Sequence[np.ndarray], x: np.ndarray, g: np.ndarray, h: float = 1e-6):
+    """Central finite differences of L = Re <g, (W_0 kron ... kron W_{m-1}) x>
+    with respect to every real and imaginary component of x and of each W_k,
+    through the dense Kronecker product (shares nothing with `grad_mixed`).
+    Tiny N only.  Returns (gx, [gW_k])."""
+    Ws = [np.asarray(Wk, dtype=np.complex128) for Wk in Ws]
+    x = np.asarray(x, dtype=np.complex128)
+    g = np.asarray(g, dtype=np.complex128)
+
+    def loss(ws, xv):
+        return float(np.real(np.vdot(g, kron_list(ws) @ xv)))
+
+    gx = np.zeros_like(x)
+    for i in range(x.size):
+        for unit in (1.0, 1j):
+            xp = x.copy(); xp[i] += h * unit
+            xm = x.copy(); xm[i] -= h * unit
+            gx[i] += (loss(Ws, xp) - loss(Ws, xm)) / (2 * h) * unit
+    gWs = []
+    for k, Wk in enumerate(Ws):
+        gk = np.zeros_like(Wk)
+        for i in range(Wk.shape[0]):
+            for j in range(Wk.shape[1]):
+                for unit in (1.0, 1j):
+                    wp = [w.copy() for w in Ws]; wp[k][i, j] += h * unit
+                    wm = [w.copy() for w in Ws]; wm[k][i, j] -= h * unit
+                    gk[i, j] += (loss(wp, x) - loss(wm, x)) / (2 * h) * unit
+        gWs.append(gk)
+    return gx, gWs
 
 
 # ---------------------------------------------------------------------------

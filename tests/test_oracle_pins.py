@@ -335,3 +335,46 @@ def test_mixed_radix_matches_kron_of_distinct_factors():
     W = haar_unitary(3, 9)
     x81 = gaussian((2, 81), seed=6, complex_=True)
     np.testing.assert_allclose(O.staged_mixed([W] * 4, x81), O.staged(W, x81, 4), atol=1e-13)
+
+
+def test_grad_mixed_vs_finite_differences_and_autograd():
+    # distinct factors, non-unitary, complex: finite differences through the
+    # dense Kronecker product of the factors
+    rng = np.random.default_rng(81)
+    bs = [2, 3, 4]
+    Ws = [rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b)) for b in bs]
+    N = int(np.prod(bs))
+    x = gaussian(N, seed=82, complex_=True)
+    g = gaussian(N, seed=83, complex_=True)
+    gx, gWs = O.grad_mixed(Ws, x, g)
+    fx, fWs = O.fd_grad_mixed(Ws, x, g)
+    assert np.linalg.norm(gx - fx) / np.linalg.norm(fx) < 1e-7
+    for gk, fk in zip(gWs, fWs):
+        assert np.linalg.norm(gk - fk) / np.linalg.norm(fk) < 1e-7
+    # torch autograd on a dense kron graph (CPU, complex128), batch of 2
+    torch = pytest.importorskip("torch")
+    X = gaussian((2, N), seed=84, complex_=True)
+    Gg = gaussian((2, N), seed=85, complex_=True)
+    Wt = [torch.tensor(W, dtype=torch.complex128, requires_grad=True) for W in Ws]
+    Xt = torch.tensor(X, dtype=torch.complex128, requires_grad=True)
+    K = Wt[0]
+    for W in Wt[1:]:
+        K = torch.kron(K, W)
+    y = Xt @ K.transpose(0, 1)
+    L = torch.real(torch.sum(torch.conj(torch.tensor(Gg)) * y))
+    L.backward()
+    gx2, gWs2 = O.grad_mixed(Ws, X, Gg)
+    np.testing.assert_allclose(Xt.grad.numpy(), gx2, atol=1e-12)
+    for Wk, gk in zip(Wt, gWs2):
+        np.testing.assert_allclose(Wk.grad.numpy(), gk, atol=1e-12)
+
+
+def test_grad_mixed_with_identical_factors_sums_to_uniform_grad():
+    # all factors equal: the uniform gradient is the sum of the per-factor ones
+    W = haar_unitary(3, 91)
+    x = gaussian((2, 81), seed=92, complex_=True)
+    g = gaussian((2, 81), seed=93, complex_=True)
+    gx, gWs = O.grad_mixed([W] * 4, x, g)
+    ux, uW = O.grad(W, x, g, 4)
+    np.testing.assert_allclose(gx, ux, atol=1e-12)
+    np.testing.assert_allclose(sum(gWs), uW, atol=1e-11)
