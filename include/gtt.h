@@ -24,9 +24,8 @@
  *  - Complex data is interleaved (re, im), as in torch.complex64/complex128.
  *  - Pointers named x, y, W, gy, gx, gW, saved and ws are DEVICE pointers
  *    owned by the caller; the library never frees them.  Forward / inverse
- *    / backward allocate no device memory, with one exception: the first
- *    call on a ragged plan uploads its work list into device memory that
- *    lives until gtt_plan_destroy (make one call before capturing a graph).
+ *    / backward allocate no device memory (a ragged plan's work list is
+ *    uploaded by gtt_plan; see there).
  *  - All device work is enqueued on `stream` (a hipStream_t; NULL is the
  *    null stream).  Calls return as soon as the work is enqueued.
  *  - Argument checks run on the host, before any HIP call, and report a
@@ -61,7 +60,9 @@ typedef enum gtt_status {
     GTT_ERR_WORKSPACE = 5,     /* ws_bytes smaller than the call needs */
     GTT_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement */
     GTT_ERR_HIP = 7,           /* a HIP runtime call or kernel launch failed */
-    GTT_ERR_INTERNAL = 8
+    GTT_ERR_INTERNAL = 8,
+    GTT_ERR_TIMEOUT = 9        /* a persistent ragged launch gave up waiting at a
+                                  grid barrier (reported by gtt_plan_check) */
 } gtt_status;
 
 typedef enum gtt_dtype {
@@ -121,13 +122,20 @@ typedef struct gtt_plan_s* gtt_plan_t;
  * count > 1).  On error *out is set to NULL.
  * The plan holds host memory and, for ragged batches, a device work list
  * (one descriptor per instance and digit group, one entry per tile) and the
- * grid-barrier words, created and uploaded by the first forward / inverse
- * call on the current device (synchronously: do not make that first call
- * inside a graph capture) and freed by gtt_plan_destroy.  Without
- * GTT_FLAG_PERSISTENT a ragged call launches, in order on the caller's
- * stream, one kernel per phase and tile class.  Calls with
- * GTT_FLAG_PERSISTENT share the plan's barrier words: do not run one such
- * plan on two streams at once.
+ * grid-barrier words.  gtt_plan builds the list and uploads it, synchronously,
+ * to the device current at that time; calls on the plan must run with that
+ * device current (GTT_ERR_INVALID_VALUE otherwise), and every forward /
+ * inverse call, the first included, allocates nothing and can be captured
+ * into a graph.  (Only when no device is visible to the process at plan
+ * time is the upload deferred to the plan's first forward / inverse call.)
+ * gtt_plan_destroy frees the list.  Without GTT_FLAG_PERSISTENT a ragged call
+ * launches, in order on the caller's stream, one kernel per phase and tile
+ * class.  With GTT_FLAG_PERSISTENT a call launches a one-thread reset of the
+ * barrier words and then ONE kernel whose grid (occupancy x compute units)
+ * waits at a grid barrier between digit groups; the wait is bounded (see
+ * gtt_plan_barrier_limit) and a failed wait is reported by gtt_plan_check.
+ * Calls with GTT_FLAG_PERSISTENT share the plan's barrier words: do not run
+ * one such plan on two streams at once.
  */
 gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int32_t* n,
                     int64_t batch, const int64_t* x_off, const int32_t* w_idx,
@@ -142,7 +150,8 @@ gtt_status gtt_plan(gtt_plan_t* out, int32_t count, const int32_t* b, const int3
  * whose place value is b_{k+1} b_{k+2} ... b_{m-1}.  W is passed to forward /
  * inverse as the matrices W_0, W_1, ..., W_{m-1} back to back (compute
  * dtype, row-major).  `batch` contiguous instances of N elements.
- * gtt_backward and gtt_filter return GTT_ERR_UNSUPPORTED for mixed plans.
+ * gtt_backward returns gW in the same layout (the gradient of every factor);
+ * gtt_filter returns GTT_ERR_UNSUPPORTED for mixed plans.
  */
 gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, int64_t batch,
                           gtt_dtype dtype, uint32_t flags);
@@ -184,12 +193,14 @@ gtt_status gtt_inverse(gtt_plan_t p, const void* W, const void* y, void* x,
  *     gx = G_N^H gy;
  *     gW = sum over digits s, instances and fibres of digit s of c_s a_s^H,
  * where a_s is the input of the pass on digit s and c_s the gradient at its
- * output (for real dtypes ^H is ^T).  gW is overwritten (b x b, compute dtype;
- * for ragged plans, the layout of the W table), never accumulated.  gx or gW
+ * output (for real dtypes ^H is ^T).  gW is overwritten (compute dtype; b x b
+ * for uniform plans, the W table's layout for ragged plans, the factors
+ * W_0 .. W_{m-1} back to back for mixed plans), never accumulated; it is
+ * summed in FP64 (complex FP64 for complex data) and rounded once.  gx or gW
  * may be NULL to skip them (not both).  `saved` (nullable) is the buffer
  * filled by gtt_forward for the same x and W; without it the activations are
- * recomputed in the workspace.  Floating dtypes only (GTT_ERR_UNSUPPORTED for
- * GTT_I32 and for mixed plans).
+ * recomputed in the workspace.  Floating dtypes and radices up to 32 (every
+ * factor of a mixed plan); GTT_ERR_UNSUPPORTED for GTT_I32 and larger radices.
  */
 gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* saved,
                         const void* gy, void* gx, void* gW, void* ws, size_t ws_bytes,
@@ -218,6 +229,25 @@ gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff
  */
 gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, int64_t k, int64_t* idx, void* val,
                         void* recon, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gtt_plan_check -- waits for the work enqueued on `stream`, then reports
+ * whether a persistent ragged launch of this plan gave up waiting at a grid
+ * barrier since the last check (GTT_ERR_TIMEOUT; its outputs are incomplete)
+ * and clears that record.  GTT_OK for plans without persistent launches.
+ * Synchronous; not for use inside a graph capture.
+ */
+gtt_status gtt_plan_check(gtt_plan_t p, void* stream);
+
+/*
+ * gtt_plan_barrier_limit -- polls (each followed by a short sleep) that a
+ * work-group of a persistent ragged launch makes at a grid barrier before it
+ * gives up (default 2^24, several seconds).  A work-group that gives up
+ * raises the launch's failure word; every work-group leaves the kernel at its
+ * next barrier, and gtt_plan_check reports GTT_ERR_TIMEOUT.
+ * GTT_ERR_INVALID_VALUE for plans that are not ragged.
+ */
+gtt_status gtt_plan_barrier_limit(gtt_plan_t p, uint32_t polls);
 
 /* Frees the plan and its device work list.  NULL is accepted. */
 gtt_status gtt_plan_destroy(gtt_plan_t p);

@@ -35,8 +35,18 @@ def sources():
     return out
 
 
-def _compile(src: str) -> tuple[str, str]:
+def _newest_header() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    hs.append(os.path.join(INCLUDE, "gtt.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, incremental: bool = False) -> tuple[str, str]:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(src) and t > _newest_header():
+            return obj, ""
     cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", src, "-o", obj]
@@ -47,13 +57,15 @@ def _compile(src: str) -> tuple[str, str]:
     return obj, msg
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object
+    or than any header) and link libgtt.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, msg in ex.map(_compile, srcs):
+        for obj, msg in ex.map(lambda f: _compile(f, incremental), srcs):
             objs.append(obj)
             if verbose and msg.strip():
                 print(msg)
@@ -70,5 +82,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only sources newer than their objects (headers: all)")
     args = ap.parse_args()
-    print(build(args.jobs, args.verbose))
+    print(build(args.jobs, args.verbose, args.incremental))

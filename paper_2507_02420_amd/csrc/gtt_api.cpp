@@ -259,6 +259,74 @@ static void make_fast(Group* g, size_t csize, bool bwd) {
     g->lds_bytes = (size_t)lds_tile_elems_host(g->tileE, m.pad) * csize;
 }
 
+// Tile and checkpoint schedule of a backward group on the general kernel.
+// Candidate tiles hold G * 2^i elements (at most 40 KiB, or one group's
+// positions); a work-group's LDS holds as many tiles as fit in 80 KiB (two
+// work-groups per compute unit) or 160 KiB, at most k + 1 (then every
+// activation of the group is computed once).  Preference: HBM rows of at
+// least 32 bytes for strided groups (where any tile allows), then the fewest
+// LDS passes per tile, then the smaller LDS budget, then the larger tile.
+static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, int k, int64_t total, gtt_dtype dt,
+                             int kind, int64_t cmin, bool shared_w) {
+    const size_t es = storage_size(dt), cs = compute_size(dt);
+    int maxb = 0;
+    int64_t wloc = 0, G = 1;
+    for (int j = 0; j < k; ++j) {
+        maxb = std::max(maxb, rad[s0 + j]);
+        wloc += (int64_t)rad[s0 + j] * rad[s0 + j];
+        G *= rad[s0 + j];
+    }
+    if (shared_w) wloc = (int64_t)rad[s0] * rad[s0];
+    const bool radix_ok = maxb <= 32 && wloc <= 4096 && k <= kMaxDigits;
+    const size_t over = radix_ok ? bwd_overhead_bytes((int)wloc, dt) : 0;
+    const int64_t Tmax = std::max<int64_t>(G, (int64_t)(40 * 1024) / (int64_t)cs);
+    bool found = false;
+    Group best;
+    int best_passes = 0, best_slots = 0;
+    int64_t best_row = 0;
+    size_t best_cap = 0;
+    for (size_t cap : {(size_t)80 * 1024, (size_t)160 * 1024}) {
+        for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
+            Group c;
+            fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
+            const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
+            if (over + 3 * tb > cap) break;  // tiles only grow with T
+            const int slots = (int)std::min<size_t>((cap - over) / tb, (size_t)std::min(k + 1, kMaxBwdSlots));
+            const int passes = bwd_fwd_passes(k, slots - 2) + 2 * k;
+            const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, 32);
+            bool better = !found;
+            if (!better) {
+                if (row != best_row) better = row > best_row;
+                else if (passes != best_passes) better = passes < best_passes;
+                else if (cap != best_cap) better = cap < best_cap;
+                else better = c.tileE > best.tileE;
+            }
+            if (better) {
+                found = true;
+                best = c;
+                best_passes = passes;
+                best_slots = slots;
+                best_row = row;
+                best_cap = cap;
+            }
+        }
+    }
+    if (!found) {
+        // no backward for this group: keep the forward geometry for the
+        // plan's description
+        fill_group(out, rad, s0, k, total, Tmax, es, cs, kind, cmin);
+        out->bwd_ok = false;
+        out->bwd_maxb = maxb;
+        return;
+    }
+    *out = best;
+    out->bwd_ok = true;
+    out->bwd_slots = best_slots;
+    out->bwd_maxb = maxb;
+    out->bwd_wloc = (int)wloc;
+    out->bwd_ops = bwd_schedule(k, best_slots);
+}
+
 // Plan the digit groups for one radix list.
 gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags,
                        bool uniform, std::vector<Group>* groups, std::vector<Group>* bwd_groups, bool ragged) {
@@ -311,19 +379,24 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                 }
                 for (Group& g : *groups) make_fast(&g, cs, false);
                 if (bwd_groups) {
-                    // backward: same digit groups, tiles of at most 40 KiB; the
-                    // matrix-core backward handles up to 4 digits on vector
-                    // tiles of at most 8192 elements, others take the
-                    // runtime-radix backward
+                    // backward: same digit groups.  Complex radix 8 takes the
+                    // matrix-core backward (up to 4 digits on vector tiles of
+                    // at most 8192 elements); every other group the general
+                    // backward, on tiles chosen for its checkpoint schedule
                     bwd_groups->clear();
                     for (const Group& fg : *groups) {
                         Group g;
-                        const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
-                        fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
-                        if (g.kind == kKindCMfma &&
-                            (g.k > 4 || g.tileE > 8192 || (g.mode != kContigVec && g.mode != kRowVec)))
-                            g.kind = kKindValu;
-                        make_fast(&g, cs, true);
+                        if (kind == kKindCMfma) {
+                            const int64_t Tb = (int64_t)(40 * 1024) / (int64_t)cs;
+                            fill_group(&g, rad, fg.s0, fg.k, total, Tb, es, cs, kind, cmin);
+                            if (g.k <= 4 && g.tileE <= 8192 && (g.mode == kContigVec || g.mode == kRowVec)) {
+                                make_fast(&g, cs, true);
+                                bwd_groups->push_back(g);
+                                continue;
+                            }
+                        }
+                        plan_bwd_general(&g, rad, fg.s0, fg.k, total, dt, kind == kKindCMfma ? kKindValu : kind,
+                                         cmin, uniform);
                         bwd_groups->push_back(g);
                     }
                 }
@@ -419,6 +492,11 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
 }
 
 namespace gtt {
+gtt_status launch_group_rw(gtt_plan_s* tp, gtt_dtype dt, const Group& g, const std::vector<int>& rad,
+                           const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint, const void* in,
+                           void* out, hipStream_t s) {
+    return launch_group(tp, dt, g, rad, wofs, N, W, adjoint, in, out, s);
+}
 gtt_status launch_group_inst(gtt_plan_s* tp, gtt_dtype dt, const Group& g, int b, int64_t N, const void* W,
                              bool adjoint, const void* in, void* out, hipStream_t s) {
     std::vector<int> rad(g.s0 + g.k, b);
@@ -467,6 +545,7 @@ const char* gtt_status_string(gtt_status s) {
         case GTT_ERR_UNSUPPORTED: return "GTT_ERR_UNSUPPORTED";
         case GTT_ERR_HIP: return "GTT_ERR_HIP";
         case GTT_ERR_INTERNAL: return "GTT_ERR_INTERNAL";
+        case GTT_ERR_TIMEOUT: return "GTT_ERR_TIMEOUT";
     }
     return "GTT_ERR_UNKNOWN";
 }
@@ -620,7 +699,7 @@ gtt_status gtt_plan_mixed(gtt_plan_t* out, int32_t m, const int32_t* radices, in
         p->rad[d] = radices[m - 1 - d];
         p->wofs[d] = fofs[m - 1 - d];
     }
-    gtt_status st = plan_groups(p->rad, batch, dtype, flags, false, &p->groups, nullptr);
+    gtt_status st = plan_groups(p->rad, batch, dtype, flags, false, &p->groups, &p->bwd_groups);
     if (st != GTT_OK) {
         delete p;
         return st;
@@ -635,6 +714,17 @@ gtt_status gtt_plan_destroy(gtt_plan_t p) {
     destroy_ragged(p);
     delete p;
     return GTT_OK;
+}
+
+gtt_status gtt_plan_check(gtt_plan_t p, void* stream) {
+    if (!p) return GTT_ERR_INVALID_VALUE;
+    if (p->kind != PlanKind::Ragged) return GTT_OK;
+    return ragged_check(p, static_cast<hipStream_t>(stream));
+}
+
+gtt_status gtt_plan_barrier_limit(gtt_plan_t p, uint32_t polls) {
+    if (!p || p->kind != PlanKind::Ragged) return GTT_ERR_INVALID_VALUE;
+    return ragged_set_spin_limit(p, polls);
 }
 
 gtt_status gtt_workspace_size(gtt_plan_t p, size_t* fwd, size_t* bwd, size_t* saved) {
@@ -754,7 +844,8 @@ gtt_status gtt_selftest(void) {
                 if (plan_groups(rad, 3, dt, GTT_FLAG_NO_TUNE, true, &gs, &bgs) != GTT_OK) return GTT_ERR_INTERNAL;
                 if (bgs.size() != gs.size()) return GTT_ERR_INTERNAL;
                 for (size_t i = 0; i < gs.size(); ++i)
-                    if (bgs[i].s0 != gs[i].s0 || bgs[i].k != gs[i].k || bwd_lds_bytes(bgs[i], compute_size(dt), b) > 160 * 1024)
+                    if (bgs[i].s0 != gs[i].s0 || bgs[i].k != gs[i].k ||
+                        (bgs[i].bwd_ok && bwd_lds_bytes(bgs[i], dt) > 160 * 1024) || (b <= 32 && !bgs[i].bwd_ok))
                         return GTT_ERR_INTERNAL;
                 int s = 0;
                 for (const Group& g : gs) {
@@ -782,7 +873,7 @@ gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* 
     if (!aligned16(W) || !aligned16(x) || !aligned16(gy) || (gx && !aligned16(gx)) || (gW && !aligned16(gW)) ||
         (saved && !aligned16(saved)) || (ws && !aligned16(ws)))
         return GTT_ERR_ALIGNMENT;
-    if (p->dtype == GTT_I32 || p->kind == PlanKind::Mixed) return GTT_ERR_UNSUPPORTED;
+    if (p->dtype == GTT_I32) return GTT_ERR_UNSUPPORTED;
     if (p->inner) return f32_backward(p, W, x, saved, gy, gx, gW, ws, ws_bytes, static_cast<hipStream_t>(stream));
     return backward_impl(p, W, x, saved, gy, gx, gW, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }

@@ -15,6 +15,12 @@ namespace gtt {
 
 constexpr int kMaxDigits = 32;
 constexpr int kThreads = 256;  // work-group size of every pass kernel
+// first-stage vectors of the gW reduction (room for them follows the
+// partial vectors in the workspace)
+constexpr int kReduceBlocks = 64;
+// general backward: schedule operations and LDS tiles of a work-group
+constexpr int kMaxBwdOps = 192;
+constexpr int kMaxBwdSlots = 16;
 
 // q = floor(n / d) for 0 <= n < 2^31 via one multiply-high (Granlund and
 // Montgomery's division by invariant integers): m = floor(2^32 (2^s - d) / d) + 1,
@@ -71,7 +77,7 @@ struct PassArgs {
 struct CBwdArgs {
     PassArgs p;          // tile geometry; p.in = a_in, p.out = c_in, p.W = W
     const void* c_out;   // cotangent at the group's output
-    void* partials;      // [gridDim.x][64] complex float
+    void* partials;      // [gridDim.x][64] complex double
 };
 
 }  // namespace gtt

@@ -288,10 +288,10 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_kernel(CBwdArgs
             for (int w = 0; w < kBwdThreads / 64; ++w) s += red[w * 256 + mm * 16 + nn];
             return s;
         };
-        cf g;
-        g.re = (float)(Mv(2 * r, 2 * q) + Mv(2 * r + 1, 2 * q + 1));
-        g.im = (float)(Mv(2 * r + 1, 2 * q) - Mv(2 * r, 2 * q + 1));
-        static_cast<cf*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
+        cd g;
+        g.re = Mv(2 * r, 2 * q) + Mv(2 * r + 1, 2 * q + 1);
+        g.im = Mv(2 * r + 1, 2 * q) - Mv(2 * r, 2 * q + 1);
+        static_cast<cd*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
     }
 }
 
@@ -902,10 +902,10 @@ __global__ __launch_bounds__(kBwdThreads) void gtt_c64_mfma8_bwd_fast_kernel(CBw
             for (int w = 0; w < kBwdThreads / 64; ++w) s += red[w * 256 + mm * 16 + nn];
             return s;
         };
-        cf g;
-        g.re = (float)(Mv(r, q) + Mv(8 + r, 8 + q));
-        g.im = (float)(Mv(8 + r, q) - Mv(r, 8 + q));
-        static_cast<cf*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
+        cd g;
+        g.re = Mv(r, q) + Mv(8 + r, 8 + q);
+        g.im = Mv(8 + r, q) - Mv(r, 8 + q);
+        static_cast<cd*>(ba.partials)[(size_t)blockIdx.x * 64 + threadIdx.x] = g;
     }
 }
 

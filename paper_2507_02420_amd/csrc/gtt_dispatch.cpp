@@ -11,12 +11,12 @@ hipError_t launch_pass_bf16(int, int, const PassArgs&, unsigned, size_t, hipStre
 hipError_t launch_pass_f16(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 hipError_t launch_pass_i32(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 
-hipError_t launch_bwd_f64(const BwdArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_f32(const BwdArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_c128(const BwdArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_c64(const BwdArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_bf16(const BwdArgs&, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_f16(const BwdArgs&, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f64(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f32(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c128(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c64(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_bf16(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f16(const BwdArgs&, int, unsigned, size_t, hipStream_t);
 hipError_t launch_reduce_f64(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_f32(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_c128(const void*, int64_t, int, void*, hipStream_t);
@@ -24,14 +24,14 @@ hipError_t launch_reduce_c64(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_bf16(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_f16(const void*, int64_t, int, void*, hipStream_t);
 
-hipError_t launch_bwd(DT dt, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s) {
     switch (dt) {
-        case DT::F64: return launch_bwd_f64(a, grid, lds, s);
-        case DT::F32: return launch_bwd_f32(a, grid, lds, s);
-        case DT::C128: return launch_bwd_c128(a, grid, lds, s);
-        case DT::C64: return launch_bwd_c64(a, grid, lds, s);
-        case DT::BF16: return launch_bwd_bf16(a, grid, lds, s);
-        case DT::F16: return launch_bwd_f16(a, grid, lds, s);
+        case DT::F64: return launch_bwd_f64(a, maxb, grid, lds, s);
+        case DT::F32: return launch_bwd_f32(a, maxb, grid, lds, s);
+        case DT::C128: return launch_bwd_c128(a, maxb, grid, lds, s);
+        case DT::C64: return launch_bwd_c64(a, maxb, grid, lds, s);
+        case DT::BF16: return launch_bwd_bf16(a, maxb, grid, lds, s);
+        case DT::F16: return launch_bwd_f16(a, maxb, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -64,10 +64,15 @@ constexpr int kKindCMfma = 3;    // complex64, radix 8, FP32 matrix cores
 hipError_t launch_pass(DT dt, int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 struct BwdArgs;
-// backward of one digit group (runtime radix <= 16, floating dtypes)
-hipError_t launch_bwd(DT dt, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
-// gW = fixed-order sum of nparts partial vectors of bb compute-dtype values
+// backward of one digit group (runtime radices <= maxb <= 32, floating dtypes)
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s);
+// gW = fixed-order sum of nparts partial vectors of bb accumulation-dtype
+// values (FP64 / complex FP64), written in the compute dtype
 hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s);
+// bytes zeros at p (a kernel, not a memset node: safe under graph capture)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// fresh grid-barrier words before a persistent ragged launch
+hipError_t launch_barrier_reset(unsigned* bar, hipStream_t s);
 
 struct CBwdArgs;
 // backward of one digit group, complex64 radix 8 on the matrix cores

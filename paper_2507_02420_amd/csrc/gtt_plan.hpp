@@ -38,6 +38,14 @@ struct Group {
     uint64_t fmap = 0;   // its fibre-to-lane maps (PassArgs::fmap)
     uint32_t pmap = 0;   // pass-only maps of a paired backward layout (PassArgs::pmap)
     int fast_conflicts = 0;  // residual LDS bank conflicts of that layout (model)
+    // backward groups on the general kernel (every kind but the complex
+    // radix-8 matrix-core one): LDS tiles per work-group, the checkpoint
+    // schedule run on them, the largest radix and the staged matrix entries
+    int bwd_slots = 0;
+    int bwd_maxb = 0;
+    int bwd_wloc = 0;
+    bool bwd_ok = true;  // false: this build has no backward for the group
+    std::vector<uint16_t> bwd_ops;
 };
 
 // LDS layout of the per-lane-address radix-8 kernels for K digits, tiles of
@@ -123,22 +131,43 @@ size_t storage_size(gtt_dtype d);
 size_t compute_size(gtt_dtype d);
 gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt, uint32_t flags, bool uniform,
                        std::vector<Group>* groups, std::vector<Group>* bwd_groups, bool ragged = false);
-size_t bwd_lds_bytes(const Group& g, size_t csize, int b);
-size_t bwd_partials_elems(const std::vector<Group>& bg, int b);
+// accumulation dtype of the weight gradient: FP64, complex FP64 for complex data
+size_t acc_size(gtt_dtype d);
+size_t bwd_lds_bytes(const Group& g, gtt_dtype dt);
+// LDS bytes of the general backward besides its tiles
+size_t bwd_overhead_bytes(int wloc, gtt_dtype dt);
+// forward passes of the optimal checkpoint schedule (k digits, `free_slots`
+// activation slots besides the group input and the cotangent)
+int bwd_fwd_passes(int k, int free_slots);
+// the schedule itself (operations as in gtt_bwd.hpp)
+std::vector<uint16_t> bwd_schedule(int k, int nslots);
+// partial-vector entries of every backward launch of a group list (wslot
+// entries per work-group)
+size_t bwd_partials_elems(const std::vector<Group>& bg, int wslot);
 
 gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int32_t* n, const int64_t* x_off,
                        const int32_t* w_idx);
 void destroy_ragged(gtt_plan_s* p);
+// waits for `s`, then reports and clears a grid-barrier failure of the
+// plan's persistent launches (GTT_ERR_TIMEOUT)
+gtt_status ragged_check(gtt_plan_s* p, hipStream_t s);
+gtt_status ragged_set_spin_limit(gtt_plan_s* p, uint32_t polls);
 gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out, bool adjoint, char* saved,
                         hipStream_t s);
 void workspace_sizes(const gtt_plan_s* p, size_t* fwd, size_t* bwd, size_t* saved);
 size_t bwd_partial_bytes(const gtt_plan_s* p);
+// every digit group of the plan has a backward kernel (floating dtypes,
+// radices <= 32, LDS)
+bool plan_has_backward(const gtt_plan_s* p);
 std::string describe_plan(const gtt_plan_s* p);
 // bracket a launch with events when timing is enabled (no-ops otherwise)
 void timing_begin(gtt_plan_s* p, hipStream_t s);
 void timing_end(gtt_plan_s* p, hipStream_t s, const std::string& name, double bytes);
 void timing_release(gtt_plan_s* p);
 std::string timing_read(gtt_plan_s* p);
+gtt_status launch_group_rw(gtt_plan_s* tp, gtt_dtype dt, const Group& g, const std::vector<int>& rad,
+                           const std::vector<int64_t>& wofs, int64_t N, const void* W, bool adjoint, const void* in,
+                           void* out, hipStream_t s);
 gtt_status launch_group_inst(gtt_plan_s* tp, gtt_dtype dt, const Group& g, int b, int64_t N, const void* W,
                              bool adjoint, const void* in, void* out, hipStream_t s);
 gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void* saved, const void* gy, void* gx,

@@ -17,8 +17,9 @@ namespace gtt {
 void fill_pass_args(PassArgs* a, const Group& g, const std::vector<int>& rad, const std::vector<int64_t>& wofs,
                     int64_t N);
 
-// Device work list of a ragged plan (built on the host at plan time, uploaded
-// on the first call that needs it).
+// Device work list of a ragged plan: built on the host and uploaded at plan
+// time to the device current then (when no device is visible at plan time,
+// on the first call instead).
 struct RaggedState {
     std::vector<RaggedDesc> desc;
     std::vector<RaggedItem> items;
@@ -39,6 +40,8 @@ struct RaggedState {
     unsigned* d_bar = nullptr;
     int grid_persistent = 0;
     int cus = 0;
+    int device = -1;                   // device holding the work list
+    uint32_t spin_limit = 1u << 24;    // polls of a grid-barrier wait
 };
 
 static void build_worklist(gtt_plan_s* p) {
@@ -133,6 +136,8 @@ static gtt_status upload_worklist(gtt_plan_s* p) {
     RaggedState* rs = p->rs;
     if (rs->uploaded) return GTT_OK;
     const DT dt = static_cast<DT>((int)p->dtype);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GTT_ERR_HIP;
     if (hipMalloc(&rs->d_desc, rs->desc.size() * sizeof(RaggedDesc)) != hipSuccess) return GTT_ERR_HIP;
     if (hipMalloc(&rs->d_items, std::max<size_t>(1, rs->items.size()) * sizeof(RaggedItem)) != hipSuccess)
         return GTT_ERR_HIP;
@@ -145,16 +150,22 @@ static gtt_status upload_worklist(gtt_plan_s* p) {
             hipSuccess)
         return GTT_ERR_HIP;
     if (hipMemset(rs->d_bar, 0, 4 * sizeof(unsigned)) != hipSuccess) return GTT_ERR_HIP;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return GTT_ERR_HIP;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GTT_ERR_HIP;
     rs->cus = prop.multiProcessorCount;
     int per_cu = 0;
     if (ragged_occupancy(dt, rs->lds_max, &per_cu) != hipSuccess || per_cu < 1) return GTT_ERR_HIP;
     rs->grid_persistent = per_cu * rs->cus;
+    rs->device = dev;
     rs->uploaded = true;
     return GTT_OK;
+}
+
+// a device is visible to this process (no HIP context is created on a
+// machine without one)
+static bool device_present() {
+    int n = 0;
+    return hipGetDeviceCount(&n) == hipSuccess && n > 0;
 }
 
 gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int32_t* n, const int64_t* x_off,
@@ -235,6 +246,29 @@ gtt_status plan_ragged(gtt_plan_s* p, int32_t count, const int32_t* b, const int
     for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
     if (maxR > kMaxPhases) return GTT_ERR_UNSUPPORTED;
     build_worklist(p);
+    // the work list goes to the device now, so that forward / inverse
+    // allocate nothing and can be captured from the first call
+    if (device_present()) return upload_worklist(p);
+    return GTT_OK;
+}
+
+gtt_status ragged_check(gtt_plan_s* p, hipStream_t s) {
+    RaggedState* rs = p->rs;
+    if (!rs || !rs->uploaded) return GTT_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return GTT_ERR_HIP;
+    unsigned w[4] = {0, 0, 0, 0};
+    if (hipMemcpy(w, rs->d_bar, sizeof w, hipMemcpyDeviceToHost) != hipSuccess) return GTT_ERR_HIP;
+    if (w[2] == 0 && w[3] == 0) return GTT_OK;
+    // clear the failure words (the arrival and generation words are reset
+    // before every persistent launch)
+    const unsigned z[2] = {0, 0};
+    if (hipMemcpy(rs->d_bar + 2, z, sizeof z, hipMemcpyHostToDevice) != hipSuccess) return GTT_ERR_HIP;
+    return GTT_ERR_TIMEOUT;
+}
+
+gtt_status ragged_set_spin_limit(gtt_plan_s* p, uint32_t polls) {
+    if (!p->rs) return GTT_ERR_INVALID_VALUE;
+    p->rs->spin_limit = polls;
     return GTT_OK;
 }
 
@@ -261,6 +295,9 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
     if (p->flags & GTT_FLAG_PER_INSTANCE) return ragged_per_instance(p, W, in, out, adjoint, saved, s);
     gtt_status st = upload_worklist(p);
     if (st != GTT_OK) return st;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return GTT_ERR_HIP;
+    if (dev != p->rs->device) return GTT_ERR_INVALID_VALUE;  // the work list lives on another device
     RaggedState* rs = p->rs;
     const DT dt = static_cast<DT>((int)p->dtype);
     RaggedArgs a;
@@ -275,12 +312,14 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
     a.saved = adjoint ? nullptr : saved;
     a.W = W;
     a.bar = rs->d_bar;
+    a.spin_limit = rs->spin_limit;
     static const char* dn[] = {"f64", "f32", "c128", "c64", "bf16", "f16", "i32"};
     if (p->flags & GTT_FLAG_PERSISTENT) {
         int64_t most = 0;
         for (int i = 0; i < a.nphases; ++i) most = std::max(most, rs->phase_start[i + 1] - rs->phase_start[i]);
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rs->grid_persistent, most));
         a.persistent = 1;
+        if (launch_barrier_reset(rs->d_bar, s) != hipSuccess) return GTT_ERR_HIP;
         timing_begin(p, s);
         if (launch_ragged(dt, a, grid, rs->lds_max, s) != hipSuccess) return GTT_ERR_HIP;
         timing_end(p, s, std::string("ragged persistent ") + dn[(int)p->dtype],
@@ -341,15 +380,17 @@ static int max_groups(const gtt_plan_s* p) {
 }
 
 size_t bwd_partial_bytes(const gtt_plan_s* p) {
-    // per-work-group partials, plus 64 first-stage reduction vectors after the
-    // partials of each W (radix <= 16: at most 256 values each)
+    // per-work-group partial vectors (accumulation dtype), plus the
+    // reduction's first-stage vectors after the partials of each W
+    const size_t as = acc_size(p->dtype);
     size_t partial = 0;
     if (p->kind == PlanKind::Ragged) {
-        for (const Instance& t : p->inst) partial += bwd_partials_elems(t.bwd_groups, t.b) * p->csize;
-        partial += p->w_b.size() * 64 * 256 * p->csize;
-    } else if (p->kind == PlanKind::Uniform) {
-        partial += bwd_partials_elems(p->bwd_groups, p->b) * p->csize;
-        partial += 64 * (size_t)p->b * p->b * p->csize;
+        for (const Instance& t : p->inst) partial += bwd_partials_elems(t.bwd_groups, t.b * t.b) * as;
+        for (int wb : p->w_b) partial += (size_t)kReduceBlocks * wb * wb * as;
+    } else {
+        const int wslot = (int)p->w_elems;
+        partial += bwd_partials_elems(p->bwd_groups, wslot) * as;
+        partial += (size_t)kReduceBlocks * wslot * as;
     }
     return (partial + 255) & ~(size_t)255;
 }
@@ -439,15 +480,20 @@ std::string timing_read(gtt_plan_s* p) {
 
 std::string describe_plan(const gtt_plan_s* p) {
     auto grp = [](const Group& g) {
-        char b[400];
+        char b[512];
         std::snprintf(b, sizeof b,
                       "{\"s0\":%d,\"k\":%d,\"S\":%lld,\"G\":%lld,\"C\":%d,\"P\":%d,\"L\":%lld,\"tiles\":%lld,"
                       "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"kind\":\"%s\",\"lds_bytes\":%zu,"
-                      "\"fast_ni\":%d,\"fmap\":%llu,\"pmap\":%u,\"fast_conflicts\":%d}",
+                      "\"fast_ni\":%d,\"fmap\":%llu,\"pmap\":%u,\"fast_conflicts\":%d,\"bwd_slots\":%d,"
+                      "\"bwd_ops\":%d,\"bwd_fwd_passes\":%d,\"bwd_ok\":%s,\"bwd_schedule\":[",
                       g.s0, g.k, (long long)g.S, (long long)g.G, g.C, g.P, (long long)g.L, (long long)g.ntiles,
                       (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : g.kind == 2 ? "mfma" : "cmfma",
-                      g.lds_bytes, g.fast_ni, (unsigned long long)g.fmap, g.pmap, g.fast_conflicts);
-        return std::string(b);
+                      g.lds_bytes, g.fast_ni, (unsigned long long)g.fmap, g.pmap, g.fast_conflicts, g.bwd_slots,
+                      (int)g.bwd_ops.size(), g.bwd_slots ? bwd_fwd_passes(g.k, g.bwd_slots - 2) : 0,
+                      g.bwd_ok ? "true" : "false");
+        std::string r(b);
+        for (size_t i = 0; i < g.bwd_ops.size(); ++i) r += (i ? "," : "") + std::to_string((int)g.bwd_ops[i]);
+        return r + "]}";
     };
     std::string s = "{";
     char head[256];

@@ -11,13 +11,19 @@
 //
 // Persistent mode runs every phase in ONE launch of the all-class kernel (a
 // work-group takes the items of the current phase round-robin and dispatches
-// on the class) and separates the phases by a grid barrier (the next digit group of an instance needs all tiles of the
-// previous one).  The barrier counts arrivals with a device-scope atomic; the
-// last work-group to arrive resets the count and advances a generation word
-// the others wait on, so the state returns to zero after every barrier and the
-// launch can be replayed from a captured graph.  The grid never exceeds the
-// number of co-resident work-groups, and every wait is bounded: after the spin
-// limit a work-group raises the error word and leaves, so no wave can hang.
+// on the class) and separates the phases by a grid barrier (the next digit
+// group of an instance needs all tiles of the previous one).  The barrier
+// counts arrivals with a device-scope atomic; the last work-group to arrive
+// resets the count and advances a generation word the others wait on, so the
+// state returns to zero after every barrier and the launch can be replayed
+// from a captured graph.  The grid never exceeds the number of co-resident
+// work-groups (occupancy x compute units, not a cooperative launch), and
+// every wait is bounded: after `spin_limit` polls a work-group raises the
+// failure word; every work-group that sees it leaves the kernel at its next
+// barrier (no wave can hang, no phase runs on partial data).  A one-thread
+// kernel before every persistent launch zeroes the arrival and generation
+// words and moves a raised failure word into a sticky record that the host
+// reads and clears with gtt_plan_check.
 #pragma once
 
 #include "gtt_args.hpp"
@@ -62,10 +68,15 @@ struct RaggedArgs {
     void* y;
     void* saved;
     const void* W;
-    unsigned* bar;       // [0] arrivals, [1] generation, [2] error flag
+    unsigned* bar;       // [0] arrivals, [1] generation, [2] failure of this
+                         // launch, [3] sticky failure record
+    uint32_t spin_limit; // polls of a barrier wait before it gives up
 };
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks) {
+// Returns false when the barrier failed (this or another work-group gave up
+// waiting); the caller then leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, uint32_t spin_limit) {
+    __shared__ unsigned failed;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -76,19 +87,23 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks) {
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            // bounded wait: ~2^24 polls with s_sleep is several seconds
+            // bounded wait (the default limit, 2^24 polls with s_sleep, is
+            // several seconds); a failure raised elsewhere ends it at once
+            // (a limit of 0 gives up without polling)
             for (uint32_t spin = 0;; ++spin) {
-                if (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) break;
-                if (spin > (1u << 24)) {
+                if (spin >= spin_limit || __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
+                if (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != gen) break;
                 __builtin_amdgcn_s_sleep(4);
             }
         }
         __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        failed = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
+    return failed == 0;
 }
 
 template <typename C, int B>
@@ -290,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void gtt_ragged_kernel(RaggedArgs r) {
             }
             ragged_item<T, kClsAny>(smem_raw, r, it);
         }
-        if (r.persistent && p + 1 < p1) grid_barrier(r.bar, gridDim.x);
+        if (r.persistent && p + 1 < p1 && !grid_barrier(r.bar, gridDim.x, r.spin_limit)) return;
     }
 }
 

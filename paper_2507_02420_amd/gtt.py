@@ -21,7 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libgtt.so")
 OK = 0
 STATUS_NAMES = {0: "GTT_OK", 1: "GTT_ERR_INVALID_VALUE", 2: "GTT_ERR_SHAPE", 3: "GTT_ERR_DTYPE",
                 4: "GTT_ERR_ALIGNMENT", 5: "GTT_ERR_WORKSPACE", 6: "GTT_ERR_UNSUPPORTED",
-                7: "GTT_ERR_HIP", 8: "GTT_ERR_INTERNAL"}
+                7: "GTT_ERR_HIP", 8: "GTT_ERR_INTERNAL", 9: "GTT_ERR_TIMEOUT"}
+ERR_UNSUPPORTED = 6
+ERR_TIMEOUT = 9
 # gtt_dtype
 F64, F32, C128, C64, BF16, F16, I32 = range(7)
 FLAG_FP32_INTERMEDIATE = 0x1
@@ -40,7 +42,7 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
            "gtt_backward", "gtt_filter", "gtt_compress", "gtt_plan_destroy", "gtt_status_string",
            "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_set_tuning",
-           "gtt_selftest"]
+           "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit"]
 
 
 class GTTError(RuntimeError):
@@ -79,6 +81,8 @@ def lib() -> ctypes.CDLL:
     L.gtt_plan_timing_read.argtypes = [vp, ctypes.c_char_p, sz]
     L.gtt_set_tuning.argtypes = [i32, ctypes.c_int, i32, i32, i32]
     L.gtt_selftest.argtypes = []
+    L.gtt_plan_check.argtypes = [vp, vp]
+    L.gtt_plan_barrier_limit.argtypes = [vp, u32]
     for name in EXPORTS:
         if name != "gtt_status_string":
             getattr(L, name).restype = ctypes.c_int
@@ -211,6 +215,17 @@ class Plan:
         buf = ctypes.create_string_buffer(1 << 16)
         _check(lib().gtt_plan_timing_read(self._h, buf, len(buf)), "gtt_plan_timing_read")
         return json.loads(buf.value.decode())
+
+    def check(self):
+        """Wait for the current stream; raise GTTError(GTT_ERR_TIMEOUT) if a
+        persistent ragged launch of this plan gave up at a grid barrier since
+        the last check (and clear that record)."""
+        _check(lib().gtt_plan_check(self._h, _stream()), "gtt_plan_check")
+
+    def barrier_limit(self, polls: int):
+        """Polls a work-group of a persistent ragged launch makes at a grid
+        barrier before it gives up (default 2**24)."""
+        _check(lib().gtt_plan_barrier_limit(self._h, int(polls)), "gtt_plan_barrier_limit")
 
     # -- calls ---------------------------------------------------------------
     def _ws(self, nbytes: int, device) -> Optional[torch.Tensor]:

@@ -400,3 +400,37 @@ def test_last_stage_direct_store_covers_tile(dtype):
                                 seen.add(lam)
                         assert seen == set(range(tile_e))
     assert checked > 0
+
+
+def test_check_and_barrier_limit_without_a_gpu_call():
+    # uniform plans have no barrier: check is a no-op, the limit is refused;
+    # a ragged plan created without a visible device defers its upload, and
+    # checking it needs no HIP call either
+    L = G.lib()
+    st, h = _plan(1, [4], [5])
+    assert st == 0
+    assert L.gtt_plan_check(h, None) == 0
+    assert L.gtt_plan_barrier_limit(h, 10) == 1
+    assert L.gtt_plan_check(None, None) == 1
+    L.gtt_plan_destroy(h)
+    if not torch.cuda.is_available():
+        st, h = _plan(3, [2, 4, 16], [10, 5, 3], flags=G.FLAG_PERSISTENT)
+        assert st == 0
+        assert L.gtt_plan_barrier_limit(h, 0) == 0
+        assert L.gtt_plan_check(h, None) == 0
+        L.gtt_plan_destroy(h)
+    assert L.gtt_status_string(9).decode() == "GTT_ERR_TIMEOUT"
+
+
+def test_backward_refuses_radix_above_32_before_any_hip_call():
+    L = G.lib()
+    a = ctypes.c_void_p(0x10000)
+    for b, dt in ((33, G.F32), (64, G.C64)):
+        st, h = _plan(1, [b], [2], dtype=dt)
+        assert st == 0
+        assert L.gtt_backward(h, a, a, None, a, a, a, a, 1 << 20, None) == 6
+        L.gtt_plan_destroy(h)
+    # radix 32 has a backward (rejected here only for the missing workspace)
+    st, h = _plan(1, [32], [2], dtype=G.BF16)
+    assert L.gtt_backward(h, a, a, None, a, a, a, None, 0, None) == 5
+    L.gtt_plan_destroy(h)

@@ -34,13 +34,26 @@ def _grad_case(b, n, batch, dtype, seed, use_saved=True):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.complex64, torch.complex128], ids=str)
 @pytest.mark.parametrize("b,n,batch", [(2, 3, 2), (2, 14, 2), (3, 5, 3), (3, 9, 2), (4, 4, 3), (4, 8, 2),
                                        (5, 4, 2), (6, 3, 2), (7, 3, 2), (8, 3, 2), (8, 5, 2), (11, 2, 3),
-                                       (16, 2, 2), (16, 3, 1)])
+                                       (16, 2, 2), (16, 3, 1), (32, 2, 2), (32, 3, 1), (21, 2, 2)])
 def test_backward_matches_oracle(b, n, batch, dtype):
+    # gW is summed in FP64 for every dtype and rounded once: the FP32 / c64
+    # bound holds for gW as for gx
     say(f"backward b={b} n={n} batch={batch} dtype={dtype}")
     gx, gW, rgx, rgW = _grad_case(b, n, batch, dtype, seed=5000 + 31 * b + n)
     tol = TOL[dtype]
     assert rel_err(gx, rgx) < tol
-    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < tol * 10
+    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=str)
+@pytest.mark.parametrize("b,n,batch", [(16, 2, 3), (16, 3, 2), (32, 2, 3), (32, 3, 1), (2, 13, 2), (4, 5, 3)])
+def test_backward_16bit_storage(b, n, batch, dtype):
+    # 16-bit storage: gx is rounded to the storage type (1e-2 bound); gW is
+    # float32 (W's dtype), summed in FP64 from the stored operands
+    say(f"backward 16-bit b={b} n={n} batch={batch} dtype={dtype}")
+    gx, gW, rgx, rgW = _grad_case(b, n, batch, dtype, seed=5200 + b + n)
+    assert rel_err(gx, rgx) < 1e-2
+    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < 1e-2
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.complex64], ids=str)
@@ -49,7 +62,7 @@ def test_backward_without_saved_recomputes(b, n, dtype):
     say(f"backward (no saved) b={b} n={n} dtype={dtype}")
     gx, gW, rgx, rgW = _grad_case(b, n, 2, dtype, seed=6000 + b + n, use_saved=False)
     assert rel_err(gx, rgx) < TOL[dtype]
-    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.complex64], ids=str)
@@ -67,7 +80,7 @@ def test_backward_boundary_slots_of_odd_length(dtype, use_saved):
     finally:
         G.set_tuning(b, dtype, 0, 0, 0)
     assert rel_err(gx, rgx) < TOL[dtype]
-    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+    assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < TOL[dtype]
 
 
 def test_backward_c128_b8_n3_tight():
@@ -97,7 +110,7 @@ def test_backward_only_gw_and_only_gx_and_inplace():
     gx2, gW2 = plan.backward(W, x, g2, gx=g2)     # gx aliases gy
     torch.cuda.synchronize()
     assert rel_err(host64(gx), rgx) < 1e-5
-    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-4
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-5
     assert torch.equal(gx2, gx)
     assert torch.equal(gW2, gW)
 
@@ -117,7 +130,7 @@ def test_backward_gw_only_single_group(b, n, batch, dtype):
     torch.cuda.synchronize()
     assert torch.equal(x, x0) and torch.equal(g, g0)
     _, rgW = O.grad(W64, x64, host64(g), n)
-    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < TOL[dtype]
 
 
 # complex radix-8 shapes covering every (digits, tile) variant of the
@@ -136,7 +149,7 @@ def test_backward_c64_radix8_tiles(n, batch, want_gx):
     rgx, rgW = O.grad(W64, x64, host64(g), n)
     if want_gx:
         assert rel_err(host64(gx), rgx) < TOL[dtype]
-    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 10 * TOL[dtype]
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < TOL[dtype]
 
 
 def test_backward_deterministic():
@@ -152,30 +165,70 @@ def test_backward_deterministic():
 
 def test_full_size_differentiation_workload():
     # 256 x c64, b=8, n=6 (N = 262144): the launch configuration of the
-    # benchmark.  gx is checked on sampled instances; gW by linearity in g:
-    # with g zero outside three instances, gW is the oracle gradient of those
-    # three instances alone.
+    # benchmark.  y and gx on sampled instances against the oracle; gW (one
+    # sum over all 256 instances, ~5e8 outer-product terms) against the
+    # oracle gradient of the whole batch, computed in chunks of instances
+    # (gW is a sum over instances).
     b, n, batch, dtype = 8, 6, 256, torch.complex64
     say("full-size differentiation 256 x 8^6 c64")
     x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=41)
     g = gaussian((batch, b ** n), seed=43, complex_=True).astype(np.complex64)
-    keep = [0, 97, 255]
-    mask = np.zeros(batch, dtype=bool)
-    mask[keep] = True
-    g_sparse = np.where(mask[:, None], g, 0)
     plan = G.Plan(b, n, batch, dtype)
     _, _, sv = plan.workspace_size()
     saved = torch.empty(sv, dtype=torch.uint8, device="cuda")
     y = plan.forward(W, x, saved=saved)
     gt = torch.from_numpy(g).cuda()
-    gx, _ = plan.backward(W, x, gt, saved=saved)
-    _, gW = plan.backward(W, x, torch.from_numpy(g_sparse).cuda(), saved=saved)
+    gx, gW = plan.backward(W, x, gt, saved=saved)
     torch.cuda.synchronize()
     for i in (3, 128, 250):
         assert rel_err(host64(y[i]), O.staged(W64, x64[i], n)) < 1e-5
         assert rel_err(host64(gx[i]), O.adjoint(W64, host64(gt[i]), n)) < 1e-5
-    _, rgW = O.grad(W64, x64[keep], g_sparse[keep].astype(np.complex128), n)
-    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-5
+    rgW = np.zeros((b, b), dtype=np.complex128)
+    g64 = g.astype(np.complex128)
+    for c0 in range(0, batch, 16):
+        _, part = O.grad(W64, x64[c0:c0 + 16], g64[c0:c0 + 16], n)
+        rgW += part
+    err = np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW)
+    say(f"  gW rel err over 256 instances {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64, torch.complex128], ids=str)
+@pytest.mark.parametrize("radices,batch", [([2, 3, 4, 5], 3), ([3, 8, 2, 7, 4], 2), ([16, 2, 9], 2),
+                                           ([32, 4], 3), ([5, 5, 5, 5, 5, 5, 5], 2), ([2] * 14 + [3], 1)])
+def test_mixed_radix_backward(radices, batch, dtype):
+    # distinct factors W_0 kron ... kron W_{m-1}: gx and every factor's
+    # gradient against the oracle (gW comes back in the W table's layout)
+    say(f"mixed backward {radices} batch={batch} dtype={dtype}")
+    cplx = dtype in COMPLEX
+    from paper_2507_02420_amd.inputs import haar_unitary
+    Ws = [haar_unitary(r, 150 + i, complex_=cplx) for i, r in enumerate(radices)]
+    N = int(np.prod(radices))
+    wdt = G.W_DTYPE[dtype]
+    Wt = torch.cat([torch.from_numpy(w).to(wdt).reshape(-1) for w in Ws]).cuda()
+    xt = torch.from_numpy(gaussian((batch, N), seed=160, complex_=cplx)).to(dtype).cuda()
+    gt = torch.from_numpy(gaussian((batch, N), seed=161, complex_=cplx)).to(dtype).cuda()
+    plan = G.Plan.mixed(radices, batch, dtype)
+    _, _, sv = plan.workspace_size()
+    saved = torch.empty(max(sv, 16), dtype=torch.uint8, device="cuda")
+    plan.forward(Wt, xt, saved=saved)
+    gx, gW = plan.backward(Wt, xt, gt, saved=saved)
+    gx2, gW2 = plan.backward(Wt, xt, gt)          # activations recomputed
+    torch.cuda.synchronize()
+    Ws64 = [torch.from_numpy(w).to(wdt).to(torch.complex128).numpy() for w in Ws]
+    rgx, rgWs = O.grad_mixed(Ws64, host64(xt), host64(gt))
+    if not cplx:
+        rgx = rgx.real
+    tol = TOL[dtype]
+    assert rel_err(host64(gx), rgx) < tol
+    got = host64(gW)
+    pos = 0
+    for r, rg in zip(radices, rgWs):
+        blk = got[pos:pos + r * r].reshape(r, r)
+        rg = rg if cplx else rg.real
+        assert np.linalg.norm(blk - rg) / np.linalg.norm(rg) < tol, (r, pos)
+        pos += r * r
+    assert torch.equal(gx2, gx) and torch.equal(gW2, gW)
 
 
 def test_autograd_function_gradcheck():

@@ -96,10 +96,11 @@ def test_n_zero_is_identity(dtype):
     assert torch.equal(y.cpu(), x.cpu())
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64, torch.bfloat16, torch.int32],
-                         ids=str)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64, torch.complex128, torch.bfloat16,
+                                   torch.int32], ids=str)
 def test_signed_permutation_w_is_exact(dtype):
-    # products with 0 and +-1 and sums with exact zeros are exact in every dtype
+    # products with 0 and +-1 and sums with exact zeros are exact in every
+    # dtype; complex data is compared in both components
     b, n, batch = 4, 7, 2
     say(f"signed permutation dtype={dtype}")
     perm = np.array([2, 0, 3, 1])
@@ -109,16 +110,50 @@ def test_signed_permutation_w_is_exact(dtype):
     rng = np.random.default_rng(7)
     if dtype == torch.int32:
         xn = rng.integers(-1000, 1000, size=(batch, b ** n))
+    elif dtype in COMPLEX:
+        xn = rng.standard_normal((batch, b ** n)) + 1j * rng.standard_normal((batch, b ** n))
     else:
         xn = rng.standard_normal((batch, b ** n))
     xt = torch.from_numpy(xn).to(dtype).cuda()
     Wt = torch.from_numpy(Wn).to(G.W_DTYPE[dtype]).cuda()
     y = G.Plan(b, n, batch, dtype).forward(Wt, xt)
     torch.cuda.synchronize()
-    x64 = xt.cpu().to(torch.float64).numpy()
+    wide = torch.complex128 if dtype in COMPLEX else torch.float64
+    x64 = xt.cpu().to(wide).numpy()
     ref = O.staged(Wn, x64, n)
-    got = y.cpu().to(torch.float64).numpy()
-    assert np.array_equal(got, ref)
+    got = y.cpu().to(wide).numpy()
+    if dtype in COMPLEX:
+        assert np.array_equal(got.real, ref.real) and np.array_equal(got.imag, ref.imag)
+        assert np.count_nonzero(ref.imag) > 0
+    else:
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("which", ["hadamard", "orthogonal"])
+def test_single_fp64_vector_b2_n10_against_dense(which):
+    # one f64 vector, N = 2^10, x ~ N(0,1) (seed 11); W the normalised 2 x 2
+    # Hadamard matrix or a 2 x 2 orthogonal matrix from QR of a Gaussian
+    # (seed 12); checked against the dense 1024 x 1024 Kronecker matvec
+    # (Def. 2.4) at 1e-12, and the Hadamard case also against the Sylvester
+    # matrix (the Hadamard reduction of §2.6)
+    from paper_2507_02420_amd.inputs import gaussian, hadamard2, haar_unitary
+    b, n = 2, 10
+    say(f"single f64 vector b=2 n=10 W={which}")
+    Wn = hadamard2(True) if which == "hadamard" else haar_unitary(2, 12, complex_=False)
+    xn = gaussian(b ** n, seed=11)
+    xt = torch.from_numpy(xn).cuda().reshape(1, -1)
+    Wt = torch.from_numpy(Wn).cuda()
+    plan = G.Plan(b, n, 1, torch.float64)
+    y = plan.forward(Wt, xt)
+    back = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    got = host64(y)[0]
+    ref = O.dense(Wn, xn, n)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
+    if which == "hadamard":
+        syl = O.sylvester_hadamard(n) / 2 ** (n / 2)
+        assert np.linalg.norm(got - syl @ xn) / np.linalg.norm(xn) < 1e-12
+    assert np.linalg.norm(host64(back)[0] - xn) / np.linalg.norm(xn) < 1e-12
 
 
 def test_dft_base_matrix_is_fftn_on_gpu():

@@ -70,8 +70,9 @@ def test_backward(b, n, batch, dtype, use_saved):
     rgx, rgW = O.grad(W64, x64, host64(g), n)
     ok, slack = _rounded_once(host64(gx), rgx, dtype)
     assert ok, slack
-    # the weight gradient is float32 (W's dtype): float32 accuracy
-    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-4
+    # the weight gradient is float32 (W's dtype), summed in FP64 and rounded
+    # once: float32 accuracy
+    assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < 1e-5
     assert torch.equal(gx2, gx) and torch.equal(gW2, gW) and torch.equal(gW3, gW)
 
 
