@@ -207,6 +207,25 @@ gtt_status gtt_backward(gtt_plan_t p, const void* W, const void* x, const void* 
                         void* stream);
 
 /*
+ * gtt_backward_noalloc -- gtt_backward for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same gradients, bit for bit, with no `ws`
+ * argument.  The workspace is a device array of GTT_NOALLOC_SCRATCH_BYTES
+ * inside the library, one per GPU, held until the process ends; the call
+ * allocates nothing (its first call on a device looks up that array's
+ * address).  GTT_ERR_WORKSPACE, before any HIP call, when the call needs more
+ * than that: pass `saved` (else the activations between digit groups are
+ * recomputed in the scratch) and a gx that is not gy (else the cotangent
+ * between digit groups is kept there) to need only the gradient partial sums.
+ * Every call on one GPU shares its array: calls that overlap on one GPU (on
+ * different streams or host threads) race and must be serialised by the
+ * caller.
+ */
+#define GTT_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+gtt_status gtt_backward_noalloc(gtt_plan_t p, const void* W, const void* x, const void* saved,
+                                const void* gy, void* gx, void* gW, void* stream);
+
+/*
  * gtt_filter -- classical natural-order filter (§4.3, Alg. 3 without the
  * ancilla): coefficients X = G_N x are split at natural index `cutoff`
  * (k < cutoff -> low, k >= cutoff -> high) and each part is mapped back with

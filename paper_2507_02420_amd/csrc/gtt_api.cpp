@@ -64,6 +64,10 @@ size_t compute_size(gtt_dtype d) {
     return 0;
 }
 
+size_t f32_buf_bytes(const gtt_plan_s* p) {
+    return (((size_t)p->total_elems * sizeof(float)) + 255) & ~(size_t)255;
+}
+
 static bool valid_dtype(int d) { return d >= GTT_F64 && d <= GTT_I32; }
 
 static int ilog2_floor(uint64_t v) {
@@ -567,9 +571,6 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 // float32 in the workspace, run the float32 plan there (in place), convert
 // the results back (round to nearest even).
 // ---------------------------------------------------------------------------
-static size_t f32_buf_bytes(const gtt_plan_s* p) {
-    return (((size_t)p->total_elems * sizeof(float)) + 255) & ~(size_t)255;
-}
 
 static gtt_status f32_apply(gtt_plan_s* p, const void* W, const void* in, void* out, void* saved, void* ws,
                             size_t ws_bytes, bool adjoint, hipStream_t s) {

@@ -225,6 +225,22 @@ bool plan_has_backward(const gtt_plan_s* p) {
     return groups_have_bwd(p->bwd_groups);
 }
 
+size_t backward_ws_need(const gtt_plan_s* p, bool have_saved, bool cb_in_gx) {
+    const size_t es = p->esize;
+    size_t need = bwd_partial_bytes(p);
+    if (p->kind != PlanKind::Ragged) {
+        const int R = (int)p->groups.size();
+        if (R > 1 && !have_saved) need += (size_t)(R - 1) * (size_t)p->slot * es;
+        if (R > 1 && !cb_in_gx) need += (size_t)p->total_elems * es;
+    } else {
+        int maxR = 0;
+        for (const Instance& t : p->inst) maxR = std::max(maxR, (int)t.groups.size());
+        if (maxR > 1 && !have_saved) need += (size_t)(maxR - 1) * (size_t)p->slot * es;
+        if (!cb_in_gx) need += (size_t)p->slot * es;
+    }
+    return need;
+}
+
 gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void* saved, const void* gy, void* gx,
                          void* gW, void* ws, size_t ws_bytes, hipStream_t s) {
     const size_t es = p->esize, cs = p->csize, as = acc_size(p->dtype);

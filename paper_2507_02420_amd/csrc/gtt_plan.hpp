@@ -159,6 +159,11 @@ size_t bwd_partial_bytes(const gtt_plan_s* p);
 // every digit group of the plan has a backward kernel (floating dtypes,
 // radices <= 32, LDS)
 bool plan_has_backward(const gtt_plan_s* p);
+// workspace bytes one gtt_backward call needs (saved passed or not; the
+// cotangent between digit groups kept in gx or not)
+size_t backward_ws_need(const gtt_plan_s* p, bool have_saved, bool cb_in_gx);
+// bytes of one float32 copy of a buffer (GTT_FLAG_FP32_INTERMEDIATE plans)
+size_t f32_buf_bytes(const gtt_plan_s* p);
 std::string describe_plan(const gtt_plan_s* p);
 // bracket a launch with events when timing is enabled (no-ops otherwise)
 void timing_begin(gtt_plan_s* p, hipStream_t s);

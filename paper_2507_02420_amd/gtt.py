@@ -42,7 +42,7 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
            "gtt_backward", "gtt_filter", "gtt_compress", "gtt_plan_destroy", "gtt_status_string",
            "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_set_tuning",
-           "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit"]
+           "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit", "gtt_backward_noalloc"]
 
 
 class GTTError(RuntimeError):
@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_selftest.argtypes = []
     L.gtt_plan_check.argtypes = [vp, vp]
     L.gtt_plan_barrier_limit.argtypes = [vp, u32]
+    L.gtt_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name != "gtt_status_string":
             getattr(L, name).restype = ctypes.c_int

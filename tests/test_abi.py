@@ -434,3 +434,19 @@ def test_backward_refuses_radix_above_32_before_any_hip_call():
     st, h = _plan(1, [32], [2], dtype=G.BF16)
     assert L.gtt_backward(h, a, a, None, a, a, a, None, 0, None) == 5
     L.gtt_plan_destroy(h)
+
+
+def test_noalloc_backward_checks_before_any_hip_call():
+    L = G.lib()
+    a, m = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x10004)
+    st, h = _plan(1, [8], [6], batch=256, dtype=G.C64)
+    assert st == 0
+    assert L.gtt_backward_noalloc(None, a, a, None, a, a, a, None) == 1
+    assert L.gtt_backward_noalloc(h, a, a, None, a, None, None, None) == 1    # neither gx nor gW
+    assert L.gtt_backward_noalloc(h, a, m, None, a, a, a, None) == 4
+    # 256 x 8^6 complex64 without saved activations: more than the scratch
+    assert L.gtt_backward_noalloc(h, a, a, None, a, a, a, None) == 5
+    L.gtt_plan_destroy(h)
+    st, h = _plan(1, [2], [5], dtype=G.I32)
+    assert L.gtt_backward_noalloc(h, a, a, None, a, a, a, None) == 6
+    L.gtt_plan_destroy(h)
