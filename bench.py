@@ -191,10 +191,11 @@ def copy_ceiling_gbs(nbytes=1 << 30, iters=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline_headline(tensors, budget_s=15.0):
-    """FP64 oracle (numpy, single core) on a bounded sample of the headline
-    workload: forward + gradient of whole instances, timed; also the GPU
-    error on those instances."""
+def cpu_baseline_headline(tensors, budget_s=30.0):
+    """FP64 oracle (numpy, single core) on the headline workload: forward +
+    gradient of whole instances, timed, until every instance is done or about
+    budget_s of CPU work; also the GPU error on those instances (y and gx per
+    instance; gW, a sum over instances, when all of them were done)."""
     from oracle import gtt_oracle as O
     x, g, W, y, gx, gW = tensors
     b, n = 8, 6
@@ -206,7 +207,7 @@ def cpu_baseline_headline(tensors, budget_s=15.0):
         prev = None
     done = 0
     errs_y, errs_gx = [], []
-    t0 = time.perf_counter()
+    rgW = np.zeros((b, b), dtype=np.complex128)
     elapsed = 0.0
     # instances in a fixed scattered order until about budget_s of CPU work
     for i in [(37 * j) % 256 for j in range(256)]:
@@ -214,8 +215,9 @@ def cpu_baseline_headline(tensors, budget_s=15.0):
         gi = g[i].cpu().numpy().astype(np.complex128)
         ts = time.perf_counter()
         yi = O.staged(W64, xi, n)
-        gxi, _ = O.grad(W64, xi, gi, n)
+        gxi, gWi = O.grad(W64, xi, gi, n)
         elapsed += time.perf_counter() - ts
+        rgW += gWi
         done += 1
         errs_y.append(float(np.linalg.norm(y[i].cpu().numpy() - yi) / np.linalg.norm(yi)))
         errs_gx.append(float(np.linalg.norm(gx[i].cpu().numpy() - gxi) / np.linalg.norm(gxi)))
@@ -225,13 +227,32 @@ def cpu_baseline_headline(tensors, budget_s=15.0):
     if prev is not None:
         os.sched_setaffinity(0, prev)
     elems = done * b ** n
-    return {
+    out = {
         "value": elems / elapsed, "unit": "elements/s", "cores": cores, "kind": "oracle",
         "sample": f"{done} of 256 instances (N=262144 c64 upcast to complex128): numpy staged forward + "
                   f"stage-wise gradient, {elapsed:.2f} s on one pinned host core",
         "gpu_rel_err_y_max": max(errs_y), "gpu_rel_err_gx_max": max(errs_gx),
         "cpu_model": _cpu_model(), "cores_available": len(prev) if prev else os.cpu_count(),
     }
+    if done == 256:
+        gw = gW.cpu().numpy().astype(np.complex128)
+        out["gpu_rel_err_gW_all_256"] = float(np.linalg.norm(gw - rgW) / np.linalg.norm(rgW))
+    return out
+
+
+def oracle_rate(fn, elems: int) -> dict:
+    """Elements/s of one oracle call on one pinned host core."""
+    try:
+        prev = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(prev)})
+    except (AttributeError, OSError):
+        prev = None
+    t0 = time.perf_counter()
+    out = fn()
+    dt = time.perf_counter() - t0
+    if prev is not None:
+        os.sched_setaffinity(0, prev)
+    return {"elements_per_s": elems / dt, "seconds": dt, "cores": 1, "kind": "oracle", "result": out}
 
 
 def _cpu_model() -> str:
@@ -249,134 +270,262 @@ def _cpu_model() -> str:
 # secondary workloads (GPU-only checks: round trips, bit exactness, the plain
 # FP32 path as reference for the bf16 ragged batch)
 # ---------------------------------------------------------------------------
-def secondary(iters=10):
+def _gpu():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _flusher():
+    import torch
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=_gpu())  # 1 GiB
+    return lambda: scratch.zero_()  # evicts the 256 MB Infinity Cache
+
+
+def _timed_plan(p, fn, iters, flush=None):
+    """Median ms of fn() and the plan's per-kernel timing over the calls."""
+    fn()
+    _sync()
+    p.timing(True)
+    ms, _ = time_calls(fn, iters, flush=flush)
+    tm = p.timing_read()
+    p.timing(False)
+    return ms, tm
+
+
+def _dominant_entry(tm, E):
+    nm_, t_, ach = dominant(tm)
+    return {"dominant": nm_, "dominant_avg_ms": t_["avg_ms"], "dominant_bytes_per_launch": t_["bytes_per_launch"],
+            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+
+
+def wl_c1(iters=50, cpu=True):
+    """Single FP64 vector, b=2, n=10: normalised Hadamard and a random 2x2
+    orthogonal W; latency-bound (one work-group)."""
     import torch
     from paper_2507_02420_amd import gtt as G
-    from paper_2507_02420_amd.inputs import (gaussian, hadamard2, haar_unitary, int_uniform, ragged_shapes,
-                                             uniform)
-    dev = torch.device("cuda:0")
+    from paper_2507_02420_amd.inputs import gaussian, hadamard2, haar_unitary
     res = {}
-    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
-    flush = lambda: scratch.zero_()  # evicts the 256 MB Infinity Cache
-
-    # single FP64 vector, b=2, n=10: Hadamard and random orthogonal W
-    x = torch.from_numpy(gaussian(1024, seed=11)).to(dev)
+    xn = gaussian(1024, seed=11)
+    x = torch.from_numpy(xn).to(_gpu())
     p = G.Plan(2, 10, 1, torch.float64)
-    for nm, W in (("hadamard", hadamard2(True)), ("orthogonal", haar_unitary(2, 12, complex_=False))):
-        Wt = torch.from_numpy(W).to(dev)
+    for nm, Wn in (("hadamard", hadamard2(True)), ("orthogonal", haar_unitary(2, 12, complex_=False))):
+        Wt = torch.from_numpy(Wn).to(_gpu())
         y = torch.empty_like(x)
-        ms, _ = time_calls(lambda: p.forward(Wt, x, y), iters * 5)
-        res[f"f64_b2_n10_{nm}"] = {"us_per_call": ms * 1e3, "elements_per_s": 1024 / (ms * 1e-3)}
+        ms, _ = time_calls(lambda: p.forward(Wt, x, y), iters)
+        e = {"us_per_call": ms * 1e3, "elements_per_s": 1024 / (ms * 1e-3)}
+        if cpu:
+            from oracle import gtt_oracle as O
+            r = oracle_rate(lambda: O.dense(Wn, xn, 10), 1024)
+            ref = r.pop("result")
+            r["form"] = "dense 1024 x 1024 Kronecker matvec"
+            e["cpu_oracle"] = r
+            e["rel_err_vs_dense"] = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
+        res[f"f64_b2_n10_{nm}"] = e
+    return res
 
-    # 64 x complex64, b=4, n=10: forward then inverse
+
+def wl_c2(iters=10, cpu=True):
+    """64 x complex64, b=4, n=10: forward then inverse."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
     b, n, batch = 4, 10, 64
-    x = torch.from_numpy(gaussian((batch, b ** n), seed=21, complex_=True).astype(np.complex64)).to(dev)
-    W = torch.from_numpy(haar_unitary(4, 22).astype(np.complex64)).to(dev)
+    xn = gaussian((batch, b ** n), seed=21, complex_=True).astype(np.complex64)
+    x = torch.from_numpy(xn).to(_gpu())
+    W = torch.from_numpy(haar_unitary(4, 22).astype(np.complex64)).to(_gpu())
     p = G.Plan(b, n, batch, torch.complex64)
     y = torch.empty_like(x)
     xr = torch.empty_like(x)
-    p.forward(W, x, y), p.inverse(W, y, xr)   # first launches (code load) untimed
-    _sync()
-    p.timing(True)
-    ms, _ = time_calls(lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
-    tm = p.timing_read()
-    p.timing(False)
+    ms, tm = _timed_plan(p, lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
     E = batch * b ** n
-    nm_, t_, ach = dominant(tm)
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
-    res["c64_b4_n10_x64_fwd_inv"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err,
-                                     "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
+         "kernels": tm}
+    if cpu:
+        from oracle import gtt_oracle as O
+        W64 = W.cpu().to(torch.complex128).numpy()
+        x0 = xn[0].astype(np.complex128)
+        r = oracle_rate(lambda: O.staged(W64, x0, n), b ** n)
+        ref = r.pop("result")
+        r["sample"] = "instance 0 (N=1048576), numpy staged forward"
+        e["cpu_oracle"] = r
+        e["rel_err_fwd_instance0_vs_oracle"] = float(np.linalg.norm(y[0].cpu().numpy() - ref) / np.linalg.norm(ref))
+    return e
 
-    # 16 x float32, b=3, n=13 (odd strides), MALL flushed
+
+def wl_c3a(iters=10, cpu=True):
+    """16 x float32, b=3, n=13 (odd strides), MALL flushed."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import haar_unitary, uniform
     b, n, batch = 3, 13, 16
-    x = torch.from_numpy(uniform((batch, b ** n), seed=31).astype(np.float32)).to(dev)
-    W = torch.from_numpy(haar_unitary(3, 32, complex_=False).astype(np.float32)).to(dev)
+    xn = uniform((batch, b ** n), seed=31).astype(np.float32)
+    x = torch.from_numpy(xn).to(_gpu())
+    W = torch.from_numpy(haar_unitary(3, 32, complex_=False).astype(np.float32)).to(_gpu())
     p = G.Plan(b, n, batch, torch.float32)
     y = torch.empty_like(x)
-    p.forward(W, x, y)
-    _sync()
-    p.timing(True)
-    ms, _ = time_calls(lambda: p.forward(W, x, y), iters, flush=flush)
-    tm = p.timing_read()
-    p.timing(False)
+    ms, tm = _timed_plan(p, lambda: p.forward(W, x, y), iters, flush=_flusher())
     xr = p.inverse(W, y)
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
     E = batch * b ** n
-    nm_, t_, ach = dominant(tm)
-    res["f32_b3_n13_x16_fwd"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err,
-                                 "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
+         "kernels": tm}
+    if cpu:
+        from oracle import gtt_oracle as O
+        W64 = W.cpu().double().numpy()
+        x0 = xn[0].astype(np.float64)
+        r = oracle_rate(lambda: O.staged(W64, x0, n), b ** n)
+        ref = r.pop("result")
+        r["sample"] = "instance 0 (N=1594323), numpy staged forward"
+        e["cpu_oracle"] = r
+        e["rel_err_fwd_instance0_vs_oracle"] = float(np.linalg.norm(y[0].cpu().double().numpy() - ref) /
+                                                     np.linalg.norm(ref))
+    return e
 
-    # 16 x int32, b=2, n=20, unnormalised Hadamard, MALL flushed; bit-exact
+
+def wl_c3b(iters=10, cpu=True):
+    """16 x int32, b=2, n=20, unnormalised Hadamard, MALL flushed; bit-exact."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import hadamard2, int_uniform
     b, n, batch = 2, 20, 16
-    xi = torch.from_numpy(int_uniform((batch, b ** n), seed=33, lo=-100, hi=100)).to(torch.int32).to(dev)
-    H = torch.from_numpy(hadamard2(False)).to(torch.int32).to(dev)
+    xn = int_uniform((batch, b ** n), seed=33, lo=-100, hi=100)
+    xi = torch.from_numpy(xn).to(torch.int32).to(_gpu())
+    H = torch.from_numpy(hadamard2(False)).to(torch.int32).to(_gpu())
     p = G.Plan(b, n, batch, torch.int32)
     y = torch.empty_like(xi)
-    p.forward(H, xi, y)
-    _sync()
-    p.timing(True)
-    ms, _ = time_calls(lambda: p.forward(H, xi, y), iters, flush=flush)
-    tm = p.timing_read()
-    p.timing(False)
+    ms, tm = _timed_plan(p, lambda: p.forward(H, xi, y), iters, flush=_flusher())
     back = p.inverse(H, y)
     exact = bool(torch.equal(back, xi * (1 << n)))
     E = batch * b ** n
-    nm_, t_, ach = dominant(tm)
-    res["i32_hadamard_b2_n20_x16_fwd"] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
-                                          "inverse_of_forward_is_2^n_x_exactly": exact,
-                                          "dominant": nm_, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "inverse_of_forward_is_2^n_x_exactly": exact,
+         **_dominant_entry(tm, E), "kernels": tm}
+    if cpu:
+        from oracle import gtt_oracle as O
+        r = oracle_rate(lambda: O.staged_int32(hadamard2(False).astype(np.int64), xn[0], n), b ** n)
+        ref = r.pop("result")
+        r["sample"] = "instance 0 (N=1048576), exact integer staged forward"
+        e["cpu_oracle"] = r
+        e["fwd_instance0_bit_exact_vs_oracle"] = bool(np.array_equal(y[0].cpu().numpy(), ref))
+    return e
 
-    # ragged bf16 batch: 1024 instances, b in {2,4,16,32}, N in [2^10, 2^20]
+
+def wl_c5(iters=5, cpu=True):
+    """Ragged bf16 batch: 1024 instances, b in {2,4,16,32}, N in [2^10, 2^20],
+    against the plain FP32 path (the same plan with f32 storage)."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import haar_unitary, ragged_shapes
     shapes = ragged_shapes(1024, seed=52)
     bs = [s_[0] for s_ in shapes]
     ns = [s_[1] for s_ in shapes]
-    Ntot = sum(b_ ** n_ for b_, n_ in shapes)
+    Ns = [b_ ** n_ for b_, n_ in shapes]
+    Ntot = sum(Ns)
     rng = np.random.default_rng(53)
-    x32 = torch.from_numpy(rng.standard_normal(Ntot, dtype=np.float32)).to(dev)
+    x32 = torch.from_numpy(rng.standard_normal(Ntot, dtype=np.float32)).to(_gpu())
     xb = x32.to(torch.bfloat16)
     xf = xb.to(torch.float32)     # the same values, plain FP32 storage
+    del x32
     Ws = [haar_unitary(r, 54 + i, complex_=False).astype(np.float32) for i, r in enumerate((2, 4, 16, 32))]
-    Wt = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).to(dev)
+    Wt = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).to(_gpu())
     pb = G.Plan(bs, ns, 1, torch.bfloat16)
     pf = G.Plan(bs, ns, 1, torch.float32)
     yb = torch.empty_like(xb)
     yf = torch.empty_like(xf)
-    msb, _ = time_calls(lambda: pb.forward(Wt, xb, yb), 3)
-    msf, _ = time_calls(lambda: pf.forward(Wt, xf, yf), 3)
+    msb, tmb = _timed_plan(pb, lambda: pb.forward(Wt, xb, yb), iters)
+    msf, _ = _timed_plan(pf, lambda: pf.forward(Wt, xf, yf), iters)
     # the same batch as ONE persistent launch (grid barriers between phases)
     pp = G.Plan(bs, ns, 1, torch.bfloat16, flags=G.FLAG_PERSISTENT)
     yp = torch.empty_like(xb)
-    pp.forward(Wt, xb, yp)   # the first call uploads the work list
-    msp, _ = time_calls(lambda: pp.forward(Wt, xb, yp), 3)
+    pp.forward(Wt, xb, yp)
+    msp, _ = time_calls(lambda: pp.forward(Wt, xb, yp), iters)
+    pp.check()
     # the default per-phase launches captured in a HIP graph: one launch
-    # for the caller
+    # for the caller (the work list was uploaded by the plan)
     yg = torch.empty_like(xb)
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        pb.forward(Wt, xb, yg)
-    torch.cuda.current_stream().wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         pb.forward(Wt, xb, yg)
     yg.zero_()
-    msg, _ = time_calls(graph.replay, 5)
+    msg, _ = time_calls(graph.replay, iters)
     _sync()
     same = bool(torch.equal(yp, yb)) and bool(torch.equal(yg, yb))
-    # per-instance error of the bf16 path against the plain FP32 path
-    offs = np.cumsum([0] + [b_ ** n_ for b_, n_ in shapes])
-    yb32 = yb.to(torch.float32)
-    errs = []
-    for t in range(0, 1024, 8):
+    # HBM: algorithmic bytes (read x, write y once: 2 E s) and the bytes the
+    # launches move (every digit-group phase reads and writes its instances)
+    alg = 2.0 * Ntot * 2
+    moved = sum(v["bytes_per_launch"] * v["launches"] for v in tmb.values()) / iters
+    ms_launches = sum(v["total_ms"] for v in tmb.values()) / iters
+    per_class = {}
+    for k, v in tmb.items():
+        cls = k.split(" ", 3)[-1]
+        c = per_class.setdefault(cls, {"ms": 0.0, "bytes": 0.0})
+        c["ms"] += v["total_ms"] / iters
+        c["bytes"] += v["bytes_per_launch"] * v["launches"] / iters
+    for c in per_class.values():
+        c["GBs"] = c["bytes"] / (c["ms"] * 1e-3) / 1e9
+        c["frac"] = c["GBs"] / HBM_PEAK_GBS
+    e = {"elements": Ntot, "ms_bf16": msb, "elements_per_s_bf16": Ntot / (msb * 1e-3),
+         "ms_bf16_persistent_launch": msp, "ms_bf16_graph_replay": msg,
+         "persistent_and_graph_equal_phases": same,
+         "ms_plain_fp32": msf, "elements_per_s_plain_fp32": Ntot / (msf * 1e-3), "speedup_vs_plain_fp32": msf / msb,
+         "hbm": {"algorithmic_bytes": alg, "algorithmic_frac": alg / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "moved_bytes": moved, "round_trips": moved / alg,
+                 "achieved_frac": moved / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "achieved_frac_launches_only": moved / (ms_launches * 1e-3) / 1e9 / HBM_PEAK_GBS},
+         "classes": per_class}
+    # per-instance error of the bf16 path against the FP64 oracle on the
+    # stored bf16 values: the first instance of every distinct (b, n) shape
+    # and the last instance of each radix's largest shape
+    from oracle import gtt_oracle as O
+    offs = np.cumsum([0] + Ns)
+    first = {}
+    for t, s_ in enumerate(shapes):
+        first.setdefault(s_, t)
+    last_largest = [max((t for t in range(1024) if shapes[t][0] == b), key=lambda t: (Ns[t], t)) for b in (2, 4, 16, 32)]
+    pick = sorted(set(first.values()) | set(last_largest))
+    ridx = {2: 0, 4: 1, 16: 2, 32: 3}
+    errs, errs32 = {}, {}
+    t_or, n_or = 0.0, 0
+    for t in pick:
+        b_, n_ = shapes[t]
         a, c = int(offs[t]), int(offs[t + 1])
-        errs.append(float((torch.linalg.vector_norm(yb32[a:c] - yf[a:c]) / torch.linalg.vector_norm(yf[a:c])).item()))
-    res["ragged_bf16_1024"] = {"elements": Ntot, "ms_bf16": msb, "elements_per_s_bf16": Ntot / (msb * 1e-3),
-                               "ms_bf16_persistent_launch": msp, "ms_bf16_graph_replay": msg,
-                               "persistent_and_graph_equal_phases": same,
-                               "ms_plain_fp32": msf, "elements_per_s_plain_fp32": Ntot / (msf * 1e-3),
-                               "rel_err_vs_fp32_max": max(errs), "rel_err_vs_fp32_median": float(np.median(errs)),
-                               "instances_checked": len(errs)}
-    del scratch
+        xv = xb[a:c].float().cpu().double().numpy()
+        ts = time.perf_counter()
+        ref = O.staged(Ws[ridx[b_]].astype(np.float64), xv, n_)
+        t_or += time.perf_counter() - ts
+        n_or += c - a
+        errs.setdefault(b_, []).append(float(np.linalg.norm(yb[a:c].float().cpu().double().numpy() - ref) /
+                                             np.linalg.norm(ref)))
+        errs32.setdefault(b_, []).append(float(np.linalg.norm(yf[a:c].cpu().double().numpy() - ref) /
+                                               np.linalg.norm(ref)))
+    e["rel_err_vs_fp64_oracle"] = {f"b={b_}": {"max": max(v), "median": float(np.median(v)), "instances": len(v)}
+                                   for b_, v in sorted(errs.items())}
+    e["plain_fp32_rel_err_vs_fp64_oracle"] = {f"b={b_}": {"max": max(v), "median": float(np.median(v))}
+                                              for b_, v in sorted(errs32.items())}
+    e["instances_checked"] = len(pick)
+    if cpu:
+        e["cpu_oracle"] = {"elements_per_s": n_or / t_or, "seconds": t_or, "cores": 1, "kind": "oracle",
+                           "sample": f"{len(pick)} instances ({n_or} elements): one of every distinct (b, n) "
+                                     "shape and each radix's largest, numpy staged forward (FP64)"}
+    return e
+
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3a": wl_c3a, "c3b": wl_c3b, "c5": wl_c5}
+WL_NAMES = {"c1": "f64_b2_n10", "c2": "c64_b4_n10_x64_fwd_inv", "c3a": "f32_b3_n13_x16_fwd",
+            "c3b": "i32_hadamard_b2_n20_x16_fwd", "c5": "ragged_bf16_1024"}
+
+
+def secondary(cpu=True, only=None):
+    res = {}
+    for k, fn in WORKLOADS.items():
+        if only and k not in only:
+            continue
+        print(f"bench: workload {k}", file=sys.stderr, flush=True)
+        r = fn(cpu=cpu)
+        if k == "c1":
+            res.update(r)
+        else:
+            res[WL_NAMES[k]] = r
     return res
 
 
@@ -387,6 +536,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--only", default="",
+                    help="comma-separated secondary workloads to run alone (c1,c2,c3a,c3b,c5), no headline "
+                         "(for profiling); prints their JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -396,6 +548,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.only:
+        only = [w.strip() for w in args.only.split(",") if w.strip()]
+        bad = [w for w in only if w not in WORKLOADS]
+        if bad:
+            print(f"unknown workloads {bad}; known: {sorted(WORKLOADS)}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(secondary(cpu=not args.no_cpu, only=only)), flush=True)
+        return
     print("bench: headline fwd+bwd 256 x 8^6 c64", file=sys.stderr, flush=True)
     h = headline(args.steps, args.warmup)
     E = h["E"]
@@ -431,8 +591,7 @@ def main():
         cpu = cpu_baseline_headline(h["tensors"])
     extra = None
     if not args.no_extra:
-        print("bench: secondary workloads", file=sys.stderr, flush=True)
-        extra = secondary()
+        extra = secondary(cpu=not args.no_cpu)
     line = {
         "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "step_ms_p10_p50_p90": h["step_ms_p10_p50_p90"],

@@ -295,16 +295,21 @@ gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len);
 
 /*
  * gtt_set_tuning -- override the launch heuristics for plans created after
- * this call, for radix b and storage dtype (used by the autotuner):
- *   lds_budget_bytes : LDS bytes of one tile (0 = default),
+ * this call, for radix b, digit count n (0: every n without an entry of its
+ * own) and storage dtype (used by the autotuner; uniform plans and each
+ * instance of a ragged plan look up their own (b, n)):
+ *   lds_budget_bytes : LDS bytes of one forward tile (0 = default),
  *   min_row_bytes    : least contiguous bytes per tile row for strided digit
  *                      groups (0 = default),
  *   max_group_digits : most digits fused into one HBM round trip (0 = no
- *                      limit beyond the tile size).
- * Process-wide; not thread-safe against concurrent gtt_plan calls.
+ *                      limit beyond the tile size),
+ *   bwd_lds_bytes    : LDS bytes of one work-group of the general backward
+ *                      (tiles and checkpoint slots; 0 = default search).
+ * An entry with all four values 0 restores the defaults.  Process-wide; not
+ * thread-safe against concurrent gtt_plan calls.
  */
-gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
-                          int32_t max_group_digits);
+gtt_status gtt_set_tuning(int32_t b, int32_t n, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
+                          int32_t max_group_digits, int32_t bwd_lds_bytes);
 
 /*
  * gtt_selftest -- host-only checks of the index arithmetic (fast division by

@@ -76,29 +76,43 @@ static int ilog2_floor(uint64_t v) {
     return r;
 }
 
-// tuning table: (b, dtype) -> overrides
+// tuning table: (b, n, dtype) -> overrides; n == 0 applies to every n of
+// that radix without an entry of its own
 struct TuneEntry {
     int b;
+    int n;
     int dtype;
     int lds_budget;
     int min_row_bytes;
     int max_group_digits;
+    int bwd_lds;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
 
-static void tuning_for(int b, gtt_dtype dt, uint32_t flags, int* budget, int* minrow, int* maxk) {
-    *budget = 0;
-    *minrow = 0;
-    *maxk = 0;
-    if (flags & GTT_FLAG_NO_TUNE) return;
+struct Tuning {
+    int budget = 0, minrow = 0, maxk = 0, bwd_lds = 0;
+};
+
+static Tuning tuning_for(int b, int n, gtt_dtype dt, uint32_t flags) {
+    Tuning t;
+    if (flags & GTT_FLAG_NO_TUNE) return t;
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneEntry* any = nullptr;
+    const TuneEntry* exact = nullptr;
     for (const auto& e : g_tune)
         if (e.b == b && e.dtype == (int)dt) {
-            *budget = e.lds_budget;
-            *minrow = e.min_row_bytes;
-            *maxk = e.max_group_digits;
+            if (e.n == n) exact = &e;
+            if (e.n == 0) any = &e;
         }
+    const TuneEntry* e = exact ? exact : any;
+    if (e) {
+        t.budget = e->lds_budget;
+        t.minrow = e->min_row_bytes;
+        t.maxk = e->max_group_digits;
+        t.bwd_lds = e->bwd_lds;
+    }
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -271,7 +285,7 @@ static void make_fast(Group* g, size_t csize, bool bwd) {
 // least 32 bytes for strided groups (where any tile allows), then the fewest
 // LDS passes per tile, then the smaller LDS budget, then the larger tile.
 static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, int k, int64_t total, gtt_dtype dt,
-                             int kind, int64_t cmin, bool shared_w) {
+                             int kind, int64_t cmin, bool shared_w, int bwd_lds) {
     const size_t es = storage_size(dt), cs = compute_size(dt);
     int maxb = 0;
     int64_t wloc = 0, G = 1;
@@ -289,7 +303,9 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
     int best_passes = 0, best_slots = 0;
     int64_t best_row = 0;
     size_t best_cap = 0;
-    for (size_t cap : {(size_t)80 * 1024, (size_t)160 * 1024}) {
+    std::vector<size_t> caps = {(size_t)80 * 1024, (size_t)160 * 1024};
+    if (bwd_lds > 0) caps.assign(1, (size_t)bwd_lds);  // tuned: one LDS budget per work-group
+    for (size_t cap : caps) {
         for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
             Group c;
             fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
@@ -352,8 +368,8 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     const bool small_b = kind != kKindGeneric;
     // the bf16 / f16 matrix-core pass keeps its tile in the storage type
     const size_t cs_fwd = (kind == kKindMfma && es == 2) ? es : cs;
-    int tb = 0, tr = 0, tk = 0;
-    tuning_for(uniform ? b0 : 0, dt, flags, &tb, &tr, &tk);
+    const Tuning tu = tuning_for(uniform ? b0 : 0, n, dt, flags);
+    const int tb = tu.budget, tr = tu.minrow, tk = tu.maxk;
     std::vector<int64_t> budgets;
     if (tb > 0) {
         budgets.push_back(tb);
@@ -400,7 +416,7 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
                             }
                         }
                         plan_bwd_general(&g, rad, fg.s0, fg.k, total, dt, kind == kKindCMfma ? kKindValu : kind,
-                                         cmin, uniform);
+                                         cmin, uniform, tu.bwd_lds);
                         bwd_groups->push_back(g);
                     }
                 }
@@ -798,20 +814,23 @@ gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len) {
     return GTT_OK;
 }
 
-gtt_status gtt_set_tuning(int32_t b, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
-                          int32_t max_group_digits) {
-    if (b < 2 || !valid_dtype((int)dtype)) return GTT_ERR_INVALID_VALUE;
-    if (lds_budget_bytes < 0 || lds_budget_bytes > 160 * 1024 || min_row_bytes < 0 || max_group_digits < 0)
+gtt_status gtt_set_tuning(int32_t b, int32_t n, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
+                          int32_t max_group_digits, int32_t bwd_lds_bytes) {
+    if (b < 2 || n < 0 || !valid_dtype((int)dtype)) return GTT_ERR_INVALID_VALUE;
+    if (lds_budget_bytes < 0 || lds_budget_bytes > 160 * 1024 || min_row_bytes < 0 || max_group_digits < 0 ||
+        bwd_lds_bytes < 0 || bwd_lds_bytes > 160 * 1024)
         return GTT_ERR_INVALID_VALUE;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& e : g_tune)
-        if (e.b == b && e.dtype == (int)dtype) {
+        if (e.b == b && e.n == n && e.dtype == (int)dtype) {
             e.lds_budget = lds_budget_bytes;
             e.min_row_bytes = min_row_bytes;
             e.max_group_digits = max_group_digits;
+            e.bwd_lds = bwd_lds_bytes;
             return GTT_OK;
         }
-    g_tune.push_back(TuneEntry{b, (int)dtype, lds_budget_bytes, min_row_bytes, max_group_digits});
+    g_tune.push_back(
+        TuneEntry{b, n, (int)dtype, lds_budget_bytes, min_row_bytes, max_group_digits, bwd_lds_bytes});
     return GTT_OK;
 }
 

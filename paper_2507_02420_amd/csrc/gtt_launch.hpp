@@ -82,6 +82,8 @@ hipError_t launch_cbwd8(const CBwdArgs& a, unsigned grid, size_t lds, hipStream_
 // forward / adjoint pass of k <= 4 radix-8 digits, complex64, tiles of
 // 2048 * ni elements, 1024 threads, per-lane LDS addresses
 hipError_t launch_cpass8_fast(int k, int ni, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
+// forward / adjoint pass of complex64 radix-8 digits, general tiles
+hipError_t launch_cpass8(const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
 hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 // k dominant coefficients of every instance (ascending indices, ties to the

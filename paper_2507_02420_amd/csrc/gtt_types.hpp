@@ -98,15 +98,10 @@ template <>
 __device__ __forceinline__ int32_t from_c<int32_t>(uint32_t v) { return (int32_t)v; }
 template <>
 __device__ __forceinline__ bf16 from_c<bf16>(float v) {
-    // round to nearest, ties to even; NaN stays a quiet NaN
-    uint32_t u = __float_as_uint(v);
+    // round to nearest, ties to even (gfx950's v_cvt_pk_bf16_f32); NaN stays
+    // a quiet NaN
     bf16 r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r.bits = (uint16_t)((u >> 16) | 0x40u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r.bits = (uint16_t)(u >> 16);
-    }
+    r.bits = __builtin_bit_cast(uint16_t, (__bf16)v);
     return r;
 }
 template <>

@@ -1,54 +1,4 @@
-// Instantiations of the digit-group pass kernels for storage type double.
-#include "gtt_launch.hpp"
-#include "gtt_pass.hpp"
+// Digit-group pass launchers for storage type double.
+#include "gtt_inst.hpp"
 
-namespace gtt {
-
-template <typename K>
-static hipError_t set_lds(K kernel, size_t lds) {
-    if (lds > 65536) return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    return hipSuccess;
-}
-
-hipError_t launch_pass_f64(int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
-    using T = double;
-    hipError_t e = hipSuccess;
-#define GTT_LAUNCH(KER)                                                       \
-    do {                                                                      \
-        e = set_lds(KER, lds);                                                \
-        if (e != hipSuccess) return e;                                        \
-        hipLaunchKernelGGL(KER, dim3(grid), dim3(kThreads), lds, s, a);       \
-    } while (0)
-    // the VALU pass kernels that prefetch run a persistent grid
-#define GTT_LAUNCH_VALU(B)                                                                    \
-    do {                                                                                      \
-        e = set_lds((gtt_pass_kernel<T, B>), lds);                                            \
-        if (e != hipSuccess) return e;                                                        \
-        const unsigned g = pass_prefetches<typename Tr<T>::C, B>()                            \
-                               ? resident_grid((gtt_pass_kernel<T, B>), kThreads, lds, grid)  \
-                               : grid;                                                        \
-        hipLaunchKernelGGL((gtt_pass_kernel<T, B>), dim3(g), dim3(kThreads), lds, s, a);      \
-    } while (0)
-    if (kind == kKindGeneric) {
-        GTT_LAUNCH(gtt_pass_generic_kernel<T>);
-    } else if (kind == kKindMfma) {
-        return hipErrorInvalidValue;
-    } else {
-        switch (b) {
-            case 2: GTT_LAUNCH_VALU(2); break;
-            case 3: GTT_LAUNCH_VALU(3); break;
-            case 4: GTT_LAUNCH_VALU(4); break;
-            case 5: GTT_LAUNCH_VALU(5); break;
-            case 6: GTT_LAUNCH_VALU(6); break;
-            case 7: GTT_LAUNCH_VALU(7); break;
-            case 8: GTT_LAUNCH_VALU(8); break;
-            default: GTT_LAUNCH(gtt_pass_generic_kernel<T>); break;
-        }
-    }
-#undef GTT_LAUNCH
-#undef GTT_LAUNCH_VALU
-    return hipGetLastError();
-}
-
-}  // namespace gtt
+GTT_PASS_INSTANTIATE(f64, double)

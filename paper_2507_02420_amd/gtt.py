@@ -79,7 +79,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.gtt_plan_timing.argtypes = [vp, i32]
     L.gtt_plan_timing_read.argtypes = [vp, ctypes.c_char_p, sz]
-    L.gtt_set_tuning.argtypes = [i32, ctypes.c_int, i32, i32, i32]
+    L.gtt_set_tuning.argtypes = [i32, i32, ctypes.c_int, i32, i32, i32, i32]
     L.gtt_selftest.argtypes = []
     L.gtt_plan_check.argtypes = [vp, vp]
     L.gtt_plan_barrier_limit.argtypes = [vp, u32]
@@ -110,8 +110,10 @@ def load_tuning(path: Optional[str] = None) -> int:
         return 0
     n = 0
     for e in table.get("entries", []):
-        st = _lib.gtt_set_tuning(int(e["b"]), _NAME_TO_GTT[e["dtype"]], int(e["lds_budget"]),
-                                 int(e["min_row_bytes"]), int(e.get("max_group_digits", 0)))
+        if not e.get("override", True):
+            continue
+        st = _lib.gtt_set_tuning(int(e["b"]), int(e.get("n", 0)), _NAME_TO_GTT[e["dtype"]], int(e["lds_budget"]),
+                                 int(e["min_row_bytes"]), int(e.get("max_group_digits", 0)), int(e.get("bwd_lds", 0)))
         n += st == OK
     return n
 
@@ -296,9 +298,12 @@ def _compress(self, W: torch.Tensor, x: torch.Tensor, k: int, reconstruct: bool 
 Plan.compress = _compress
 
 
-def set_tuning(b: int, dtype, lds_budget_bytes: int, min_row_bytes: int, max_group_digits: int = 0):
-    _check(lib().gtt_set_tuning(int(b), TORCH_TO_GTT[dtype], int(lds_budget_bytes), int(min_row_bytes),
-                                int(max_group_digits)), "gtt_set_tuning")
+def set_tuning(b: int, dtype, lds_budget_bytes: int, min_row_bytes: int, max_group_digits: int = 0, n: int = 0,
+               bwd_lds_bytes: int = 0):
+    """Tiling overrides for plans created afterwards (radix b, n digits or
+    every n when n == 0, storage dtype); all zeros restore the defaults."""
+    _check(lib().gtt_set_tuning(int(b), int(n), TORCH_TO_GTT[dtype], int(lds_budget_bytes), int(min_row_bytes),
+                                int(max_group_digits), int(bwd_lds_bytes)), "gtt_set_tuning")
 
 
 def selftest() -> int:

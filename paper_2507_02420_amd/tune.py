@@ -1,10 +1,24 @@
-"""Autotuner for the digit-group tiling of libgtt.so.
+"""Autotuner for the tiling of libgtt.so.
 
-For each (radix, storage dtype) workload it times the forward transform over a
-grid of tile budgets (LDS bytes per tile) and least row widths of strided
-digit groups, through gtt_set_tuning, and records the fastest pair.  The
-result is a JSON table that ``gtt.load_tuning`` feeds back into
-gtt_set_tuning before plans are built.
+Three searches, each through gtt_set_tuning (keyed by radix b, digit count n
+and storage dtype) and timed with HIP events on the GPU:
+
+  forward  -- for each benchmark shape (a single FP64 vector b=2 n=10;
+              64 x c64 b=4 n=10; 16 x f32 b=3 n=13; 16 x int32 b=2 n=20;
+              256 x c64 b=8 n=6) the forward transform over a grid of tile
+              budgets (LDS bytes per tile), least row widths of strided
+              digit groups and most digits per group;
+  ragged   -- for each distinct (b, n) of the 1024-instance bf16 shape list
+              (b in {2, 4, 16, 32}, N in [2^10, 2^20]) the same grid, timed
+              on a ragged plan holding just that shape's instances (the
+              ragged class kernels, with as many instances as the list has);
+  backward -- for shapes that run the general backward kernel, the LDS
+              budget of one backward work-group (which sets how many tiles
+              of checkpointed activations it holds).
+
+Every result goes into the table; an entry overrides the built-in heuristic
+("override": true) only when it tiles differently and is at least 2 %
+faster.  ``gtt.load_tuning`` applies the overrides before plans are built.
 
 Usage (on the GPU):
     python -m paper_2507_02420_amd.tune [--out FILE] [--quick]
@@ -19,33 +33,38 @@ import sys
 import torch
 
 from . import gtt as G
+from .inputs import ragged_shapes
 
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
 DT_NAMES = {torch.float64: "f64", torch.float32: "f32", torch.complex128: "c128", torch.complex64: "c64",
             torch.bfloat16: "bf16", torch.float16: "f16", torch.int32: "i32"}
 DT_BY_NAME = {v: k for k, v in DT_NAMES.items()}
 
-# representative workloads: (b, n, batch, dtype); the bf16 ones hold about
-# as many elements as one radix class of a ragged batch of 2^28 elements
-# over four radices (64 vectors of 2^20)
-WORKLOADS = [
-    (8, 6, 256, torch.complex64),
-    (4, 10, 64, torch.complex64),
-    (3, 13, 16, torch.float32),
-    (2, 20, 16, torch.int32),
-    (2, 20, 64, torch.bfloat16),
-    (4, 10, 64, torch.bfloat16),
-    (16, 5, 64, torch.bfloat16),
-    (32, 4, 64, torch.bfloat16),
+# (name, b, n, batch, dtype)
+FORWARD = [
+    ("single f64 vector", 2, 10, 1, torch.float64),
+    ("64 x c64 b=4 n=10", 4, 10, 64, torch.complex64),
+    ("16 x f32 b=3 n=13", 3, 13, 16, torch.float32),
+    ("16 x i32 b=2 n=20", 2, 20, 16, torch.int32),
+    ("256 x c64 b=8 n=6", 8, 6, 256, torch.complex64),
 ]
-BUDGETS = [16384, 24576, 32768, 49152, 65536]
-MIN_ROWS = [64, 128, 256, 512]
-MAX_DIGITS = [0, 2, 3, 4, 5, 6, 7]
+BACKWARD = [
+    ("64 x f32 b=4 n=10", 4, 10, 64, torch.float32),
+    ("16 x f32 b=2 n=20", 2, 20, 16, torch.float32),
+    ("16 x f32 b=3 n=13", 3, 13, 16, torch.float32),
+    ("64 x c64 b=4 n=10", 4, 10, 64, torch.complex64),
+    ("64 x bf16 b=16 n=4", 16, 4, 64, torch.bfloat16),
+    ("32 x bf16 b=32 n=3", 32, 3, 32, torch.bfloat16),
+]
+BUDGETS = [16384, 32768, 49152, 65536]
+MIN_ROWS = [32, 64, 128, 256]
+MAX_DIGITS = [0, 2, 3, 4]
+BWD_LDS = [0, 40960, 65536, 81920, 122880, 163840]
 
 
-def _time_forward(plan, W, x, y, iters=10, flush=None):
+def _median_ms(fn, iters=10, flush=None):
     for _ in range(2):
-        plan.forward(W, x, y)
+        fn()
     torch.cuda.synchronize()
     ts = []
     for _ in range(iters):
@@ -55,7 +74,7 @@ def _time_forward(plan, W, x, y, iters=10, flush=None):
         s = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
         s.record()
-        plan.forward(W, x, y)
+        fn()
         e.record()
         e.synchronize()
         ts.append(s.elapsed_time(e))
@@ -63,47 +82,138 @@ def _time_forward(plan, W, x, y, iters=10, flush=None):
     return ts[len(ts) // 2]
 
 
-def tune_one(b, n, batch, dtype, budgets=BUDGETS, min_rows=MIN_ROWS, max_digits=MAX_DIGITS, log=print):
-    dev = torch.device("cuda")
-    N = b ** n
+def _data(shape, dtype, dev):
     if dtype.is_complex:
-        x = torch.randn(batch, N, dtype=dtype, device=dev)
-    elif dtype == torch.int32:
-        x = torch.randint(-100, 101, (batch, N), dtype=torch.int32, device=dev)
-    else:
-        x = torch.randn(batch, N, device=dev).to(dtype)
+        return torch.randn(*shape, dtype=dtype, device=dev)
+    if dtype == torch.int32:
+        return torch.randint(-100, 101, shape, dtype=torch.int32, device=dev)
+    return torch.randn(*shape, device=dev).to(dtype)
+
+
+def _w(b, dtype, dev, count=1):
     wdt = G.W_DTYPE[dtype]
-    W = (torch.randn(b, b, device=dev) if wdt != torch.int32 else torch.ones(b, b, device=dev)).to(wdt)
+    if wdt == torch.int32:
+        return torch.ones(count * b * b, device=dev).to(wdt)
+    return torch.randn(count * b * b, dtype=wdt if wdt.is_complex else torch.float32, device=dev).to(wdt)
+
+
+def _tiling(b, n, dtype, flags=0):
+    """The digit groups and tiles of (b, n, dtype) under the current tuning
+    (a ragged plan tiles each instance as this one-instance plan does)."""
+    p = G.Plan(b, n, 1, dtype, flags=flags)
+    return json.dumps([(g["k"], g["C"], g["P"] and 1, g["tile_elems"]) for g in p.describe()["groups"]])
+
+
+def _plan_tiling(plan):
+    return json.dumps([(g["k"], g["C"], g["P"], g["tile_elems"]) for g in plan.describe()["groups"]])
+
+
+def _grid_search(b, n, dtype, make_plan, time_plan, budgets, rows, maxd, log, uniform=True):
+    """Best forward tiling for (b, n, dtype) over the grid; make_plan(flags)
+    builds the plan under the current tuning, time_plan(plan) times it;
+    tilings are compared on the plan itself (uniform) or on the one-instance
+    plan of the shape (ragged)."""
+    best, seen = None, set()
+    for bud in budgets:
+        for mr in rows:
+            for mk in maxd:
+                G.set_tuning(b, dtype, bud, mr, mk, n=n)
+                try:
+                    plan = make_plan(0)
+                except G.GTTError:
+                    continue
+                desc = _plan_tiling(plan) if uniform else _tiling(b, n, dtype)
+                if desc in seen:      # same tiling as an earlier grid point
+                    continue
+                seen.add(desc)
+                ms = time_plan(plan)
+                if best is None or ms < best["ms"]:
+                    best = {"ms": ms, "lds_budget": bud, "min_row_bytes": mr, "max_group_digits": mk, "groups": desc}
+    G.set_tuning(b, dtype, 0, 0, 0, n=n)
+    base_plan = make_plan(G.FLAG_NO_TUNE)
+    base = time_plan(base_plan)
+    base_desc = _plan_tiling(base_plan) if uniform else _tiling(b, n, dtype, G.FLAG_NO_TUNE)
+    best.update({"heuristic_ms": base, "heuristic_groups": base_desc})
+    best["override"] = bool(best["groups"] != base_desc and best["ms"] < 0.98 * base)
+    log(f"  b={b} n={n} {DT_NAMES[dtype]}: heuristic {base:.4f} ms, best {best['ms']:.4f} ms "
+        f"(budget {best['lds_budget']}, min row {best['min_row_bytes']}, max digits {best['max_group_digits']})"
+        f"{' -> override' if best['override'] else ''}")
+    return best
+
+
+def tune_forward(name, b, n, batch, dtype, budgets, rows, maxd, log):
+    dev = torch.device("cuda")
+    x = _data((batch, b ** n), dtype, dev)
+    W = _w(b, dtype, dev).reshape(b, b)
     y = torch.empty_like(x)
     small = x.numel() * x.element_size() < (512 << 20)
     scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev) if small else None
     flush = (lambda: scratch.zero_()) if small else None
+    e = _grid_search(b, n, dtype, lambda fl: G.Plan(b, n, batch, dtype, flags=fl),
+                     lambda p: _median_ms(lambda: p.forward(W, x, y), flush=flush), budgets, rows, maxd, log)
+    e.update({"search": "forward", "workload": name, "b": b, "n": n, "batch": batch, "dtype": DT_NAMES[dtype],
+              "bwd_lds": 0})
+    return e
+
+
+def tune_ragged_shapes(budgets, rows, maxd, log):
+    """Per distinct (b, n) of the 1024-instance bf16 list: a ragged plan of
+    that shape's instances only, timed per candidate tiling."""
+    dev = torch.device("cuda")
+    shapes = ragged_shapes(1024, seed=52)
+    counts = {}
+    for s in shapes:
+        counts[s] = counts.get(s, 0) + 1
+    out = []
+    for (b, n), c in sorted(counts.items()):
+        N = b ** n
+        x = _data((c * N,), torch.bfloat16, dev)
+        W = _w(b, torch.bfloat16, dev)
+        y = torch.empty_like(x)
+
+        def make(fl, b=b, n=n, c=c):
+            return G.Plan([b] * c, [n] * c, 1, torch.bfloat16, flags=fl)
+
+        e = _grid_search(b, n, torch.bfloat16, make,
+                         lambda p, W=W, x=x, y=y: _median_ms(lambda: p.forward(W, x, y)), budgets, rows, maxd, log,
+                         uniform=False)
+        e.update({"search": "ragged", "workload": f"{c} bf16 instances b={b} n={n} of the 1024-instance list",
+                  "b": b, "n": n, "batch": c, "dtype": "bf16", "bwd_lds": 0})
+        out.append(e)
+    return out
+
+
+def tune_backward(name, b, n, batch, dtype, caps, log):
+    dev = torch.device("cuda")
+    x = _data((batch, b ** n), dtype, dev)
+    g = _data((batch, b ** n), dtype, dev)
+    W = _w(b, dtype, dev).reshape(b, b)
     best = None
-    seen = set()
-    for bud in budgets:
-        for mr in min_rows:
-            for mk in max_digits:
-                G.set_tuning(b, dtype, bud, mr, mk)
-                try:
-                    plan = G.Plan(b, n, batch, dtype)
-                except G.GTTError:
-                    continue
-                desc = json.dumps([(g["k"], g["C"], g["P"]) for g in plan.describe()["groups"]])
-                if desc in seen:      # same tiling as an earlier grid point
-                    continue
-                seen.add(desc)
-                ms = _time_forward(plan, W, x, y, flush=flush)
-                if best is None or ms < best[0]:
-                    best = (ms, bud, mr, desc, mk)
-    G.set_tuning(b, dtype, 0, 0, 0)
-    base_plan = G.Plan(b, n, batch, dtype, flags=G.FLAG_NO_TUNE)
-    base = _time_forward(base_plan, W, x, y, flush=flush)
-    base_desc = json.dumps([(g["k"], g["C"], g["P"]) for g in base_plan.describe()["groups"]])
-    log(f"b={b} n={n} batch={batch} {DT_NAMES[dtype]}: heuristic {base:.4f} ms, best {best[0]:.4f} ms "
-        f"(budget {best[1]}, min row {best[2]}, groups {best[3]})")
-    return {"b": b, "n": n, "batch": batch, "dtype": DT_NAMES[dtype], "lds_budget": best[1],
-            "min_row_bytes": best[2], "max_group_digits": best[4], "ms": best[0], "heuristic_ms": base,
-            "groups": best[3], "heuristic_groups": base_desc}
+    base = None
+    for cap in caps:
+        G.set_tuning(b, dtype, 0, 0, 0, n=n, bwd_lds_bytes=cap)
+        try:
+            p = G.Plan(b, n, batch, dtype)
+            _, _, sv = p.workspace_size()
+            saved = torch.empty(max(sv, 16), dtype=torch.uint8, device=dev)
+            p.forward(W, x, saved=saved)
+            gx = torch.empty_like(x)
+            gW = torch.empty_like(W)
+            ms = _median_ms(lambda: p.backward(W, x, g, saved=saved, gx=gx, gW=gW))
+        except G.GTTError:
+            continue
+        desc = json.dumps([(gg["k"], gg["tile_elems"], gg["bwd_slots"]) for gg in p.describe()["bwd_groups"]])
+        if cap == 0:
+            base = (ms, desc)
+        if best is None or ms < best[0]:
+            best = (ms, cap, desc)
+    G.set_tuning(b, dtype, 0, 0, 0, n=n)
+    override = bool(best[1] != 0 and best[2] != base[1] and best[0] < 0.98 * base[0])
+    log(f"  backward b={b} n={n} {DT_NAMES[dtype]}: default {base[0]:.4f} ms, best {best[0]:.4f} ms "
+        f"(work-group LDS {best[1] or 'default'}){' -> override' if override else ''}")
+    return {"search": "backward", "workload": name, "b": b, "n": n, "batch": batch, "dtype": DT_NAMES[dtype],
+            "lds_budget": 0, "min_row_bytes": 0, "max_group_digits": 0, "bwd_lds": best[1], "ms": best[0],
+            "heuristic_ms": base[0], "groups": best[2], "heuristic_groups": base[1], "override": override}
 
 
 def main():
@@ -112,18 +222,22 @@ def main():
     ap.add_argument("--quick", action="store_true", help="fewer grid points")
     args = ap.parse_args()
     budgets = [16384, 32768, 65536] if args.quick else BUDGETS
-    rows = [128, 256] if args.quick else MIN_ROWS
+    rows = [64, 128] if args.quick else MIN_ROWS
     maxd = [0, 3] if args.quick else MAX_DIGITS
+    log = lambda m: print(m, flush=True)
     table = {"arch": torch.cuda.get_device_properties(0).gcnArchName, "entries": []}
-    for (b, n, batch, dt) in WORKLOADS:
-        e = tune_one(b, n, batch, dt, budgets, rows, maxd, log=lambda m: print(m, flush=True))
-        # keep an override only when it tiles differently from the built-in
-        # heuristic and beats it
-        if e["groups"] != e["heuristic_groups"] and e["ms"] < 0.98 * e["heuristic_ms"]:
-            table["entries"].append(e)
+    log("forward tiling")
+    for w in FORWARD:
+        table["entries"].append(tune_forward(*w, budgets, rows, maxd, log))
+    log("ragged shapes (bf16)")
+    table["entries"].extend(tune_ragged_shapes(budgets, rows, maxd, log))
+    log("backward work-group LDS")
+    for w in BACKWARD:
+        table["entries"].append(tune_backward(*w, BWD_LDS, log))
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
-    print(f"wrote {args.out}", file=sys.stderr)
+    n_over = sum(e["override"] for e in table["entries"])
+    print(f"wrote {args.out}: {len(table['entries'])} entries, {n_over} overrides", file=sys.stderr)
 
 
 if __name__ == "__main__":

@@ -89,9 +89,11 @@ def test_call_validation_before_any_hip_call():
 
 def test_tuning_validation():
     L = G.lib()
-    assert L.gtt_set_tuning(1, G.F32, 0, 0, 0) == 1
-    assert L.gtt_set_tuning(2, G.F32, 200 * 1024, 0, 0) == 1
-    assert L.gtt_set_tuning(2, G.F32, 0, 0, -1) == 1
+    assert L.gtt_set_tuning(1, 0, G.F32, 0, 0, 0, 0) == 1
+    assert L.gtt_set_tuning(2, 0, G.F32, 200 * 1024, 0, 0, 0) == 1
+    assert L.gtt_set_tuning(2, 0, G.F32, 0, 0, -1, 0) == 1
+    assert L.gtt_set_tuning(2, -1, G.F32, 0, 0, 0, 0) == 1
+    assert L.gtt_set_tuning(2, 0, G.F32, 0, 0, 0, 200 * 1024) == 1
 
 
 def test_tuning_changes_split_and_not_results():
@@ -147,7 +149,7 @@ def test_binding_refuses_host_tensors():
 
 def test_planner_layouts_match_compiled_specializations():
     # the radix-8 kernels have compile-time-offset instantiations for the
-    # layouts of the 256 x 8^6 complex64 workload (pass_c64.hip: FwdLay4,
+    # layouts of the 256 x 8^6 complex64 workload (cmfma_c64.hip: FwdLay4,
     # FwdLay2, BwdLay4, BwdLay2); the planner must keep producing them, or
     # that workload silently falls back to run-time offsets
     d = G.Plan(8, 6, 256, torch.complex64).describe()
@@ -450,3 +452,25 @@ def test_noalloc_backward_checks_before_any_hip_call():
     st, h = _plan(1, [2], [5], dtype=G.I32)
     assert L.gtt_backward_noalloc(h, a, a, None, a, a, a, None) == 6
     L.gtt_plan_destroy(h)
+
+
+def test_tuning_per_digit_count_and_backward_budget():
+    # an entry for (b, n) takes precedence over the radix-wide entry (n = 0);
+    # the backward's LDS budget per work-group sets its checkpoint slots
+    G.set_tuning(8, torch.complex64, 0, 0, 3)
+    G.set_tuning(8, torch.complex64, 0, 0, 2, n=5)
+    try:
+        k6 = [g["k"] for g in G.Plan(8, 6, 4, torch.complex64).describe()["groups"]]
+        k5 = [g["k"] for g in G.Plan(8, 5, 4, torch.complex64).describe()["groups"]]
+    finally:
+        G.set_tuning(8, torch.complex64, 0, 0, 0, n=5)
+        G.set_tuning(8, torch.complex64, 0, 0, 0)
+    assert k6 == [3, 3] and max(k5) <= 2 and sum(k5) == 5
+    base = G.Plan(4, 5, 3, torch.float32).describe()["bwd_groups"][0]
+    G.set_tuning(4, torch.float32, 0, 0, 0, n=5, bwd_lds_bytes=20 * 1024)
+    try:
+        g = G.Plan(4, 5, 3, torch.float32).describe()["bwd_groups"][0]
+    finally:
+        G.set_tuning(4, torch.float32, 0, 0, 0, n=5)
+    assert base["bwd_slots"] == 6
+    assert g["bwd_ok"] and 3 <= g["bwd_slots"] < 6 and g["bwd_fwd_passes"] > base["bwd_fwd_passes"]

@@ -1,9 +1,9 @@
 """The benchmark's secondary workloads at their full sizes and in the launch
-configuration the benchmark times, checked on sampled instances against the
-FP64 oracle: 64 x complex64 radix 4 (forward and inverse), 16 x float32
-radix 3 with n = 13 (odd strides), 16 x int32 unnormalised Hadamard radix 2
-with n = 20 (bit-exact), and the plain-FP32 form of the 1024-instance
-ragged batch."""
+configuration the benchmark times, every instance checked against the FP64
+oracle (computed in chunks of instances): 64 x complex64 radix 4 (forward
+and inverse), 16 x float32 radix 3 with n = 13 (odd strides), 16 x int32
+unnormalised Hadamard radix 2 with n = 20 (bit-exact), and the plain-FP32
+form of the 1024-instance ragged batch (sampled instances)."""
 import numpy as np
 import pytest
 import torch
@@ -26,9 +26,10 @@ def test_c64_radix4_n10_batch64_forward_inverse():
     xr = plan.inverse(W, y)
     torch.cuda.synchronize()
     W64 = host64(W)
-    rows = [0, 31, 63]
-    x64 = host64(x[rows])
-    assert rel_err(host64(y[rows]), O.staged(W64, x64, n)) < TOL[torch.complex64]
+    for c0 in range(0, batch, 8):
+        x64 = host64(x[c0:c0 + 8])
+        assert rel_err(host64(y[c0:c0 + 8]), O.staged(W64, x64, n)) < TOL[torch.complex64], c0
+        assert rel_err(host64(xr[c0:c0 + 8]), O.adjoint(W64, host64(y[c0:c0 + 8]), n)) < TOL[torch.complex64], c0
     assert rel_err(host64(xr), host64(x)) < 3 * TOL[torch.complex64]
 
 
@@ -41,9 +42,9 @@ def test_f32_radix3_n13_batch16():
     y = plan.forward(W, x)
     xr = plan.inverse(W, y)
     torch.cuda.synchronize()
-    rows = [0, 7, 15]
-    x64 = host64(x[rows])
-    assert rel_err(host64(y[rows]), O.staged(host64(W), x64, n)) < TOL[torch.float32]
+    for c0 in range(0, batch, 4):
+        x64 = host64(x[c0:c0 + 4])
+        assert rel_err(host64(y[c0:c0 + 4]), O.staged(host64(W), x64, n)) < TOL[torch.float32], c0
     assert rel_err(host64(xr), host64(x)) < 3 * TOL[torch.float32]
 
 
@@ -56,10 +57,11 @@ def test_int32_hadamard_radix2_n20_batch16_exact():
     y = plan.forward(H, x)
     xr = plan.inverse(H, y)
     torch.cuda.synchronize()
-    # |y| <= 100 * 2^20 < 2^31 and the FP64 oracle is exact on these integers
-    for r in (0, 9, 15):
-        ref = O.staged(hadamard2(False), x[r].cpu().numpy().astype(np.float64), n)
-        assert np.array_equal(y[r].cpu().numpy().astype(np.int64), ref.astype(np.int64))
+    # every instance against the exact integer oracle (|y| <= 100 * 2^20)
+    H64 = hadamard2(False).astype(np.int64)
+    for r in range(batch):
+        ref = O.staged_int32(H64, x[r].cpu().numpy().astype(np.int64), n)
+        assert np.array_equal(y[r].cpu().numpy(), ref), r
     assert torch.equal(xr, x * (1 << n))
 
 
