@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -279,11 +280,15 @@ static void make_fast(Group* g, size_t csize, bool bwd) {
 
 // Tile and checkpoint schedule of a backward group on the general kernel.
 // Candidate tiles hold G * 2^i elements (at most 40 KiB, or one group's
-// positions); a work-group's LDS holds as many tiles as fit in 80 KiB (two
-// work-groups per compute unit) or 160 KiB, at most k + 1 (then every
-// activation of the group is computed once).  Preference: HBM rows of at
-// least 32 bytes for strided groups (where any tile allows), then the fewest
-// LDS passes per tile, then the smaller LDS budget, then the larger tile.
+// positions) and a work-group holds as many of them as fit its LDS budget
+// (40, 64, 80, 120 or 160 KiB), at most k + 1 (then every activation of the
+// group is computed once).  A work-group is four waves, one per SIMD, so the
+// budget sets the waves per SIMD (160 KiB / budget, at most four) that hide
+// the latency of LDS and global accesses.  Preference: HBM rows of at least
+// 32 bytes for strided groups (where any tile allows), then the smallest
+// estimated time per element, LDS passes (forward passes of the schedule
+// plus a gradient sweep and an adjoint pass per digit) over
+// (waves / 4)^0.75, then the larger tile.
 static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, int k, int64_t total, gtt_dtype dt,
                              int kind, int64_t cmin, bool shared_w, int bwd_lds) {
     const size_t es = storage_size(dt), cs = compute_size(dt);
@@ -296,38 +301,53 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
     }
     if (shared_w) wloc = (int64_t)rad[s0] * rad[s0];
     const bool radix_ok = maxb <= 32 && wloc <= 4096 && k <= kMaxDigits;
+    // one W for every digit and a radix with a register-block kernel: the
+    // schedule runs over blocks of rd digits (one LDS round trip a block)
+    const int rd0 = shared_w ? bwd_block_digits(static_cast<DT>((int)dt), rad[s0]) : 0;
+    const bool pow2 = (rad[s0] & (rad[s0] - 1)) == 0;
     const size_t over = radix_ok ? bwd_overhead_bytes((int)wloc, dt) : 0;
     const int64_t Tmax = std::max<int64_t>(G, (int64_t)(40 * 1024) / (int64_t)cs);
     bool found = false;
     Group best;
-    int best_passes = 0, best_slots = 0;
+    int best_passes = 0, best_slots = 0, best_rd = 0, best_units = 0;
     int64_t best_row = 0;
     size_t best_cap = 0;
-    std::vector<size_t> caps = {(size_t)80 * 1024, (size_t)160 * 1024};
+    std::vector<size_t> caps = {(size_t)40 * 1024, (size_t)64 * 1024, (size_t)80 * 1024, (size_t)120 * 1024,
+                                (size_t)160 * 1024};
     if (bwd_lds > 0) caps.assign(1, (size_t)bwd_lds);  // tuned: one LDS budget per work-group
+    double best_cost = 0.0;
     for (size_t cap : caps) {
         for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
             Group c;
             fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
             const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
             if (over + 3 * tb > cap) break;  // tiles only grow with T
-            const int slots = (int)std::min<size_t>((cap - over) / tb, (size_t)std::min(k + 1, kMaxBwdSlots));
-            const int passes = bwd_fwd_passes(k, slots - 2) + 2 * k;
+            // the register-block kernel addresses a block as one padded base
+            // plus fixed offsets: a power-of-two radix, or an unpadded tile
+            const int rd = (rd0 > 0 && (pow2 || c.pad_shift == kNoPad)) ? rd0 : 0;
+            const int units = rd > 0 ? (k + rd - 1) / rd : k;
+            const int slots = (int)std::min<size_t>((cap - over) / tb, (size_t)std::min(units + 1, kMaxBwdSlots));
+            const int passes = bwd_fwd_passes(units, slots - 2) + 2 * units;
+            const size_t lds = over + (size_t)slots * tb;
+            const int waves = (int)std::min<size_t>(4, (160 * 1024) / lds);
+            const double cost = (double)passes / std::pow((double)waves / 4.0, 0.75);
             const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, 32);
             bool better = !found;
             if (!better) {
                 if (row != best_row) better = row > best_row;
-                else if (passes != best_passes) better = passes < best_passes;
-                else if (cap != best_cap) better = cap < best_cap;
+                else if (cost != best_cost) better = cost < best_cost;
                 else better = c.tileE > best.tileE;
             }
             if (better) {
                 found = true;
                 best = c;
+                best_rd = rd;
+                best_units = units;
                 best_passes = passes;
                 best_slots = slots;
                 best_row = row;
                 best_cap = cap;
+                best_cost = cost;
             }
         }
     }
@@ -344,7 +364,8 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
     out->bwd_slots = best_slots;
     out->bwd_maxb = maxb;
     out->bwd_wloc = (int)wloc;
-    out->bwd_ops = bwd_schedule(k, best_slots);
+    out->bwd_rd = best_rd;
+    out->bwd_ops = bwd_schedule(best_units, best_slots);
 }
 
 // Plan the digit groups for one radix list.

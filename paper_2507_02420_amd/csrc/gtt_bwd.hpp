@@ -261,6 +261,246 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Radix-specialised backward on register blocks (one W shared by every
+// digit, radix B = 2..5 known at compile time).  The digits of the group are
+// taken RD at a time ("blocks"); the host's checkpoint schedule runs over the
+// blocks (operation digit field = block index), so an LDS slot holds the
+// activation at the start of a block.  A thread owns one B^r-element block of
+// the tile (r <= RD digits, the positions of one value of every other digit)
+// in registers:
+//   - forward over a block: load, apply W along its r digits in registers,
+//     store (one LDS round trip for r digits);
+//   - gradient and adjoint over a block: load the block's activation and its
+//     cotangent, rebuild the r activations inside the block in registers,
+//     then for the block's digits from the last down: add the outer products
+//     of the digit's fibres into the thread's FP64 accumulators and apply
+//     W^H along the digit to the cotangent in registers; store the cotangent
+//     (again one LDS round trip for r digits).
+// W and W^H live in registers; the accumulators too, for the whole launch
+// (every block a thread owns, tile after tile, in order), and are summed
+// over the work-group once at the end: over the lanes of a wave by a fixed
+// shuffle tree, then over the waves in order.
+// ---------------------------------------------------------------------------
+// digits per register block for storage type T (compute type C) and radix
+// b; 0: no radix-specialised kernel
+template <typename C>
+__host__ __device__ constexpr int bwd_block_digits(int b) {
+    if (std::is_same<C, float>::value) return b == 2 ? 4 : (b == 3 || b == 4) ? 2 : b == 5 ? 1 : 0;
+    if (std::is_same<C, double>::value) return b == 2 ? 3 : b == 3 ? 2 : (b == 4 || b == 5) ? 1 : 0;
+    if (std::is_same<C, cf>::value) return b == 2 ? 3 : (b == 3 || b == 4) ? 1 : 0;
+    if (std::is_same<C, cd>::value) return b == 2 ? 2 : (b == 3 || b == 4) ? 1 : 0;
+    return 0;
+}
+
+__device__ __forceinline__ double acc_shfl_down(double v, int d) { return __shfl_down(v, d, 64); }
+__device__ __forceinline__ cd acc_shfl_down(cd v, int d) {
+    return cd{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
+}
+
+// The B^R positions of block f of a group whose first block digit is j:
+// lam0 (the block's digits zero) plus m * step, m the block-local index
+// (digit j + d at stride B^d).  The padded map lds_phys is additive over
+// numbers with disjoint bits; for a power-of-two radix the block positions
+// and lam0 have disjoint bits, and an odd radix (3, 5) runs unpadded tiles
+// (the map is the identity): phys(lam0 + m * step) = phys(lam0) + phys(m * step).
+template <int B, int R>
+struct BlockGeom {
+    static constexpr int NB = IPow<B, R>::value;
+    uint32_t off[NB];
+    uint32_t Cm, F, bj, bjr;
+    int logC, pad;
+    __device__ __forceinline__ BlockGeom(const PassArgs& a, int j, uint32_t rows) {
+        Cm = (1u << a.logC) - 1u;
+        F = (rows << a.logC) / (uint32_t)NB;
+        bj = (uint32_t)a.bpow[j];
+        bjr = (uint32_t)a.bpow[j + R];
+        logC = a.logC;
+        pad = a.pad_shift;
+        const uint32_t step = bj << a.logC;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) off[m] = lds_phys((uint32_t)m * step, pad);
+    }
+    __device__ __forceinline__ uint32_t base(const PassArgs& a, int j, uint32_t f) const {
+        const uint32_t c = f & Cm;
+        const uint32_t f1 = f >> logC;
+        const uint32_t Q = fdiv(f1, a.divb[j]);
+        return lds_phys(((Q * bjr + (f1 - Q * bj)) << logC) | c, pad);
+    }
+};
+
+// forward over a block: dst = W along digits j..j+R-1 of src (dst may be src)
+template <typename C, int B, int R>
+__device__ __forceinline__ void block_fwd(const C* src, C* dst, const C (&w)[B * B], const PassArgs& a, int j,
+                                          uint32_t rows) {
+    const BlockGeom<B, R> g(a, j, rows);
+    constexpr int NB = BlockGeom<B, R>::NB;
+    for (uint32_t f = threadIdx.x; f < g.F; f += kThreads) {
+        const uint32_t ph0 = g.base(a, j, f);
+        C v[NB];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) v[m] = src[ph0 + g.off[m]];
+        BlockAll<C, B, R, 0>::run(v, w);
+#pragma unroll
+        for (int m = 0; m < NB; ++m) dst[ph0 + g.off[m]] = v[m];
+    }
+}
+
+// gradient sums over the fibres of block digit D (cotangent cv, activation av)
+template <typename C, typename Acc, int B, int R, int D>
+__device__ __forceinline__ void block_gw(const C (&cv)[(IPow<B, R>::value)], const C (&av)[(IPow<B, R>::value)],
+                                         Acc (&acc)[B * B]) {
+    constexpr int st = IPow<B, D>::value;
+    constexpr int NB = IPow<B, R>::value;
+#pragma unroll
+    for (int base = 0; base < NB; ++base) {
+        if ((base / st) % B != 0) continue;  // fibre start: digit D zero
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                acc[r * B + q] = acc_mac_conj(acc[r * B + q], cv[base + r * st], av[base + q * st]);
+    }
+}
+
+// the block's digits from D down to 0: gradient sums, then the adjoint pass
+// (the adjoint of digit 0 only when adj0)
+template <typename C, typename Acc, int B, int R, int D>
+struct BlockRev {
+    __device__ __forceinline__ static void run(C (&cv)[(IPow<B, R>::value)], const C (&acts)[R][(IPow<B, R>::value)],
+                                               const C (&wh)[B * B], Acc (&acc)[B * B], bool adj0) {
+        block_gw<C, Acc, B, R, D>(cv, acts[D], acc);
+        if (D > 0 || adj0) block_digit<C, B, R, D>(cv, wh);
+        BlockRev<C, Acc, B, R, D - 1>::run(cv, acts, wh, acc, adj0);
+    }
+};
+template <typename C, typename Acc, int B, int R>
+struct BlockRev<C, Acc, B, R, -1> {
+    __device__ __forceinline__ static void run(C (&)[(IPow<B, R>::value)], const C (&)[R][(IPow<B, R>::value)],
+                                               const C (&)[B * B], Acc (&)[B * B], bool) {}
+};
+
+// activations inside the block: acts[d + 1] = W along digit d of acts[d]
+template <typename C, int B, int R, int D>
+struct BlockActs {
+    __device__ __forceinline__ static void run(C (&acts)[R][(IPow<B, R>::value)], const C (&w)[B * B]) {
+        if constexpr (D + 1 < R) {
+#pragma unroll
+            for (int m = 0; m < IPow<B, R>::value; ++m) acts[D + 1][m] = acts[D][m];
+            block_digit<C, B, R, D>(acts[D + 1], w);
+            BlockActs<C, B, R, D + 1>::run(acts, w);
+        }
+    }
+};
+
+// gradient sums and adjoint over a block; the cotangent is stored back
+// unless this is block 0 and the group's input cotangent is not wanted
+template <typename C, typename Acc, int B, int R>
+__device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B * B], const C (&wh)[B * B],
+                                             Acc (&acc)[B * B], const PassArgs& a, int j, uint32_t rows,
+                                             bool store) {
+    const BlockGeom<B, R> g(a, j, rows);
+    constexpr int NB = BlockGeom<B, R>::NB;
+    for (uint32_t f = threadIdx.x; f < g.F; f += kThreads) {
+        const uint32_t ph0 = g.base(a, j, f);
+        C acts[R][NB], cv[NB];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            acts[0][m] = act[ph0 + g.off[m]];
+            cv[m] = Ct[ph0 + g.off[m]];
+        }
+        BlockActs<C, B, R, 0>::run(acts, w);
+        BlockRev<C, Acc, B, R, R - 1>::run(cv, acts, wh, acc, store);
+        if (store) {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Ct[ph0 + g.off[m]] = cv[m];
+        }
+    }
+}
+
+template <typename T, int B, int RD>
+__global__ __launch_bounds__(kThreads) void gtt_bwd_block_kernel(BwdArgs ba) {
+    using C = typename Tr<T>::C;
+    using Acc = typename AccOf<C>::type;
+    static_assert(RD >= 1 && RD == bwd_block_digits<C>(B), "digits per block");
+    const PassArgs& a = ba.p;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t tileP = lds_tile_elems(tileE, a.pad_shift);
+    const int wloc = ba.wloc;  // B * B
+    // the layout of gtt_bwd_kernel: [acc][red][W][W^H][slots]
+    unsigned char* pb = smem_raw;
+    pb += bwd_align16((size_t)wloc * sizeof(Acc));
+    Acc* red = reinterpret_cast<Acc*>(pb);
+    pb += (size_t)kThreads * sizeof(Acc);
+    pb += 2 * bwd_align16((size_t)wloc * sizeof(C));
+    C* slot0 = reinterpret_cast<C*>(pb);
+    auto slot = [&](int i) { return slot0 + (size_t)i * tileP; };
+    const C* __restrict__ Wg = static_cast<const C*>(a.W);
+    C w[B * B], wh[B * B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            w[r * B + q] = Wg[r * B + q];
+            wh[r * B + q] = cconj(Wg[q * B + r]);
+        }
+    Acc acc[B * B];
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) acc[e] = acc_zero(Acc{});
+    C* Ct = slot(1);
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, C>(slot(0), a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, C>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
+        __syncthreads();
+        for (int o = 0; o < ba.nops; ++o) {
+            const int op = ba.ops[o];
+            const int kind = op & 3, blk = (op >> 2) & 63, src = (op >> 8) & 15, dst = (op >> 12) & 15;
+            const int j0 = blk * RD;
+            const int r = (a.k - j0) < RD ? (a.k - j0) : RD;
+            if (kind == kOpFwd) {
+                if constexpr (RD >= 4) { if (r == 4) { block_fwd<C, B, 4>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                if constexpr (RD >= 3) { if (r == 3) { block_fwd<C, B, 3>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                if constexpr (RD >= 2) { if (r == 2) { block_fwd<C, B, 2>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                block_fwd<C, B, 1>(slot(src), slot(dst), w, a, j0, rows);
+            } else if (kind == kOpGw) {
+                // the schedule puts the block's adjoint right after its
+                // gradient sweep: both run here; the cotangent at the
+                // group's input (block 0) only when it is stored
+                const bool store = blk != 0 || a.out;
+                if (o + 1 < ba.nops && (ba.ops[o + 1] & 3) == kOpAdj) ++o;
+                if constexpr (RD >= 4) { if (r == 4) { block_gw_adj<C, Acc, B, 4>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
+                if constexpr (RD >= 3) { if (r == 3) { block_gw_adj<C, Acc, B, 3>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
+                if constexpr (RD >= 2) { if (r == 2) { block_gw_adj<C, Acc, B, 2>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
+                block_gw_adj<C, Acc, B, 1>(Ct, slot(src), w, wh, acc, a, j0, rows, store);
+            }
+            // (a lone adjoint never occurs: the host's schedules pair each
+            // block's gradient sweep with its adjoint)
+        done:
+            __syncthreads();
+        }
+        if (a.out) tile_store<T, C>(Ct, a, static_cast<T*>(a.out), t, rows);
+        __syncthreads();
+    }
+    // work-group total, fixed order: lanes by a shuffle tree, then waves
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < B * B; ++e) {
+        Acc v = acc[e];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v = acc_add(v, acc_shfl_down(v, d));
+        if (lane == 0) red[wave * (B * B) + e] = v;
+    }
+    __syncthreads();
+    Acc* part = static_cast<Acc*>(ba.partials) + (size_t)blockIdx.x * ba.wslot;
+    for (int e = threadIdx.x; e < B * B; e += kThreads) {
+        Acc v = red[e];
+        for (int w_ = 1; w_ < kThreads / 64; ++w_) v = acc_add(v, red[w_ * (B * B) + e]);
+        part[e] = v;
+    }
+}
+
 // Fixed-order sum of partial vectors of bb accumulation-type values:
 // work-group w sums the parts of its contiguous range [w*n/G, (w+1)*n/G)
 // (bb <= kThreads: interleaved chains inside the range, then the chains in
@@ -309,23 +549,39 @@ __global__ __launch_bounds__(kThreads) void gtt_reduce_kernel(const Acc* __restr
 
 // Per-storage-type launchers of the backward and of the gW reduction; each
 // bwd_<dtype>.hip translation unit instantiates them for one storage type.
-template <typename T>
-hipError_t launch_bwd_t(const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s) {
-    const void* k = maxb <= 8    ? reinterpret_cast<const void*>(gtt_bwd_kernel<T, 8>)
-                    : maxb <= 16 ? reinterpret_cast<const void*>(gtt_bwd_kernel<T, 16>)
-                                 : reinterpret_cast<const void*>(gtt_bwd_kernel<T, 32>);
-    if (maxb > 32) return hipErrorInvalidValue;
+template <typename K>
+inline hipError_t bwd_launch_one(K kernel, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (maxb <= 8)
-        hipLaunchKernelGGL((gtt_bwd_kernel<T, 8>), dim3(grid), dim3(kThreads), lds, s, a);
-    else if (maxb <= 16)
-        hipLaunchKernelGGL((gtt_bwd_kernel<T, 16>), dim3(grid), dim3(kThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL((gtt_bwd_kernel<T, 32>), dim3(grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, s, a);
     return hipGetLastError();
+}
+
+// radix: > 0 runs the register-block kernel of that radix (every digit uses
+// the one W; the schedule counts blocks of bwd_block_digits digits), 0 the
+// runtime-radix kernel (radices up to maxb)
+template <typename T>
+hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s) {
+    using C = typename Tr<T>::C;
+    if (radix > 0) {
+        constexpr int r2 = bwd_block_digits<C>(2), r3 = bwd_block_digits<C>(3), r4 = bwd_block_digits<C>(4),
+                      r5 = bwd_block_digits<C>(5);
+        switch (radix) {
+            case 2: if constexpr (r2 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 2, (r2 > 0 ? r2 : 1)>, a, grid, lds, s); break;
+            case 3: if constexpr (r3 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 3, (r3 > 0 ? r3 : 1)>, a, grid, lds, s); break;
+            case 4: if constexpr (r4 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 4, (r4 > 0 ? r4 : 1)>, a, grid, lds, s); break;
+            case 5: if constexpr (r5 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 5, (r5 > 0 ? r5 : 1)>, a, grid, lds, s); break;
+            default: break;
+        }
+        return hipErrorInvalidValue;
+    }
+    if (maxb <= 8) return bwd_launch_one(gtt_bwd_kernel<T, 8>, a, grid, lds, s);
+    if (maxb <= 16) return bwd_launch_one(gtt_bwd_kernel<T, 16>, a, grid, lds, s);
+    if (maxb <= 32) return bwd_launch_one(gtt_bwd_kernel<T, 32>, a, grid, lds, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -347,9 +603,11 @@ hipError_t launch_reduce_t(const void* partials, int64_t nparts, int bb, void* o
 // short name used in the launcher symbols, T: the storage type).
 #define GTT_BWD_INSTANTIATE(NAME, T)                                                                     \
     namespace gtt {                                                                                      \
-    hipError_t launch_bwd_##NAME(const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s) { \
-        return launch_bwd_t<T>(a, maxb, grid, lds, s);                                                   \
+    hipError_t launch_bwd_##NAME(const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds,       \
+                                 hipStream_t s) {                                                        \
+        return launch_bwd_t<T>(a, maxb, radix, grid, lds, s);                                            \
     }                                                                                                    \
+    int bwd_block_digits_##NAME(int b) { return bwd_block_digits<typename Tr<T>::C>(b); }              \
     hipError_t launch_reduce_##NAME(const void* partials, int64_t nparts, int bb, void* out,            \
                                     hipStream_t s) {                                                     \
         return launch_reduce_t<T>(partials, nparts, bb, out, s);                                         \

@@ -194,7 +194,11 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
                     lo += rad[G.s0 + j] * rad[G.s0 + j];
                 }
             }
-            if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, grid, bwd_lds_bytes(G, dt), s) != hipSuccess)
+            // the register-block kernel when the plan chose it (one W for
+            // every digit; its schedule counts blocks)
+            const int radix = (shared_w && G.bwd_rd > 0) ? rad[G.s0] : 0;
+            if (!shared_w && G.bwd_rd > 0) return GTT_ERR_INTERNAL;
+            if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, radix, grid, bwd_lds_bytes(G, dt), s) != hipSuccess)
                 return GTT_ERR_HIP;
         }
         if (tp && tp->timing.enabled) {

@@ -11,12 +11,18 @@ hipError_t launch_pass_bf16(int, int, const PassArgs&, unsigned, size_t, hipStre
 hipError_t launch_pass_f16(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 hipError_t launch_pass_i32(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 
-hipError_t launch_bwd_f64(const BwdArgs&, int, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_f32(const BwdArgs&, int, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_c128(const BwdArgs&, int, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_c64(const BwdArgs&, int, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_bf16(const BwdArgs&, int, unsigned, size_t, hipStream_t);
-hipError_t launch_bwd_f16(const BwdArgs&, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f64(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_f64(int);
+hipError_t launch_bwd_f32(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_f32(int);
+hipError_t launch_bwd_c128(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_c128(int);
+hipError_t launch_bwd_c64(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_c64(int);
+hipError_t launch_bwd_bf16(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_bf16(int);
+hipError_t launch_bwd_f16(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+int bwd_block_digits_f16(int);
 hipError_t launch_reduce_f64(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_f32(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_c128(const void*, int64_t, int, void*, hipStream_t);
@@ -24,14 +30,26 @@ hipError_t launch_reduce_c64(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_bf16(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_f16(const void*, int64_t, int, void*, hipStream_t);
 
-hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s) {
+int bwd_block_digits(DT dt, int b) {
     switch (dt) {
-        case DT::F64: return launch_bwd_f64(a, maxb, grid, lds, s);
-        case DT::F32: return launch_bwd_f32(a, maxb, grid, lds, s);
-        case DT::C128: return launch_bwd_c128(a, maxb, grid, lds, s);
-        case DT::C64: return launch_bwd_c64(a, maxb, grid, lds, s);
-        case DT::BF16: return launch_bwd_bf16(a, maxb, grid, lds, s);
-        case DT::F16: return launch_bwd_f16(a, maxb, grid, lds, s);
+        case DT::F64: return bwd_block_digits_f64(b);
+        case DT::F32: return bwd_block_digits_f32(b);
+        case DT::C128: return bwd_block_digits_c128(b);
+        case DT::C64: return bwd_block_digits_c64(b);
+        case DT::BF16: return bwd_block_digits_bf16(b);
+        case DT::F16: return bwd_block_digits_f16(b);
+        default: return 0;
+    }
+}
+
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s) {
+    switch (dt) {
+        case DT::F64: return launch_bwd_f64(a, maxb, radix, grid, lds, s);
+        case DT::F32: return launch_bwd_f32(a, maxb, radix, grid, lds, s);
+        case DT::C128: return launch_bwd_c128(a, maxb, radix, grid, lds, s);
+        case DT::C64: return launch_bwd_c64(a, maxb, radix, grid, lds, s);
+        case DT::BF16: return launch_bwd_bf16(a, maxb, radix, grid, lds, s);
+        case DT::F16: return launch_bwd_f16(a, maxb, radix, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
 }

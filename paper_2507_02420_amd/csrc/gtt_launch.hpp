@@ -64,8 +64,14 @@ constexpr int kKindCMfma = 3;    // complex64, radix 8, FP32 matrix cores
 hipError_t launch_pass(DT dt, int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s);
 
 struct BwdArgs;
-// backward of one digit group (runtime radices <= maxb <= 32, floating dtypes)
-hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, unsigned grid, size_t lds, hipStream_t s);
+// backward of one digit group, floating dtypes: radix > 0 runs the
+// register-block kernel of that radix (one W for every digit; the schedule
+// counts blocks of bwd_block_digits digits), 0 the runtime-radix kernel
+// (radices up to maxb <= 32)
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s);
+// digits per register block of the radix-b backward kernel for dtype dt (0:
+// no such kernel)
+int bwd_block_digits(DT dt, int b);
 // gW = fixed-order sum of nparts partial vectors of bb accumulation-dtype
 // values (FP64 / complex FP64), written in the compute dtype
 hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s);

@@ -42,6 +42,7 @@ struct Group {
     // radix-8 matrix-core one): LDS tiles per work-group, the checkpoint
     // schedule run on them, the largest radix and the staged matrix entries
     int bwd_slots = 0;
+    int bwd_rd = 0;      // > 0: register-block kernel, schedule over blocks of bwd_rd digits
     int bwd_maxb = 0;
     int bwd_wloc = 0;
     bool bwd_ok = true;  // false: this build has no backward for the group

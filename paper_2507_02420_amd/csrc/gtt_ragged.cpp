@@ -485,12 +485,14 @@ std::string describe_plan(const gtt_plan_s* p) {
                       "{\"s0\":%d,\"k\":%d,\"S\":%lld,\"G\":%lld,\"C\":%d,\"P\":%d,\"L\":%lld,\"tiles\":%lld,"
                       "\"tile_elems\":%lld,\"mode\":%d,\"pad_shift\":%d,\"kind\":\"%s\",\"lds_bytes\":%zu,"
                       "\"fast_ni\":%d,\"fmap\":%llu,\"pmap\":%u,\"fast_conflicts\":%d,\"bwd_slots\":%d,"
-                      "\"bwd_ops\":%d,\"bwd_fwd_passes\":%d,\"bwd_ok\":%s,\"bwd_schedule\":[",
+                      "\"bwd_ops\":%d,\"bwd_fwd_passes\":%d,\"bwd_ok\":%s,\"bwd_rd\":%d,\"bwd_schedule\":[",
                       g.s0, g.k, (long long)g.S, (long long)g.G, g.C, g.P, (long long)g.L, (long long)g.ntiles,
                       (long long)g.tileE, g.mode, g.pad_shift, g.kind == 0 ? "valu" : g.kind == 1 ? "generic" : g.kind == 2 ? "mfma" : "cmfma",
                       g.lds_bytes, g.fast_ni, (unsigned long long)g.fmap, g.pmap, g.fast_conflicts, g.bwd_slots,
-                      (int)g.bwd_ops.size(), g.bwd_slots ? bwd_fwd_passes(g.k, g.bwd_slots - 2) : 0,
-                      g.bwd_ok ? "true" : "false");
+                      (int)g.bwd_ops.size(),
+                      g.bwd_slots ? bwd_fwd_passes(g.bwd_rd > 0 ? (g.k + g.bwd_rd - 1) / g.bwd_rd : g.k, g.bwd_slots - 2)
+                                  : 0,
+                      g.bwd_ok ? "true" : "false", g.bwd_rd);
         std::string r(b);
         for (size_t i = 0; i < g.bwd_ops.size(); ++i) r += (i ? "," : "") + std::to_string((int)g.bwd_ops[i]);
         return r + "]}";

@@ -79,7 +79,9 @@ def test_backward_schedules_replay(b, n, batch, dtype):
         if g["kind"] == "cmfma":
             continue
         assert g["bwd_ok"], g
-        k, slots = g["k"], g["bwd_slots"]
+        # the register-block kernel schedules blocks of bwd_rd digits
+        k = -(-g["k"] // g["bwd_rd"]) if g["bwd_rd"] else g["k"]
+        slots = g["bwd_slots"]
         assert 2 <= slots <= 16 and (slots >= 3 or k == 1)
         fwd = replay(k, slots, g["bwd_schedule"])
         assert fwd == g["bwd_fwd_passes"]
@@ -91,16 +93,19 @@ def test_backward_schedules_replay(b, n, batch, dtype):
 
 
 def test_five_digit_group_is_linear():
-    # a 5-digit group of float32 and bf16 data: every activation computed
-    # once, k - 1 forward and k adjoint passes (2k - 1 digit passes a tile)
+    # a 5-digit group of float32 and bf16 data: every activation (at the
+    # start of a register block of 2 digits) computed once; at most 2k - 1
+    # LDS passes a tile (here 2 forward and 3 gradient / adjoint passes)
     for dtype in (torch.float32, torch.bfloat16):
         d = G.Plan(4, 5, 3, dtype).describe()
         (g,) = d["bwd_groups"]
-        assert g["k"] == 5 and g["bwd_slots"] == 6
+        units = -(-g["k"] // g["bwd_rd"]) if g["bwd_rd"] else g["k"]
+        assert g["k"] == 5 and g["bwd_slots"] == units + 1
         ops = [decode(o) for o in g["bwd_schedule"]]
         fwd = sum(1 for o in ops if o[0] == FWD)
         adj = sum(1 for o in ops if o[0] == ADJ)
-        assert fwd + adj == 2 * 5 - 1
+        assert fwd == units - 1 and adj == units
+        assert fwd + adj <= 2 * 5 - 1
 
 
 def test_mixed_radix_plans_have_backward_schedules():
@@ -109,10 +114,44 @@ def test_mixed_radix_plans_have_backward_schedules():
         d = p.describe()
         assert len(d["bwd_groups"]) == len(d["groups"])
         for g in d["bwd_groups"]:
-            assert g["bwd_ok"]
+            assert g["bwd_ok"] and g["bwd_rd"] == 0
             replay(g["k"], g["bwd_slots"], g["bwd_schedule"])
 
 
 def test_radix_above_32_has_no_backward():
     d = G.Plan(33, 2, 1, torch.float32).describe()
     assert not all(g["bwd_ok"] for g in d["bwd_groups"])
+
+
+def _phys(x, ps):
+    return x + (x >> (ps & 31)) + (x >> ((ps >> 8) & 31)) + (x >> ((ps >> 16) & 31))
+
+
+@pytest.mark.parametrize("b,n,batch,dtype", [(2, 13, 2, torch.float32), (2, 20, 16, torch.float32),
+                                             (4, 10, 64, torch.float32), (4, 10, 64, torch.complex64),
+                                             (3, 13, 16, torch.float32), (5, 6, 2, torch.float64),
+                                             (4, 8, 2, torch.bfloat16), (2, 12, 3, torch.complex128)], ids=str)
+def test_radix_backward_lds_offsets_are_additive(b, n, batch, dtype):
+    # the register-block backward addresses position m of a block (its
+    # digits j0 .. j0+r-1) as phys(lam0) + phys(m * step); check it against
+    # phys(lam0 + m * step) for every block of every planned tile
+    d = G.Plan(b, n, batch, dtype).describe()
+    for g in d["bwd_groups"]:
+        rd = g["bwd_rd"]
+        if g["kind"] == "cmfma" or rd == 0:
+            continue
+        ps, logC = g["pad_shift"], (g["C"]).bit_length() - 1
+        rows = g["P"] * g["G"]
+        for j0 in range(0, g["k"], rd):
+            r = min(rd, g["k"] - j0)
+            nb = b ** r
+            bj, bjr = b ** j0, b ** (j0 + r)
+            step = bj << logC
+            off = [_phys(m * step, ps) for m in range(nb)]
+            for f in range((rows << logC) // nb):
+                c, f1 = f & ((1 << logC) - 1), f >> logC
+                Q = f1 // bj
+                lam0 = ((Q * bjr + (f1 - Q * bj)) << logC) | c
+                base = _phys(lam0, ps)
+                for m in range(nb):
+                    assert base + off[m] == _phys(lam0 + m * step, ps), (j0, f, m)
