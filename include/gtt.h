@@ -305,8 +305,9 @@ gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len);
  *                      limit beyond the tile size),
  *   bwd_lds_bytes    : LDS bytes of one work-group of the general backward
  *                      (tiles and checkpoint slots; 0 = default search).
- * An entry with all four values 0 restores the defaults.  Process-wide; not
- * thread-safe against concurrent gtt_plan calls.
+ * All four values 0 removes the entry for (b, n, dtype) (the radix-wide
+ * entry or the defaults apply again).  Process-wide; not thread-safe against
+ * concurrent gtt_plan calls.
  */
 gtt_status gtt_set_tuning(int32_t b, int32_t n, gtt_dtype dtype, int32_t lds_budget_bytes, int32_t min_row_bytes,
                           int32_t max_group_digits, int32_t bwd_lds_bytes);

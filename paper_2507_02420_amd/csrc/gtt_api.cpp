@@ -842,14 +842,23 @@ gtt_status gtt_set_tuning(int32_t b, int32_t n, gtt_dtype dtype, int32_t lds_bud
         bwd_lds_bytes < 0 || bwd_lds_bytes > 160 * 1024)
         return GTT_ERR_INVALID_VALUE;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (auto& e : g_tune)
+    // all zeros: remove the entry (so that it no longer shadows the radix-wide one)
+    const bool clear = !lds_budget_bytes && !min_row_bytes && !max_group_digits && !bwd_lds_bytes;
+    for (size_t i = 0; i < g_tune.size(); ++i) {
+        TuneEntry& e = g_tune[i];
         if (e.b == b && e.n == n && e.dtype == (int)dtype) {
+            if (clear) {
+                g_tune.erase(g_tune.begin() + (long)i);
+                return GTT_OK;
+            }
             e.lds_budget = lds_budget_bytes;
             e.min_row_bytes = min_row_bytes;
             e.max_group_digits = max_group_digits;
             e.bwd_lds = bwd_lds_bytes;
             return GTT_OK;
         }
+    }
+    if (clear) return GTT_OK;
     g_tune.push_back(
         TuneEntry{b, n, (int)dtype, lds_budget_bytes, min_row_bytes, max_group_digits, bwd_lds_bytes});
     return GTT_OK;

@@ -97,11 +97,12 @@ def test_tuning_validation():
 
 
 def test_tuning_changes_split_and_not_results():
-    G.set_tuning(8, torch.complex64, 0, 0, 3)
+    G.set_tuning(8, torch.complex64, 0, 0, 3, n=6)
     try:
         ks = [g["k"] for g in G.Plan(8, 6, 256, torch.complex64).describe()["groups"]]
     finally:
-        G.set_tuning(8, torch.complex64, 0, 0, 0)
+        G.set_tuning(8, torch.complex64, 0, 0, 0, n=6)
+        G.load_tuning()
     assert ks == [3, 3]
     ks = [g["k"] for g in G.Plan(8, 6, 256, torch.complex64).describe()["groups"]]
     assert ks == [4, 2]
@@ -466,6 +467,7 @@ def test_tuning_per_digit_count_and_backward_budget():
     finally:
         G.set_tuning(8, torch.complex64, 0, 0, 0, n=5)
         G.set_tuning(8, torch.complex64, 0, 0, 0)
+        G.load_tuning()
     assert k6 == [3, 3] and max(k5) <= 2 and sum(k5) == 5
     base = G.Plan(4, 5, 3, torch.float32).describe()["bwd_groups"][0]
     G.set_tuning(4, torch.float32, 0, 0, 0, n=5, bwd_lds_bytes=16 * 1024)
@@ -473,6 +475,7 @@ def test_tuning_per_digit_count_and_backward_budget():
         g = G.Plan(4, 5, 3, torch.float32).describe()["bwd_groups"][0]
     finally:
         G.set_tuning(4, torch.float32, 0, 0, 0, n=5)
+        G.load_tuning()
     units = -(-base["k"] // base["bwd_rd"])
     assert base["bwd_slots"] == units + 1
     assert g["bwd_ok"] and 3 <= g["bwd_slots"] < units + 1 and g["bwd_fwd_passes"] > base["bwd_fwd_passes"]

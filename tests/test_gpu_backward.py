@@ -73,12 +73,13 @@ def test_backward_boundary_slots_of_odd_length(dtype, use_saved):
     # saved / workspace buffer whose stride is rounded up to 256 bytes
     b, n = 3, 7
     say(f"backward odd-length slots dtype={dtype} saved={use_saved}")
-    G.set_tuning(b, dtype, 0, 0, 2)
+    G.set_tuning(b, dtype, 0, 0, 2, n=n)
     try:
         gx, gW, rgx, rgW = _grad_case(b, n, 1, dtype, seed=6100, use_saved=use_saved)
         assert len(G.Plan(b, n, 1, dtype).describe()["groups"]) == 4
     finally:
-        G.set_tuning(b, dtype, 0, 0, 0)
+        G.set_tuning(b, dtype, 0, 0, 0, n=n)
+        G.load_tuning()
     assert rel_err(gx, rgx) < TOL[dtype]
     assert np.linalg.norm(gW - rgW) / np.linalg.norm(rgW) < TOL[dtype]
 

@@ -252,11 +252,12 @@ def test_mfma_small_tiles_scalar_rows(b, n, batch, dtype):
     # few elements, moved element by element instead of as 16-byte vectors
     say(f"mfma small tiles b={b} n={n} batch={batch} dtype={dtype}")
     x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=7300 + b + n)
-    G.set_tuning(b, dtype, 128, 0, 0)
+    G.set_tuning(b, dtype, 128, 0, 0, n=n)
     try:
         plan = G.Plan(b, n, batch, dtype)
     finally:
-        G.set_tuning(b, dtype, 0, 0, 0)
+        G.set_tuning(b, dtype, 0, 0, 0, n=n)
+        G.load_tuning()          # the table's entry for (b, n), if any
     groups = plan.describe()["groups"]
     assert all(g["kind"] == "mfma" for g in groups)
     assert any(g["mode"] in (1, 3) for g in groups), groups  # a scalar mode
