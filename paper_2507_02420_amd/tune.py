@@ -9,9 +9,10 @@ and storage dtype) and timed with HIP events on the GPU:
               budgets (LDS bytes per tile), least row widths of strided
               digit groups and most digits per group;
   ragged   -- for each distinct (b, n) of the 1024-instance bf16 shape list
-              (b in {2, 4, 16, 32}, N in [2^10, 2^20]) the same grid, timed
-              on a ragged plan holding just that shape's instances (the
-              ragged class kernels, with as many instances as the list has);
+              (b in {2, 4, 16, 32}, N in [2^10, 2^20]) in turn, the same
+              grid, judged by the time of the radix class inside the whole
+              batch (coordinate descent: a kept entry stays in place for the
+              shapes tuned after it);
   backward -- for shapes that run the general backward kernel, the LDS
               budget of one backward work-group (which sets how many tiles
               of checkpointed activations it holds).
@@ -156,30 +157,76 @@ def tune_forward(name, b, n, batch, dtype, budgets, rows, maxd, log):
     return e
 
 
-def tune_ragged_shapes(budgets, rows, maxd, log):
-    """Per distinct (b, n) of the 1024-instance bf16 list: a ragged plan of
-    that shape's instances only, timed per candidate tiling."""
+def tune_ragged_shapes(budgets, rows, maxd, log, iters=10):
+    """Per distinct (b, n) of the 1024-instance bf16 list, in turn: each
+    candidate tiling of that shape is timed inside the whole batch (the class
+    kernels of radix b run every instance of that radix together, so a
+    shape's tiling is judged by its radix class's time in the batch); an
+    entry is kept when it beats the class time without it by 2 %."""
     dev = torch.device("cuda")
     shapes = ragged_shapes(1024, seed=52)
+    bs, ns = [b for b, _ in shapes], [n for _, n in shapes]
+    total = sum(b ** n for b, n in shapes)
+    x = _data((total,), torch.bfloat16, dev)
+    W = torch.cat([_w(r, torch.bfloat16, dev) for r in (2, 4, 16, 32)])
+    y = torch.empty_like(x)
+
+    def class_ms(b):
+        p = G.Plan(bs, ns, 1, torch.bfloat16)
+        p.forward(W, x, y)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(iters):
+            p.timing(True)
+            p.forward(W, x, y)
+            tm = p.timing_read()
+            p.timing(False)
+            key = f" mfma b={b}" if b >= 16 else f" b={b}"
+            ts.append(sum(v["total_ms"] for k, v in tm.items() if k.endswith(key)))
+        ts.sort()
+        return ts[len(ts) // 2]
+
     counts = {}
-    for s in shapes:
-        counts[s] = counts.get(s, 0) + 1
+    for sh in shapes:
+        counts[sh] = counts.get(sh, 0) + 1
     out = []
     for (b, n), c in sorted(counts.items()):
-        N = b ** n
-        x = _data((c * N,), torch.bfloat16, dev)
-        W = _w(b, torch.bfloat16, dev)
-        y = torch.empty_like(x)
-
-        def make(fl, b=b, n=n, c=c):
-            return G.Plan([b] * c, [n] * c, 1, torch.bfloat16, flags=fl)
-
-        e = _grid_search(b, n, torch.bfloat16, make,
-                         lambda p, W=W, x=x, y=y: _median_ms(lambda: p.forward(W, x, y)), budgets, rows, maxd, log,
-                         uniform=False)
-        e.update({"search": "ragged", "workload": f"{c} bf16 instances b={b} n={n} of the 1024-instance list",
-                  "b": b, "n": n, "batch": c, "dtype": "bf16", "bwd_lds": 0})
-        out.append(e)
+        G.set_tuning(b, torch.bfloat16, 0, 0, 0, n=n)
+        base = class_ms(b)
+        base_desc = _tiling(b, n, torch.bfloat16)
+        best = {"ms": base, "lds_budget": 0, "min_row_bytes": 0, "max_group_digits": 0, "groups": base_desc}
+        seen = {base_desc}
+        for bud in budgets:
+            for mr in rows:
+                for mk in maxd:
+                    G.set_tuning(b, torch.bfloat16, bud, mr, mk, n=n)
+                    try:
+                        desc = _tiling(b, n, torch.bfloat16)
+                        if desc in seen:
+                            continue
+                        seen.add(desc)
+                        ms = class_ms(b)
+                    except G.GTTError:       # e.g. more digit groups than a ragged plan takes
+                        continue
+                    if ms < best["ms"]:
+                        best = {"ms": ms, "lds_budget": bud, "min_row_bytes": mr, "max_group_digits": mk,
+                                "groups": desc}
+        override = bool(best["groups"] != base_desc and best["ms"] < 0.98 * base)
+        # keep the winner in place for the shapes tuned after this one
+        if override:
+            G.set_tuning(b, torch.bfloat16, best["lds_budget"], best["min_row_bytes"], best["max_group_digits"], n=n)
+        else:
+            G.set_tuning(b, torch.bfloat16, 0, 0, 0, n=n)
+        log(f"  b={b} n={n} bf16 ({c} instances): class time {base:.4f} ms with the heuristic, {best['ms']:.4f} ms "
+            f"best{' -> override' if override else ''}")
+        out.append({"search": "ragged", "workload": f"radix-{b} class of the 1024-instance bf16 list, shape n={n} "
+                                                    f"({c} instances)",
+                    "b": b, "n": n, "batch": c, "dtype": "bf16", "bwd_lds": 0, "ms": best["ms"],
+                    "heuristic_ms": base, "lds_budget": best["lds_budget"], "min_row_bytes": best["min_row_bytes"],
+                    "max_group_digits": best["max_group_digits"], "groups": best["groups"],
+                    "heuristic_groups": base_desc, "override": override})
+    for e in out:
+        G.set_tuning(e["b"], torch.bfloat16, 0, 0, 0, n=e["n"])
     return out
 
 
