@@ -298,6 +298,29 @@ def _dominant_entry(tm, E):
             "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
 
 
+def _backward_entry(p, W, x, iters=10, seed=7):
+    """Forward keeping the activations between digit groups, then the
+    backward (gx and gW) of the same plan, timed alone: elements/s and HBM
+    rate of the algorithmic bytes (read gy and x, write gx: 3 E s)."""
+    import torch
+    from paper_2507_02420_amd.inputs import gaussian
+    g = torch.from_numpy(gaussian(tuple(x.shape), seed=seed, complex_=x.is_complex()).astype(
+        np.complex64 if x.is_complex() else np.float32)).to(x.device).to(x.dtype)
+    _, _, sv = p.workspace_size()
+    saved = torch.empty(max(sv, 16), dtype=torch.uint8, device=x.device)
+    y = torch.empty_like(x)
+    p.forward(W, x, y, saved=saved)
+    gx = torch.empty_like(x)
+    gW = torch.empty_like(W)
+    ms, tm = _timed_plan(p, lambda: p.backward(W, x, g, saved=saved, gx=gx, gW=gW), iters)
+    E = x.numel()
+    alg = 3.0 * E * x.element_size()
+    bw = {k: v for k, v in tm.items() if k.startswith("bwd")}
+    return {"ms": ms, "elements_per_s": E / (ms * 1e-3), "algorithmic_bytes": alg,
+            "algorithmic_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "round_trips": len(p.describe()["bwd_groups"]), **_dominant_entry(bw, E), "kernels": tm}
+
+
 def wl_c1(iters=50, cpu=True):
     """Single FP64 vector, b=2, n=10: normalised Hadamard and a random 2x2
     orthogonal W; latency-bound (one work-group)."""
@@ -340,7 +363,7 @@ def wl_c2(iters=10, cpu=True):
     E = batch * b ** n
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
     e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
-         "kernels": tm}
+         "kernels": tm, "backward": _backward_entry(p, W, x)}
     if cpu:
         from oracle import gtt_oracle as O
         W64 = W.cpu().to(torch.complex128).numpy()
@@ -369,7 +392,7 @@ def wl_c3a(iters=10, cpu=True):
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
     E = batch * b ** n
     e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
-         "kernels": tm}
+         "kernels": tm, "backward": _backward_entry(p, W, x)}
     if cpu:
         from oracle import gtt_oracle as O
         W64 = W.cpu().double().numpy()
