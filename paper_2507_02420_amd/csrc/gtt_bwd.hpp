@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
 //     of the digit's fibres into the thread's FP64 accumulators and apply
 //     W^H along the digit to the cotangent in registers; store the cotangent
 //     (again one LDS round trip for r digits).
-// W and W^H live in registers; the accumulators too, for the whole launch
+// W lives in registers (the adjoint passes read it transposed and
+// conjugated); the accumulators too, for the whole launch
 // (every block a thread owns, tile after tile, in order), and are summed
 // over the work-group once at the end: over the lanes of a wave by a fixed
 // shuffle tree, then over the waves in order.
@@ -329,13 +330,14 @@ struct BlockGeom {
     }
 };
 
-// forward over a block: dst = W along digits j..j+R-1 of src (dst may be src)
-template <typename C, int B, int R>
+// forward over a block: dst = W along digits j..j+R-1 of src (dst may be src);
+// NT threads
+template <typename C, int B, int R, int NT>
 __device__ __forceinline__ void block_fwd(const C* src, C* dst, const C (&w)[B * B], const PassArgs& a, int j,
                                           uint32_t rows) {
     const BlockGeom<B, R> g(a, j, rows);
     constexpr int NB = BlockGeom<B, R>::NB;
-    for (uint32_t f = threadIdx.x; f < g.F; f += kThreads) {
+    for (uint32_t f = threadIdx.x; f < g.F; f += NT) {
         const uint32_t ph0 = g.base(a, j, f);
         C v[NB];
 #pragma unroll
@@ -368,10 +370,10 @@ __device__ __forceinline__ void block_gw(const C (&cv)[(IPow<B, R>::value)], con
 template <typename C, typename Acc, int B, int R, int D>
 struct BlockRev {
     __device__ __forceinline__ static void run(C (&cv)[(IPow<B, R>::value)], const C (&acts)[R][(IPow<B, R>::value)],
-                                               const C (&wh)[B * B], Acc (&acc)[B * B], bool adj0) {
+                                               const C (&w)[B * B], Acc (&acc)[B * B], bool adj0) {
         block_gw<C, Acc, B, R, D>(cv, acts[D], acc);
-        if (D > 0 || adj0) block_digit<C, B, R, D>(cv, wh);
-        BlockRev<C, Acc, B, R, D - 1>::run(cv, acts, wh, acc, adj0);
+        if (D > 0 || adj0) block_digit_adj<C, B, R, D>(cv, w);
+        BlockRev<C, Acc, B, R, D - 1>::run(cv, acts, w, acc, adj0);
     }
 };
 template <typename C, typename Acc, int B, int R>
@@ -395,13 +397,12 @@ struct BlockActs {
 
 // gradient sums and adjoint over a block; the cotangent is stored back
 // unless this is block 0 and the group's input cotangent is not wanted
-template <typename C, typename Acc, int B, int R>
-__device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B * B], const C (&wh)[B * B],
-                                             Acc (&acc)[B * B], const PassArgs& a, int j, uint32_t rows,
-                                             bool store) {
+template <typename C, typename Acc, int B, int R, int NT>
+__device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B * B], Acc (&acc)[B * B],
+                                             const PassArgs& a, int j, uint32_t rows, bool store) {
     const BlockGeom<B, R> g(a, j, rows);
     constexpr int NB = BlockGeom<B, R>::NB;
-    for (uint32_t f = threadIdx.x; f < g.F; f += kThreads) {
+    for (uint32_t f = threadIdx.x; f < g.F; f += NT) {
         const uint32_t ph0 = g.base(a, j, f);
         C acts[R][NB], cv[NB];
 #pragma unroll
@@ -410,7 +411,7 @@ __device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B
             cv[m] = Ct[ph0 + g.off[m]];
         }
         BlockActs<C, B, R, 0>::run(acts, w);
-        BlockRev<C, Acc, B, R, R - 1>::run(cv, acts, wh, acc, store);
+        BlockRev<C, Acc, B, R, R - 1>::run(cv, acts, w, acc, store);
         if (store) {
 #pragma unroll
             for (int m = 0; m < NB; ++m) Ct[ph0 + g.off[m]] = cv[m];
@@ -418,11 +419,16 @@ __device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B
     }
 }
 
-template <typename T, int B, int RD>
-__global__ __launch_bounds__(kThreads) void gtt_bwd_block_kernel(BwdArgs ba) {
+// NT threads per work-group (256, 512 or 1024): the host picks the size
+// whose resident waves are the most for the tile's LDS (a large tile leaves
+// room for one or two work-groups per compute unit)
+template <typename T, int B, int RD, int NT>
+__global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
     using C = typename Tr<T>::C;
     using Acc = typename AccOf<C>::type;
     static_assert(RD >= 1 && RD == bwd_block_digits<C>(B), "digits per block");
+    static_assert(NT % 64 == 0 && NT <= 1024 && (NT / 64) * B * B <= kThreads,
+                  "the per-wave sums fit the reduction area (kThreads entries)");
     const PassArgs& a = ba.p;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
@@ -438,21 +444,18 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_block_kernel(BwdArgs ba) {
     C* slot0 = reinterpret_cast<C*>(pb);
     auto slot = [&](int i) { return slot0 + (size_t)i * tileP; };
     const C* __restrict__ Wg = static_cast<const C*>(a.W);
-    C w[B * B], wh[B * B];
+    // W only (uniform: scalar registers); the adjoint passes read it
+    // transposed and conjugated
+    C w[B * B];
 #pragma unroll
-    for (int r = 0; r < B; ++r)
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-            w[r * B + q] = Wg[r * B + q];
-            wh[r * B + q] = cconj(Wg[q * B + r]);
-        }
+    for (int e = 0; e < B * B; ++e) w[e] = Wg[e];
     Acc acc[B * B];
 #pragma unroll
     for (int e = 0; e < B * B; ++e) acc[e] = acc_zero(Acc{});
     C* Ct = slot(1);
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(slot(0), a, static_cast<const T*>(a.in), t, rows);
-        tile_load<T, C>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
+        tile_load<T, C, NT>(slot(0), a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, C, NT>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
         __syncthreads();
         for (int o = 0; o < ba.nops; ++o) {
             const int op = ba.ops[o];
@@ -460,27 +463,27 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_block_kernel(BwdArgs ba) {
             const int j0 = blk * RD;
             const int r = (a.k - j0) < RD ? (a.k - j0) : RD;
             if (kind == kOpFwd) {
-                if constexpr (RD >= 4) { if (r == 4) { block_fwd<C, B, 4>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
-                if constexpr (RD >= 3) { if (r == 3) { block_fwd<C, B, 3>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
-                if constexpr (RD >= 2) { if (r == 2) { block_fwd<C, B, 2>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
-                block_fwd<C, B, 1>(slot(src), slot(dst), w, a, j0, rows);
+                if constexpr (RD >= 4) { if (r == 4) { block_fwd<C, B, 4, NT>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                if constexpr (RD >= 3) { if (r == 3) { block_fwd<C, B, 3, NT>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                if constexpr (RD >= 2) { if (r == 2) { block_fwd<C, B, 2, NT>(slot(src), slot(dst), w, a, j0, rows); goto done; } }
+                block_fwd<C, B, 1, NT>(slot(src), slot(dst), w, a, j0, rows);
             } else if (kind == kOpGw) {
                 // the schedule puts the block's adjoint right after its
                 // gradient sweep: both run here; the cotangent at the
                 // group's input (block 0) only when it is stored
                 const bool store = blk != 0 || a.out;
                 if (o + 1 < ba.nops && (ba.ops[o + 1] & 3) == kOpAdj) ++o;
-                if constexpr (RD >= 4) { if (r == 4) { block_gw_adj<C, Acc, B, 4>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
-                if constexpr (RD >= 3) { if (r == 3) { block_gw_adj<C, Acc, B, 3>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
-                if constexpr (RD >= 2) { if (r == 2) { block_gw_adj<C, Acc, B, 2>(Ct, slot(src), w, wh, acc, a, j0, rows, store); goto done; } }
-                block_gw_adj<C, Acc, B, 1>(Ct, slot(src), w, wh, acc, a, j0, rows, store);
+                if constexpr (RD >= 4) { if (r == 4) { block_gw_adj<C, Acc, B, 4, NT>(Ct, slot(src), w, acc, a, j0, rows, store); goto done; } }
+                if constexpr (RD >= 3) { if (r == 3) { block_gw_adj<C, Acc, B, 3, NT>(Ct, slot(src), w, acc, a, j0, rows, store); goto done; } }
+                if constexpr (RD >= 2) { if (r == 2) { block_gw_adj<C, Acc, B, 2, NT>(Ct, slot(src), w, acc, a, j0, rows, store); goto done; } }
+                block_gw_adj<C, Acc, B, 1, NT>(Ct, slot(src), w, acc, a, j0, rows, store);
             }
             // (a lone adjoint never occurs: the host's schedules pair each
             // block's gradient sweep with its adjoint)
         done:
             __syncthreads();
         }
-        if (a.out) tile_store<T, C>(Ct, a, static_cast<T*>(a.out), t, rows);
+        if (a.out) tile_store<T, C, false, NT>(Ct, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
     // work-group total, fixed order: lanes by a shuffle tree, then waves
@@ -494,9 +497,9 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_block_kernel(BwdArgs ba) {
     }
     __syncthreads();
     Acc* part = static_cast<Acc*>(ba.partials) + (size_t)blockIdx.x * ba.wslot;
-    for (int e = threadIdx.x; e < B * B; e += kThreads) {
+    for (int e = threadIdx.x; e < B * B; e += NT) {
         Acc v = red[e];
-        for (int w_ = 1; w_ < kThreads / 64; ++w_) v = acc_add(v, red[w_ * (B * B) + e]);
+        for (int w_ = 1; w_ < NT / 64; ++w_) v = acc_add(v, red[w_ * (B * B) + e]);
         part[e] = v;
     }
 }
@@ -550,38 +553,99 @@ __global__ __launch_bounds__(kThreads) void gtt_reduce_kernel(const Acc* __restr
 // Per-storage-type launchers of the backward and of the gW reduction; each
 // bwd_<dtype>.hip translation unit instantiates them for one storage type.
 template <typename K>
-inline hipError_t bwd_launch_one(K kernel, const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+inline hipError_t bwd_launch_one(K kernel, const BwdArgs& a, unsigned grid, unsigned threads, size_t lds,
+                                 hipStream_t s) {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
+// Resident waves per compute unit of a kernel at NT threads and `lds` bytes
+// of LDS; 0 when it cannot run or spills to scratch.
+template <typename K>
+inline int bwd_resident_waves(K kernel, int nt, size_t lds) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+    if (fa.localSizeBytes > 0 || fa.maxThreadsPerBlock < nt) return 0;
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, nt, lds) != hipSuccess) return 0;
+    return blocks * nt / 64;
+}
+
+// The register-block kernels of radix B at 256, 512 and 1024 threads (1024
+// only where the per-wave sums fit the reduction area)
+template <typename T, int B, int RD>
+struct BwdBlockKernels {
+    static constexpr bool k1024 = 16 * B * B <= kThreads;
+    static auto get(int nt) {
+        if (nt == 1024) return gtt_bwd_block_kernel<T, B, RD, k1024 ? 1024 : 512>;
+        if (nt == 512) return gtt_bwd_block_kernel<T, B, RD, 512>;
+        return gtt_bwd_block_kernel<T, B, RD, 256>;
+    }
+    // the work-group size with the most resident waves for this LDS
+    // (ties: the smaller work-group)
+    static int threads(size_t lds) {
+        int best = kThreads, bw = bwd_resident_waves(get(kThreads), kThreads, lds);
+        for (int nt : {512, 1024}) {
+            if (nt == 1024 && !k1024) continue;
+            const int w = bwd_resident_waves(get(nt), nt, lds);
+            if (w > bw) {
+                best = nt;
+                bw = w;
+            }
+        }
+        return best;
+    }
+};
+
 // radix: > 0 runs the register-block kernel of that radix (every digit uses
 // the one W; the schedule counts blocks of bwd_block_digits digits), 0 the
-// runtime-radix kernel (radices up to maxb)
+// runtime-radix kernel (radices up to maxb).  threads: the block kernel's
+// work-group size (from launch_bwd_threads_t), ignored for the runtime radix.
 template <typename T>
-hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, int threads, size_t lds,
+                        hipStream_t s) {
     using C = typename Tr<T>::C;
     if (radix > 0) {
         constexpr int r2 = bwd_block_digits<C>(2), r3 = bwd_block_digits<C>(3), r4 = bwd_block_digits<C>(4),
                       r5 = bwd_block_digits<C>(5);
         switch (radix) {
-            case 2: if constexpr (r2 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 2, (r2 > 0 ? r2 : 1)>, a, grid, lds, s); break;
-            case 3: if constexpr (r3 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 3, (r3 > 0 ? r3 : 1)>, a, grid, lds, s); break;
-            case 4: if constexpr (r4 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 4, (r4 > 0 ? r4 : 1)>, a, grid, lds, s); break;
-            case 5: if constexpr (r5 > 0) return bwd_launch_one(gtt_bwd_block_kernel<T, 5, (r5 > 0 ? r5 : 1)>, a, grid, lds, s); break;
+            case 2: if constexpr (r2 > 0) return bwd_launch_one(BwdBlockKernels<T, 2, (r2 > 0 ? r2 : 1)>::get(threads), a, grid, threads, lds, s); break;
+            case 3: if constexpr (r3 > 0) return bwd_launch_one(BwdBlockKernels<T, 3, (r3 > 0 ? r3 : 1)>::get(threads), a, grid, threads, lds, s); break;
+            case 4: if constexpr (r4 > 0) return bwd_launch_one(BwdBlockKernels<T, 4, (r4 > 0 ? r4 : 1)>::get(threads), a, grid, threads, lds, s); break;
+            case 5: if constexpr (r5 > 0) return bwd_launch_one(BwdBlockKernels<T, 5, (r5 > 0 ? r5 : 1)>::get(threads), a, grid, threads, lds, s); break;
             default: break;
         }
         return hipErrorInvalidValue;
     }
-    if (maxb <= 8) return bwd_launch_one(gtt_bwd_kernel<T, 8>, a, grid, lds, s);
-    if (maxb <= 16) return bwd_launch_one(gtt_bwd_kernel<T, 16>, a, grid, lds, s);
-    if (maxb <= 32) return bwd_launch_one(gtt_bwd_kernel<T, 32>, a, grid, lds, s);
+    if (maxb <= 8) return bwd_launch_one(gtt_bwd_kernel<T, 8>, a, grid, kThreads, lds, s);
+    if (maxb <= 16) return bwd_launch_one(gtt_bwd_kernel<T, 16>, a, grid, kThreads, lds, s);
+    if (maxb <= 32) return bwd_launch_one(gtt_bwd_kernel<T, 32>, a, grid, kThreads, lds, s);
     return hipErrorInvalidValue;
+}
+
+// work-group size of the register-block kernel of this radix for `lds`
+// bytes of LDS (kThreads for the runtime-radix kernel)
+template <typename T>
+int launch_bwd_threads_t(int radix, size_t lds) {
+    using C = typename Tr<T>::C;
+    constexpr int r2 = bwd_block_digits<C>(2), r3 = bwd_block_digits<C>(3), r4 = bwd_block_digits<C>(4),
+                  r5 = bwd_block_digits<C>(5);
+    switch (radix) {
+        case 2: if constexpr (r2 > 0) return BwdBlockKernels<T, 2, (r2 > 0 ? r2 : 1)>::threads(lds); break;
+        case 3: if constexpr (r3 > 0) return BwdBlockKernels<T, 3, (r3 > 0 ? r3 : 1)>::threads(lds); break;
+        case 4: if constexpr (r4 > 0) return BwdBlockKernels<T, 4, (r4 > 0 ? r4 : 1)>::threads(lds); break;
+        case 5: if constexpr (r5 > 0) return BwdBlockKernels<T, 5, (r5 > 0 ? r5 : 1)>::threads(lds); break;
+        default: break;
+    }
+    return kThreads;
 }
 
 template <typename T>
@@ -603,10 +667,11 @@ hipError_t launch_reduce_t(const void* partials, int64_t nparts, int bb, void* o
 // short name used in the launcher symbols, T: the storage type).
 #define GTT_BWD_INSTANTIATE(NAME, T)                                                                     \
     namespace gtt {                                                                                      \
-    hipError_t launch_bwd_##NAME(const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds,       \
-                                 hipStream_t s) {                                                        \
-        return launch_bwd_t<T>(a, maxb, radix, grid, lds, s);                                            \
+    hipError_t launch_bwd_##NAME(const BwdArgs& a, int maxb, int radix, unsigned grid, int threads,      \
+                                 size_t lds, hipStream_t s) {                                            \
+        return launch_bwd_t<T>(a, maxb, radix, grid, threads, lds, s);                                   \
     }                                                                                                    \
+    int launch_bwd_threads_##NAME(int radix, size_t lds) { return launch_bwd_threads_t<T>(radix, lds); }  \
     int bwd_block_digits_##NAME(int b) { return bwd_block_digits<typename Tr<T>::C>(b); }              \
     hipError_t launch_reduce_##NAME(const void* partials, int64_t nparts, int bb, void* out,            \
                                     hipStream_t s) {                                                     \

@@ -198,7 +198,9 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
             // every digit; its schedule counts blocks)
             const int radix = (shared_w && G.bwd_rd > 0) ? rad[G.s0] : 0;
             if (!shared_w && G.bwd_rd > 0) return GTT_ERR_INTERNAL;
-            if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, radix, grid, bwd_lds_bytes(G, dt), s) != hipSuccess)
+            const size_t lds = bwd_lds_bytes(G, dt);
+            const int threads = launch_bwd_threads(to_dt(dt), radix, lds);
+            if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, radix, grid, threads, lds, s) != hipSuccess)
                 return GTT_ERR_HIP;
         }
         if (tp && tp->timing.enabled) {

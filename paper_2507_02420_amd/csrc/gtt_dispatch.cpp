@@ -1,4 +1,8 @@
 // Dtype dispatch to the per-dtype kernel translation units.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "gtt_launch.hpp"
 
 namespace gtt {
@@ -11,17 +15,23 @@ hipError_t launch_pass_bf16(int, int, const PassArgs&, unsigned, size_t, hipStre
 hipError_t launch_pass_f16(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 hipError_t launch_pass_i32(int, int, const PassArgs&, unsigned, size_t, hipStream_t);
 
-hipError_t launch_bwd_f64(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f64(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_f64(int, size_t);
 int bwd_block_digits_f64(int);
-hipError_t launch_bwd_f32(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f32(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_f32(int, size_t);
 int bwd_block_digits_f32(int);
-hipError_t launch_bwd_c128(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c128(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_c128(int, size_t);
 int bwd_block_digits_c128(int);
-hipError_t launch_bwd_c64(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_c64(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_c64(int, size_t);
 int bwd_block_digits_c64(int);
-hipError_t launch_bwd_bf16(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_bf16(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_bf16(int, size_t);
 int bwd_block_digits_bf16(int);
-hipError_t launch_bwd_f16(const BwdArgs&, int, int, unsigned, size_t, hipStream_t);
+hipError_t launch_bwd_f16(const BwdArgs&, int, int, unsigned, int, size_t, hipStream_t);
+int launch_bwd_threads_f16(int, size_t);
 int bwd_block_digits_f16(int);
 hipError_t launch_reduce_f64(const void*, int64_t, int, void*, hipStream_t);
 hipError_t launch_reduce_f32(const void*, int64_t, int, void*, hipStream_t);
@@ -42,16 +52,45 @@ int bwd_block_digits(DT dt, int b) {
     }
 }
 
-hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s) {
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, int threads, size_t lds,
+                      hipStream_t s) {
     switch (dt) {
-        case DT::F64: return launch_bwd_f64(a, maxb, radix, grid, lds, s);
-        case DT::F32: return launch_bwd_f32(a, maxb, radix, grid, lds, s);
-        case DT::C128: return launch_bwd_c128(a, maxb, radix, grid, lds, s);
-        case DT::C64: return launch_bwd_c64(a, maxb, radix, grid, lds, s);
-        case DT::BF16: return launch_bwd_bf16(a, maxb, radix, grid, lds, s);
-        case DT::F16: return launch_bwd_f16(a, maxb, radix, grid, lds, s);
+        case DT::F64: return launch_bwd_f64(a, maxb, radix, grid, threads, lds, s);
+        case DT::F32: return launch_bwd_f32(a, maxb, radix, grid, threads, lds, s);
+        case DT::C128: return launch_bwd_c128(a, maxb, radix, grid, threads, lds, s);
+        case DT::C64: return launch_bwd_c64(a, maxb, radix, grid, threads, lds, s);
+        case DT::BF16: return launch_bwd_bf16(a, maxb, radix, grid, threads, lds, s);
+        case DT::F16: return launch_bwd_f16(a, maxb, radix, grid, threads, lds, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+int launch_bwd_threads(DT dt, int radix, size_t lds) {
+    if (radix <= 0) return kThreads;
+    // occupancy queries once per (device, dtype, radix, LDS bytes)
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const auto key = std::make_tuple(dev, (int)dt, radix, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int nt = kThreads;
+    switch (dt) {
+        case DT::F64: nt = launch_bwd_threads_f64(radix, lds); break;
+        case DT::F32: nt = launch_bwd_threads_f32(radix, lds); break;
+        case DT::C128: nt = launch_bwd_threads_c128(radix, lds); break;
+        case DT::C64: nt = launch_bwd_threads_c64(radix, lds); break;
+        case DT::BF16: nt = launch_bwd_threads_bf16(radix, lds); break;
+        case DT::F16: nt = launch_bwd_threads_f16(radix, lds); break;
+        default: break;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = nt;
+    return nt;
 }
 
 hipError_t launch_reduce(DT dt, const void* partials, int64_t nparts, int bb, void* out, hipStream_t s) {

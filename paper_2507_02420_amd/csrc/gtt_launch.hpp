@@ -67,8 +67,14 @@ struct BwdArgs;
 // backward of one digit group, floating dtypes: radix > 0 runs the
 // register-block kernel of that radix (one W for every digit; the schedule
 // counts blocks of bwd_block_digits digits), 0 the runtime-radix kernel
-// (radices up to maxb <= 32)
-hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, size_t lds, hipStream_t s);
+// (radices up to maxb <= 32); threads: the register-block kernel's
+// work-group size, from launch_bwd_threads
+hipError_t launch_bwd(DT dt, const BwdArgs& a, int maxb, int radix, unsigned grid, int threads, size_t lds,
+                      hipStream_t s);
+// work-group size (256, 512 or 1024) of the radix-`radix` register-block
+// backward kernel with the most resident waves for `lds` bytes of LDS
+// (occupancy queries on the current device, cached); kThreads for radix 0
+int launch_bwd_threads(DT dt, int radix, size_t lds);
 // digits per register block of the radix-b backward kernel for dtype dt (0:
 // no such kernel)
 int bwd_block_digits(DT dt, int b);

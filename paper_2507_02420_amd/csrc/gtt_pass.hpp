@@ -73,6 +73,28 @@ __device__ __forceinline__ void block_digit(C (&v)[(IPow<B, R>::value)], const C
     }
 }
 
+// W^H along digit D of a register block: v[r] <- sum_q conj(W[q][r]) v[q]
+// (the adjoint taken from W's registers: no second matrix)
+template <typename C, int B, int R, int D>
+__device__ __forceinline__ void block_digit_adj(C (&v)[(IPow<B, R>::value)], const C (&w)[B * B]) {
+    constexpr int st = IPow<B, D>::value;
+    constexpr int n = IPow<B, R>::value;
+#pragma unroll
+    for (int base = 0; base < n; ++base) {
+        if ((base / st) % B != 0) continue;  // base must have digit D == 0
+        C in[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) in[q] = v[base + q * st];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            C acc = cmac_conj(czero<C>(), in[0], w[r]);
+#pragma unroll
+            for (int q = 1; q < B; ++q) acc = cmac_conj(acc, in[q], w[q * B + r]);
+            v[base + r * st] = acc;
+        }
+    }
+}
+
 // The same for the integer radix-2 Hadamard W = [[1, 1], [1, -1]]: one add
 // and one subtract per pair (wrap-around arithmetic, so the result is the
 // same as with the multiplies, which are quarter-rate for 32-bit integers).
@@ -320,7 +342,8 @@ __device__ __forceinline__ VecWalk vec_walk(const PassArgs& a, int64_t t, uint32
     return w;
 }
 
-template <typename T, typename C>
+// NT: threads of the work-group (every thread takes part)
+template <typename T, typename C, int NT = kThreads>
 __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
                                           uint32_t rows) {
     constexpr int V = Vec16<T>::V;
@@ -330,16 +353,16 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
     const int64_t l = contig ? 0 : t - hb * a.L;
     if (a.mode == kContigVec || a.mode == kRowVec) {
         const uint32_t nvec = tileE / V;
-        for (uint32_t i0 = 0; i0 < nvec; i0 += kLoadBatch * kThreads) {
+        for (uint32_t i0 = 0; i0 < nvec; i0 += kLoadBatch * NT) {
             uint4 buf[kLoadBatch];
 #pragma unroll
             for (int v = 0; v < kLoadBatch; ++v) {
-                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                const uint32_t i = i0 + threadIdx.x + v * NT;
                 if (i < nvec) buf[v] = *reinterpret_cast<const uint4*>(in + vec_offset<T>(a, t, i, hb, l, tileE));
             }
 #pragma unroll
             for (int v = 0; v < kLoadBatch; ++v) {
-                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                const uint32_t i = i0 + threadIdx.x + v * NT;
                 if (i < nvec) {
                     T vals[V];
                     *reinterpret_cast<uint4*>(vals) = buf[v];
@@ -359,11 +382,11 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
             }
         }
     } else {
-        for (uint32_t i0 = 0; i0 < tileE; i0 += kLoadBatch * kThreads) {
+        for (uint32_t i0 = 0; i0 < tileE; i0 += kLoadBatch * NT) {
             T buf[kLoadBatch];
 #pragma unroll
             for (int v = 0; v < kLoadBatch; ++v) {
-                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                const uint32_t i = i0 + threadIdx.x + v * NT;
                 if (i < tileE) {
                     const int64_t off = elem_offset(a, t, i, hb, l, tileE);
                     if (off >= 0 && (a.cut < 0 || ((off % a.N < a.cut) != (a.cut_keep_high != 0))))
@@ -374,14 +397,14 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
             }
 #pragma unroll
             for (int v = 0; v < kLoadBatch; ++v) {
-                const uint32_t i = i0 + threadIdx.x + v * kThreads;
+                const uint32_t i = i0 + threadIdx.x + v * NT;
                 if (i < tileE) lds[lds_phys(i, a.pad_shift)] = to_c(buf[v]);
             }
         }
     }
 }
 
-template <typename T, typename C, bool WALK = false>
+template <typename T, typename C, bool WALK = false, int NT = kThreads>
 __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* __restrict__ out, int64_t t,
                                            uint32_t rows) {
     constexpr int V = Vec16<T>::V;
@@ -391,6 +414,7 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
     const int64_t l = contig ? 0 : t - hb * a.L;
     if (a.mode == kContigVec || a.mode == kRowVec) {
         const uint32_t nvec = tileE / V;
+        static_assert(!WALK || NT == kThreads, "the address walk assumes kThreads threads");
         if (WALK && vec_walk_ok<T>(a)) {
             const VecWalk w = vec_walk<T>(a, t, threadIdx.x, tileE);
             uint32_t m = 0;
@@ -403,7 +427,7 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
             }
             return;
         }
-        for (uint32_t i = threadIdx.x; i < nvec; i += kThreads) {
+        for (uint32_t i = threadIdx.x; i < nvec; i += NT) {
             T vals[V];
             const uint32_t ph = lds_phys(i * V, a.pad_shift);
 #pragma unroll
@@ -411,7 +435,7 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
             gstore16<true>(out + vec_offset<T>(a, t, i, hb, l, tileE), *reinterpret_cast<const uint4*>(vals));
         }
     } else {
-        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+        for (uint32_t i = threadIdx.x; i < tileE; i += NT) {
             const int64_t off = elem_offset(a, t, i, hb, l, tileE);
             if (off >= 0) out[off] = from_c<T>(lds[lds_phys(i, a.pad_shift)]);
         }
