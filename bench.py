@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 METRIC = "GTT fwd+bwd elements/s and % of HBM roofline vs plain FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, FP32
+# without packed instructions (disabled on this target) and FP64 alike
+VALU_PEAK_TFLOPS = 78.6
 
 
 def kernel_flops(name: str, elems: int) -> float:
@@ -292,10 +295,26 @@ def _timed_plan(p, fn, iters, flush=None):
     return ms, tm
 
 
-def _dominant_entry(tm, E):
+def _dominant_entry(tm, E, flops_per_elem_digit=None):
+    """The kernel with the largest share: its HBM rate and fraction; with
+    flops_per_elem_digit (the algorithmic vector-ALU flops of one digit pass
+    per element: 2b real, 8b complex, twice that for a backward digit), also
+    its ALU view against the vector peak and which roofline binds it (the
+    larger time at peak), with the fraction of that roofline."""
     nm_, t_, ach = dominant(tm)
-    return {"dominant": nm_, "dominant_avg_ms": t_["avg_ms"], "dominant_bytes_per_launch": t_["bytes_per_launch"],
-            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+    e = {"dominant": nm_, "dominant_avg_ms": t_["avg_ms"], "dominant_bytes_per_launch": t_["bytes_per_launch"],
+         "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+    if flops_per_elem_digit:
+        import re
+        k = int(re.search(r"k=(\d+)", nm_).group(1))
+        flops = float(E) * k * flops_per_elem_digit
+        t = t_["avg_ms"] * 1e-3
+        alu = flops / t / 1e12
+        t_hbm = t_["bytes_per_launch"] / (HBM_PEAK_GBS * 1e9)
+        t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
+        e.update({"alu_flops_per_launch": flops, "alu_TFLOPs": alu, "alu_frac": alu / VALU_PEAK_TFLOPS,
+                  "bound": "alu" if t_alu > t_hbm else "hbm", "binding_frac": max(t_alu, t_hbm) / t})
+    return e
 
 
 def _backward_entry(p, W, x, iters=10, seed=7):
@@ -318,7 +337,8 @@ def _backward_entry(p, W, x, iters=10, seed=7):
     bw = {k: v for k, v in tm.items() if k.startswith("bwd")}
     return {"ms": ms, "elements_per_s": E / (ms * 1e-3), "algorithmic_bytes": alg,
             "algorithmic_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "round_trips": len(p.describe()["bwd_groups"]), **_dominant_entry(bw, E), "kernels": tm}
+            "round_trips": len(p.describe()["bwd_groups"]),
+            **_dominant_entry(bw, E, (16 if x.is_complex() else 4) * p.describe()["b"]), "kernels": tm}
 
 
 def wl_c1(iters=50, cpu=True):
@@ -362,7 +382,7 @@ def wl_c2(iters=10, cpu=True):
     ms, tm = _timed_plan(p, lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
     E = batch * b ** n
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
-    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
+    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E, 8 * b),
          "kernels": tm, "backward": _backward_entry(p, W, x)}
     if cpu:
         from oracle import gtt_oracle as O
@@ -391,7 +411,7 @@ def wl_c3a(iters=10, cpu=True):
     xr = p.inverse(W, y)
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
     E = batch * b ** n
-    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E),
+    e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E, 2 * b),
          "kernels": tm, "backward": _backward_entry(p, W, x)}
     if cpu:
         from oracle import gtt_oracle as O
