@@ -307,6 +307,13 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
     const bool pow2 = (rad[s0] & (rad[s0] - 1)) == 0;
     const size_t over = radix_ok ? bwd_overhead_bytes((int)wloc, dt) : 0;
     const int64_t Tmax = std::max<int64_t>(G, (int64_t)(40 * 1024) / (int64_t)cs);
+    // strided tiles: rows of at least this many bytes are preferred before
+    // the schedule's cost.  Power-of-two radices move 16-byte vectors and
+    // want the forward's row width (whole 128-byte lines: 32-byte rows cost
+    // 17-28 % on the complex64 radix-4 and float32 radix-2 / 4 strided
+    // groups); odd radices move 4-byte elements, where the smaller tiles'
+    // occupancy measured better than wider rows (float32 radix 3: 10 %).
+    const int64_t row_cap = pow2 ? std::max<int64_t>(32, cmin * (int64_t)es) : 32;
     bool found = false;
     Group best;
     int best_passes = 0, best_slots = 0, best_rd = 0, best_units = 0;
@@ -331,7 +338,7 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
             const size_t lds = over + (size_t)slots * tb;
             const int waves = (int)std::min<size_t>(4, (160 * 1024) / lds);
             const double cost = (double)passes / std::pow((double)waves / 4.0, 0.75);
-            const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, 32);
+            const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, row_cap);
             bool better = !found;
             if (!better) {
                 if (row != best_row) better = row > best_row;
