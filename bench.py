@@ -194,6 +194,22 @@ def copy_ceiling_gbs(nbytes=1 << 30, iters=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def size_matched_copy(x, y, iters=10, flush=None):
+    """A device copy of x into y (the same bytes a digit-group launch reads
+    and writes, the same cache flushing): the practical ceiling at this size;
+    returns {"GBs": ..., "bytes": ...}."""
+    y.copy_(x)
+    ms, _ = time_calls(lambda: y.copy_(x), iters, flush=flush)
+    nb = 2 * x.numel() * x.element_size()
+    return {"GBs": nb / (ms * 1e-3) / 1e9, "bytes": nb}
+
+
+def _with_copy(e, cp):
+    e["size_matched_copy_GBs"] = cp["GBs"]
+    e["dominant_frac_of_copy"] = e["achieved_GBs"] / cp["GBs"]
+    return e
+
+
 def cpu_baseline_headline(tensors, budget_s=30.0):
     """FP64 oracle (numpy, single core) on the headline workload: forward +
     gradient of whole instances, timed, until every instance is done or about
@@ -384,6 +400,7 @@ def wl_c2(iters=10, cpu=True):
     err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
     e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E, 8 * b),
          "kernels": tm, "backward": _backward_entry(p, W, x)}
+    _with_copy(e, size_matched_copy(x, xr))
     if cpu:
         from oracle import gtt_oracle as O
         W64 = W.cpu().to(torch.complex128).numpy()
@@ -413,6 +430,7 @@ def wl_c3a(iters=10, cpu=True):
     E = batch * b ** n
     e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err, **_dominant_entry(tm, E, 2 * b),
          "kernels": tm, "backward": _backward_entry(p, W, x)}
+    _with_copy(e, size_matched_copy(x, xr, flush=_flusher()))
     if cpu:
         from oracle import gtt_oracle as O
         W64 = W.cpu().double().numpy()
@@ -443,6 +461,7 @@ def wl_c3b(iters=10, cpu=True):
     E = batch * b ** n
     e = {"ms": ms, "elements_per_s": E / (ms * 1e-3), "inverse_of_forward_is_2^n_x_exactly": exact,
          **_dominant_entry(tm, E), "kernels": tm}
+    _with_copy(e, size_matched_copy(xi, back, flush=_flusher()))
     if cpu:
         from oracle import gtt_oracle as O
         r = oracle_rate(lambda: O.staged_int32(hadamard2(False).astype(np.int64), xn[0], n), b ** n)
