@@ -318,46 +318,51 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
     Group best;
     int best_passes = 0, best_slots = 0, best_rd = 0, best_units = 0;
     int64_t best_row = 0;
-    size_t best_cap = 0;
-    std::vector<size_t> caps = {(size_t)40 * 1024, (size_t)64 * 1024, (size_t)80 * 1024, (size_t)120 * 1024,
-                                (size_t)160 * 1024};
-    if (bwd_lds > 0) caps.assign(1, (size_t)bwd_lds);  // tuned: one LDS budget per work-group
+    const std::vector<size_t> default_caps = {(size_t)40 * 1024, (size_t)64 * 1024, (size_t)80 * 1024,
+                                              (size_t)120 * 1024, (size_t)160 * 1024};
     double best_cost = 0.0;
-    for (size_t cap : caps) {
-        for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
-            Group c;
-            fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
-            const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
-            if (over + 3 * tb > cap) break;  // tiles only grow with T
-            // the register-block kernel addresses a block as one padded base
-            // plus fixed offsets: a power-of-two radix, or an unpadded tile
-            const int rd = (rd0 > 0 && (pow2 || c.pad_shift == kNoPad)) ? rd0 : 0;
-            const int units = rd > 0 ? (k + rd - 1) / rd : k;
-            const int slots = (int)std::min<size_t>((cap - over) / tb, (size_t)std::min(units + 1, kMaxBwdSlots));
-            const int passes = bwd_fwd_passes(units, slots - 2) + 2 * units;
-            const size_t lds = over + (size_t)slots * tb;
-            const int waves = (int)std::min<size_t>(4, (160 * 1024) / lds);
-            const double cost = (double)passes / std::pow((double)waves / 4.0, 0.75);
-            const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, row_cap);
-            bool better = !found;
-            if (!better) {
-                if (row != best_row) better = row > best_row;
-                else if (cost != best_cost) better = cost < best_cost;
-                else better = c.tileE > best.tileE;
-            }
-            if (better) {
-                found = true;
-                best = c;
-                best_rd = rd;
-                best_units = units;
-                best_passes = passes;
-                best_slots = slots;
-                best_row = row;
-                best_cap = cap;
-                best_cost = cost;
+    auto search = [&](const std::vector<size_t>& caps) {
+        for (size_t cap : caps) {
+            for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
+                Group c;
+                fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
+                const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
+                if (over + 3 * tb > cap) break;  // tiles only grow with T
+                // the register-block kernel addresses a block as one padded
+                // base plus fixed offsets: a power-of-two radix, or an
+                // unpadded tile
+                const int rd = (rd0 > 0 && (pow2 || c.pad_shift == kNoPad)) ? rd0 : 0;
+                const int units = rd > 0 ? (k + rd - 1) / rd : k;
+                const int slots =
+                    (int)std::min<size_t>((cap - over) / tb, (size_t)std::min(units + 1, kMaxBwdSlots));
+                const int passes = bwd_fwd_passes(units, slots - 2) + 2 * units;
+                const size_t lds = over + (size_t)slots * tb;
+                const int waves = (int)std::min<size_t>(4, (160 * 1024) / lds);
+                const double cost = (double)passes / std::pow((double)waves / 4.0, 0.75);
+                const int64_t row = std::min<int64_t>(c.S == 1 ? INT64_MAX : (int64_t)c.C * (int64_t)es, row_cap);
+                bool better = !found;
+                if (!better) {
+                    if (row != best_row) better = row > best_row;
+                    else if (cost != best_cost) better = cost < best_cost;
+                    else better = c.tileE > best.tileE;
+                }
+                if (better) {
+                    found = true;
+                    best = c;
+                    best_rd = rd;
+                    best_units = units;
+                    best_passes = passes;
+                    best_slots = slots;
+                    best_row = row;
+                    best_cost = cost;
+                }
             }
         }
-    }
+    };
+    // tuned: one LDS budget per work-group; a budget that holds no schedule
+    // (fewer than three tiles) falls back to the built-in budgets
+    if (bwd_lds > 0) search({(size_t)bwd_lds});
+    if (!found) search(default_caps);
     if (!found) {
         // no backward for this group: keep the forward geometry for the
         // plan's description

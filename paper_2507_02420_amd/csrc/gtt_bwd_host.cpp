@@ -153,6 +153,7 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
         void* c_in = (g == 0) ? gx : (void*)cbuf;
         pa.out = c_in;
         const unsigned grid = bwd_grid(G);
+        int threads = 0;  // work-group size of a general-kernel launch
         timing_begin(tp, s);
         if (G.kind == kKindCMfma) {
             CBwdArgs ca;
@@ -199,14 +200,18 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
             const int radix = (shared_w && G.bwd_rd > 0) ? rad[G.s0] : 0;
             if (!shared_w && G.bwd_rd > 0) return GTT_ERR_INTERNAL;
             const size_t lds = bwd_lds_bytes(G, dt);
-            const int threads = launch_bwd_threads(to_dt(dt), radix, lds);
+            threads = launch_bwd_threads(to_dt(dt), radix, lds);
             if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, radix, grid, threads, lds, s) != hipSuccess)
                 return GTT_ERR_HIP;
         }
         if (tp && tp->timing.enabled) {
+            // the general kernels' labels carry the work-group size
             char nm[96];
-            std::snprintf(nm, sizeof nm, "bwd %s b=%d%s s0=%d k=%d", kDtName[(int)dt], rad[G.s0],
-                          G.kind == kKindCMfma ? " cmfma" : "", G.s0, G.k);
+            if (G.kind == kKindCMfma)
+                std::snprintf(nm, sizeof nm, "bwd %s b=%d cmfma s0=%d k=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k);
+            else
+                std::snprintf(nm, sizeof nm, "bwd %s b=%d s0=%d k=%d wg=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k,
+                              threads);
             timing_end(tp, s, nm, 3.0 * (double)G.elems * (double)es);
         }
         part += (size_t)grid * wslot * as;

@@ -155,3 +155,18 @@ def test_radix_backward_lds_offsets_are_additive(b, n, batch, dtype):
                 base = _phys(lam0, ps)
                 for m in range(nb):
                     assert base + off[m] == _phys(lam0 + m * step, ps), (j0, f, m)
+
+
+def test_tuned_backward_budget_too_small_falls_back():
+    # a tuned LDS budget per backward work-group that holds no schedule
+    # (fewer than three tiles) must not leave a group without a backward
+    try:
+        for b, n, batch, dtype in [(3, 9, 2, torch.float32), (4, 6, 3, torch.complex64)]:
+            G.set_tuning(b, dtype, 0, 0, n=n, bwd_lds_bytes=20480)
+            d = G.Plan(b, n, batch, dtype).describe()
+            assert all(g["bwd_ok"] for g in d["bwd_groups"]), d["bwd_groups"]
+            G.set_tuning(b, dtype, 0, 0, n=n)
+    finally:
+        G.set_tuning(3, torch.float32, 0, 0, n=9)
+        G.set_tuning(4, torch.complex64, 0, 0, n=6)
+        G.load_tuning()

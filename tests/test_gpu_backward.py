@@ -254,3 +254,38 @@ def test_autograd_function_matches_oracle_c64():
     rgx, rgW = O.grad(W64, x64, host64(g), n)
     assert rel_err(host64(x.grad), rgx) < 1e-5
     assert np.linalg.norm(host64(W.grad) - rgW) / np.linalg.norm(rgW) < 1e-5
+
+
+def test_backward_every_workgroup_size():
+    # the register-block backward runs 256-, 512- or 1024-thread work-groups,
+    # whichever keeps the most waves resident for the tile's LDS; tuned LDS
+    # budgets per work-group steer the choice through all three sizes
+    # (labels of the timed launches carry the size), each checked against the
+    # oracle; a budget too small for any schedule falls back to the built-in
+    # ones
+    seen = set()
+    shapes = [(3, 9, 2, torch.float32), (4, 8, 2, torch.float32), (4, 6, 3, torch.complex64)]
+    try:
+        for b, n, batch, dtype in shapes:
+            for lds in (20480, 81920, 163840):
+                G.set_tuning(b, dtype, 0, 0, n=n, bwd_lds_bytes=lds)
+                say(f"backward work-group size b={b} n={n} dtype={dtype} lds={lds}")
+                x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=5900 + b + n)
+                g = gaussian((batch, b ** n), seed=5901 + b, complex_=dtype in COMPLEX)
+                gt = torch.from_numpy(g).to(dtype).cuda()
+                plan = G.Plan(b, n, batch, dtype)
+                plan.timing(True)
+                gx, gW = plan.backward(W, x, gt)
+                torch.cuda.synchronize()
+                names = list(plan.timing_read())
+                plan.timing(False)
+                seen |= {int(nm.split("wg=")[1]) for nm in names if "wg=" in nm}
+                rgx, rgW = O.grad(W64, x64, host64(gt), n)
+                assert rel_err(host64(gx), rgx) < TOL[dtype]
+                assert np.linalg.norm(host64(gW) - rgW) / np.linalg.norm(rgW) < TOL[dtype]
+    finally:
+        for b, n, _, dtype in shapes:
+            G.set_tuning(b, dtype, 0, 0, n=n)  # all zeros: the entry is removed
+        G.load_tuning()
+    say(f"work-group sizes seen: {sorted(seen)}")
+    assert {256, 512, 1024} <= seen, seen
