@@ -25,6 +25,7 @@
 #pragma once
 
 #include "gtt_args.hpp"
+#include "gtt_mfma.hpp"
 #include "gtt_pass.hpp"
 #include "gtt_types.hpp"
 
@@ -259,6 +260,96 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
         }
         part[e] = v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core backward for radix 16 and 32 (one W for every digit; bf16,
+// f16 or float storage): the same per-tile schedule as gtt_bwd_kernel on
+// FP32 tiles in LDS, every digit operation a dense contraction on the FP32
+// MFMA (16x16x4): forward passes rebuilding activations with W, the gradient
+// sums c a^T over the fibres of a digit (four fibres per MFMA, each tile's
+// chain added into FP64), and the adjoint passes with W^T.  The waves' FP64
+// sums are added in wave order at the end.
+// ---------------------------------------------------------------------------
+template <typename T>
+constexpr bool bwd_mfma_ok() {
+    return sizeof(T) == 2 || std::is_same<T, float>::value;
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kThreads) void gtt_bwd_mfma_kernel(BwdArgs ba) {
+    static_assert(B == 16 || B == 32, "matrix-core radices");
+    static_assert(bwd_mfma_ok<T>(), "real storage with float compute");
+    constexpr int NB = B / 16;
+    const PassArgs& a = ba.p;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t tileP = lds_tile_elems(tileE, a.pad_shift);
+    // the layout of gtt_bwd_kernel ([acc][red][W][W^H][slots]): the FP64 area
+    // acc (B * B values) takes the work-group's sum; W stays in registers
+    double* acc = reinterpret_cast<double*>(smem_raw);
+    unsigned char* pb = smem_raw;
+    pb += bwd_align16((size_t)ba.wloc * sizeof(double));
+    pb += (size_t)kThreads * sizeof(double);
+    pb += 2 * bwd_align16((size_t)ba.wloc * sizeof(float));
+    float* slot0 = reinterpret_cast<float*>(pb);
+    auto slot = [&](int i) { return slot0 + (size_t)i * tileP; };
+    WFrag<float, B> wf, wt;
+    {
+        PassArgs aw = a;
+        aw.adjoint = 0;
+        load_w_frag<float, B>(wf, aw);
+        aw.adjoint = 1;  // W^T (real)
+        load_w_frag<float, B>(wt, aw);
+    }
+    double Md[NB][NB][4];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Md[bi][bj][v] = 0.0;
+    float* Ct = slot(1);
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        tile_load<T, float>(slot(0), a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, float>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
+        __syncthreads();
+        for (int o = 0; o < ba.nops; ++o) {
+            const int op = ba.ops[o];
+            const int kind = op & 3, j = (op >> 2) & 63, src = (op >> 8) & 15, dst = (op >> 12) & 15;
+            if (kind == kOpFwd) {
+                mfma_pass_f32<B>(slot(src), slot(dst), a, j, rows, wf);
+            } else if (kind == kOpGw) {
+                mfma_gw_f32<B>(Ct, slot(src), a, j, rows, Md);
+            } else if (j != 0 || a.out) {
+                // (the cotangent at the input of digit 0 only when it is
+                // stored, as in gtt_bwd_kernel)
+                mfma_pass_f32<B>(Ct, Ct, a, j, rows, wt);
+            }
+            __syncthreads();
+        }
+        if (a.out) tile_store<T, float>(Ct, a, static_cast<T*>(a.out), t, rows);
+        __syncthreads();
+    }
+    // work-group sum in wave order, then this work-group's partial vector
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int e = (16 * bi + 4 * (lane >> 4) + v) * B + 16 * bj + (lane & 15);
+                        acc[e] = (w == 0 ? 0.0 : acc[e]) + Md[bi][bj][v];
+                    }
+        }
+        __syncthreads();
+    }
+    double* part = static_cast<double*>(ba.partials) + (size_t)blockIdx.x * ba.wslot;
+    for (int e = threadIdx.x; e < ba.wslot; e += kThreads) part[e] = e < B * B ? acc[e] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -605,10 +696,11 @@ struct BwdBlockKernels {
     }
 };
 
-// radix: > 0 runs the register-block kernel of that radix (every digit uses
-// the one W; the schedule counts blocks of bwd_block_digits digits), 0 the
+// radix: 2..5 runs the register-block kernel of that radix (every digit uses
+// the one W; the schedule counts blocks of bwd_block_digits digits), 16 / 32
+// the matrix-core kernel (one W; 16-bit or float storage), 0 the
 // runtime-radix kernel (radices up to maxb).  threads: the block kernel's
-// work-group size (from launch_bwd_threads_t), ignored for the runtime radix.
+// work-group size (from launch_bwd_threads_t), ignored by the others.
 template <typename T>
 hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, int threads, size_t lds,
                         hipStream_t s) {
@@ -621,6 +713,8 @@ hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, in
             case 3: if constexpr (r3 > 0) return bwd_launch_one(BwdBlockKernels<T, 3, (r3 > 0 ? r3 : 1)>::get(threads), a, grid, threads, lds, s); break;
             case 4: if constexpr (r4 > 0) return bwd_launch_one(BwdBlockKernels<T, 4, (r4 > 0 ? r4 : 1)>::get(threads), a, grid, threads, lds, s); break;
             case 5: if constexpr (r5 > 0) return bwd_launch_one(BwdBlockKernels<T, 5, (r5 > 0 ? r5 : 1)>::get(threads), a, grid, threads, lds, s); break;
+            case 16: if constexpr (bwd_mfma_ok<T>()) return bwd_launch_one(gtt_bwd_mfma_kernel<T, 16>, a, grid, kThreads, lds, s); break;
+            case 32: if constexpr (bwd_mfma_ok<T>()) return bwd_launch_one(gtt_bwd_mfma_kernel<T, 32>, a, grid, kThreads, lds, s); break;
             default: break;
         }
         return hipErrorInvalidValue;

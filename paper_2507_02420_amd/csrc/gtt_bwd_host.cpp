@@ -196,8 +196,10 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
                 }
             }
             // the register-block kernel when the plan chose it (one W for
-            // every digit; its schedule counts blocks)
-            const int radix = (shared_w && G.bwd_rd > 0) ? rad[G.s0] : 0;
+            // every digit; its schedule counts blocks); the matrix-core
+            // kernel for radix-16 / 32 groups on the matrix cores (one W)
+            int radix = (shared_w && G.bwd_rd > 0) ? rad[G.s0] : 0;
+            if (shared_w && G.kind == kKindMfma) radix = rad[G.s0];
             if (!shared_w && G.bwd_rd > 0) return GTT_ERR_INTERNAL;
             const size_t lds = bwd_lds_bytes(G, dt);
             threads = launch_bwd_threads(to_dt(dt), radix, lds);

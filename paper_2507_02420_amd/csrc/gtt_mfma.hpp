@@ -129,11 +129,12 @@ __device__ __forceinline__ void load_w_frag(WFrag<T, B>& wf, const PassArgs& a) 
     }
 }
 
-// W along digit j of every fibre of the FP32 tile, in place, on the FP32 MFMA.
-template <typename T, int B>
-__device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j, uint32_t rows,
-                                           const WFrag<T, B>& wf) {
-    static_assert(std::is_same<T, float>::value, "16-bit storage runs mfma_stage16");
+// W (fragments wf) along digit j of every fibre of an FP32 tile on the FP32
+// MFMA: src -> dst (in place when equal: each lane reads its fibres' values
+// before it writes them).  NT threads per work-group.
+template <int B, int NT = kThreads>
+__device__ __forceinline__ void mfma_pass_f32(const float* src, float* dst, const PassArgs& a, int j, uint32_t rows,
+                                              const WFrag<float, B>& wf) {
     constexpr int NB = B / 16;
     const uint32_t F = (rows << a.logC) / B;
     const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
@@ -159,7 +160,7 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
     const uint32_t hj = (uint32_t)a.logC + LB * (uint32_t)j;
     auto ins = [&](uint32_t v) { return ((v >> hj) << (hj + LB)) | (v & ((1u << hj) - 1u)); };
     const uint32_t lane_base = lds_phys(ins((uint32_t)(lane & 15)), pad) + qoff;
-    for (uint32_t grp = wave; grp < ngrp; grp += kThreads / 64) {
+    for (uint32_t grp = wave; grp < ngrp; grp += NT / 64) {
         const uint32_t f = grp * 16 + (lane & 15);
         const bool valid = f < F;
         const uint32_t base = lds_phys(ins(__builtin_amdgcn_readfirstlane(grp) * 16u), pad) + lane_base;
@@ -167,7 +168,7 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
 #pragma unroll
         for (int h = 0; h < NB; ++h)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[h][v] = valid ? lds[base + off[h][v]] : 0.f;
+            for (int v = 0; v < 4; ++v) x[h][v] = valid ? src[base + off[h][v]] : 0.f;
         f32x4 acc[NB];
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
@@ -182,9 +183,73 @@ __device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j,
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) lds[base + off[bi][v]] = acc[bi][v];
+                for (int v = 0; v < 4; ++v) dst[base + off[bi][v]] = acc[bi][v];
         }
     }
+}
+
+// W along digit j of every fibre of the FP32 tile, in place, on the FP32 MFMA.
+template <typename T, int B>
+__device__ __forceinline__ void mfma_stage(float* lds, const PassArgs& a, int j, uint32_t rows,
+                                           const WFrag<T, B>& wf) {
+    static_assert(std::is_same<T, float>::value, "16-bit storage runs mfma_stage16");
+    mfma_pass_f32<B>(lds, lds, a, j, rows, wf);
+}
+
+// Weight-gradient sums of digit j over the fibres of an FP32 tile on the
+// FP32 MFMA: M[r][q] = sum over fibres f of c_f[r] a_f[q] (real data: the
+// rank-1 terms c a^T).  With K = four fibres per MFMA, lane (k = lane / 16,
+// m = lane % 16) supplies element m (of each 16-row block) of fibre
+// 4 grp + k of both tiles: the A operand c[m] (rows) and the B operand a[m]
+// (columns).  The FP32 chain covers one digit of one tile (the fibres a wave
+// takes, four per step) and is then added into the FP64 accumulators Md:
+// lane (q, i), value v holds block (bi, bj) entry (16 bi + 4 q + v, 16 bj + i).
+template <int B, int NT = kThreads>
+__device__ __forceinline__ void mfma_gw_f32(const float* ct, const float* at, const PassArgs& a, int j,
+                                            uint32_t rows, double (&Md)[B / 16][B / 16][4]) {
+    constexpr int NB = B / 16;
+    const uint32_t F = (rows << a.logC) / B;
+    const uint32_t step = (uint32_t)a.bpow[j] << a.logC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t m = (uint32_t)(lane & 15), k = (uint32_t)(lane >> 4);
+    const int pad = a.pad_shift;
+    constexpr uint32_t LB = B == 16 ? 4u : 5u;
+    const uint32_t hj = (uint32_t)a.logC + LB * (uint32_t)j;
+    auto ins = [&](uint32_t v) { return ((v >> hj) << (hj + LB)) | (v & ((1u << hj) - 1u)); };
+    // fibre 4 grp + k (disjoint bits) and element 16 bi + m: every part of
+    // the position is additive under lds_phys
+    uint32_t eoff[NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) eoff[bi] = lds_phys((16u * bi + m) * step, pad);
+    const uint32_t kbase = lds_phys(ins(k), pad);
+    const uint32_t ngrp = (F + 3) / 4;
+    f32x4 M[NB][NB];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj) M[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t grp = wave; grp < ngrp; grp += NT / 64) {
+        const bool valid = grp * 4 + k < F;
+        const uint32_t base = lds_phys(ins(__builtin_amdgcn_readfirstlane(grp) * 4u), pad) + kbase;
+        float cv[NB], av[NB];
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            cv[bi] = valid ? ct[base + eoff[bi]] : 0.f;
+            av[bi] = valid ? at[base + eoff[bi]] : 0.f;
+        }
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NB; ++bj)
+                M[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(cv[bi], av[bj], M[bi][bj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Md[bi][bj][v] += (double)M[bi][bj][v];
 }
 
 // ---- 16-bit tiles ----------------------------------------------------------
