@@ -268,7 +268,13 @@ gtt_status gtt_plan_check(gtt_plan_t p, void* stream);
  */
 gtt_status gtt_plan_barrier_limit(gtt_plan_t p, uint32_t polls);
 
-/* Frees the plan and its device work list.  NULL is accepted. */
+/*
+ * Frees the plan and its device memory (the ragged work list, timing
+ * events).  NULL is accepted.  It calls hipFree: not while a stream capture
+ * is running in the process in global capture mode (the capture would be
+ * invalidated); the Python binding defers the destruction of a plan collected
+ * during a capture until the capture has ended.
+ */
 gtt_status gtt_plan_destroy(gtt_plan_t p);
 
 /* Static, human-readable name of a status code. */

@@ -45,6 +45,23 @@ EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "g
            "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit", "gtt_backward_noalloc"]
 
 
+# plans whose destruction was deferred because a graph capture was running
+_DEFERRED: list = []
+
+
+def _capturing() -> bool:
+    """True while the current stream is capturing a graph."""
+    try:
+        return bool(torch.cuda.is_available() and torch.cuda.is_current_stream_capturing())
+    except Exception:  # interpreter shutdown, no device
+        return False
+
+
+def _destroy_deferred():
+    while _DEFERRED and _lib is not None and not _capturing():
+        _lib.gtt_plan_destroy(_DEFERRED.pop())
+
+
 class GTTError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -169,6 +186,7 @@ class Plan:
         if len(bs) != len(ns):
             raise ValueError("b and n must have the same length")
         self.b, self.n, self.batch = bs, ns, batch
+        _destroy_deferred()
         h = ctypes.c_void_p()
         st = L.gtt_plan(ctypes.byref(h), len(bs), _arr(ctypes.c_int32, bs), _arr(ctypes.c_int32, ns),
                         batch, None if x_off is None else _arr(ctypes.c_int64, list(x_off)),
@@ -192,8 +210,15 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
-            _lib.gtt_plan_destroy(h)
             self._h = None
+            if _capturing():
+                # the garbage collector can run this inside a graph capture;
+                # freeing the plan's device memory there would invalidate
+                # the capture, so the plan is freed after it
+                _DEFERRED.append(h)
+            else:
+                _lib.gtt_plan_destroy(h)
+                _destroy_deferred()
 
     @property
     def handle(self):

@@ -479,3 +479,18 @@ def test_tuning_per_digit_count_and_backward_budget():
     units = -(-base["k"] // base["bwd_rd"])
     assert base["bwd_slots"] == units + 1
     assert g["bwd_ok"] and 3 <= g["bwd_slots"] < units + 1 and g["bwd_fwd_passes"] > base["bwd_fwd_passes"]
+
+
+def test_plan_destruction_is_deferred_during_graph_capture(monkeypatch):
+    # a plan collected while the current stream captures a graph is freed
+    # only after the capture (hipFree would invalidate it); the capture state
+    # is simulated on the host
+    monkeypatch.setattr(G, "_capturing", lambda: True)
+    p = G.Plan(2, 4, 1, torch.float32)
+    h = p.handle
+    del p
+    assert h in G._DEFERRED
+    monkeypatch.setattr(G, "_capturing", lambda: False)
+    q = G.Plan(2, 4, 1, torch.float32)  # a new plan frees the deferred ones first
+    assert not G._DEFERRED
+    del q
