@@ -359,7 +359,8 @@ def _backward_entry(p, W, x, iters=10, seed=7):
 
 def wl_c1(iters=50, cpu=True):
     """Single FP64 vector, b=2, n=10: normalised Hadamard and a random 2x2
-    orthogonal W; latency-bound (one work-group)."""
+    orthogonal W; latency-bound (one wave: digits 0-3 in registers, 4-9
+    across lanes)."""
     import torch
     from paper_2507_02420_amd import gtt as G
     from paper_2507_02420_amd.inputs import gaussian, hadamard2, haar_unitary
@@ -371,7 +372,16 @@ def wl_c1(iters=50, cpu=True):
         Wt = torch.from_numpy(Wn).to(_gpu())
         y = torch.empty_like(x)
         ms, _ = time_calls(lambda: p.forward(Wt, x, y), iters)
-        e = {"us_per_call": ms * 1e3, "elements_per_s": 1024 / (ms * 1e-3)}
+        # the kernel alone (HIP events around its launch, inside the library):
+        # a call is mostly host-side launch latency at this size
+        p.timing(True)
+        for _ in range(iters):
+            p.forward(Wt, x, y)
+        _sync()
+        tm = p.timing_read()
+        p.timing(False)
+        kern = {k: v["avg_ms"] * 1e3 for k, v in tm.items()}
+        e = {"us_per_call": ms * 1e3, "elements_per_s": 1024 / (ms * 1e-3), "kernel_us": kern}
         if cpu:
             from oracle import gtt_oracle as O
             r = oracle_rate(lambda: O.dense(Wn, xn, 10), 1024)

@@ -83,7 +83,16 @@ hipError_t launch_pass_t(int b, int kind, const PassArgs& a, unsigned grid, size
     }
     constexpr int mx = valu_max_radix<T>();
     switch (b) {
-        case 2: return launch_valu<T, 2>(a, grid, lds, s);
+        case 2:
+            if (wave2_ok<T>(a)) {
+                // one wave per 1024 elements, four waves a work-group
+                const int64_t E = a.ntiles * (int64_t)a.P * (int64_t)a.G;
+                const int64_t wg = ((E + 1023) / 1024 + kThreads / 64 - 1) / (kThreads / 64);
+                const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(wg, 1), 1 << 20);
+                hipLaunchKernelGGL(gtt_pass_wave2_kernel<T>, dim3(g), dim3(kThreads), 0, s, a);
+                return hipGetLastError();
+            }
+            return launch_valu<T, 2>(a, grid, lds, s);
         case 3: return launch_valu<T, 3>(a, grid, lds, s);
         case 4: return launch_valu<T, 4>(a, grid, lds, s);
         case 5: return launch_valu<T, 5>(a, grid, lds, s);

@@ -664,6 +664,123 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
     });
 }
 
+// ---------------------------------------------------------------------------
+// Radix 2, digits 0..k-1 (5 <= k <= 10) of blocks of 2^k contiguous elements
+// on wavefronts alone: lane l of a block holds its elements 16 l .. 16 l + 15
+// in registers, so digits 0-3 are register digits (applied as in a
+// super-stage) and digits 4..k-1 are lane digits: the partner of lane l for
+// digit d is lane l ^ 2^(d-4), reached by a cross-lane move (a DPP quad
+// permute for d = 4, 5, a ds_bpermute otherwise).  No LDS, no barriers; one
+// wave covers 1024 elements (64 >> (k-4) blocks).
+// ---------------------------------------------------------------------------
+template <int MASK>
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
+    if constexpr (MASK == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    else if constexpr (MASK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    else return (uint32_t)__shfl_xor((int)v, MASK, 64);
+}
+template <int MASK, typename C>
+__device__ __forceinline__ C lane_xor(C v) {
+    static_assert(sizeof(C) % 4 == 0, "32-bit words");
+    uint32_t w[sizeof(C) / 4];
+    __builtin_memcpy(w, &v, sizeof(C));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(C) / 4); ++i) w[i] = lane_xor32<MASK>(w[i]);
+    C r;
+    __builtin_memcpy(&r, w, sizeof(C));
+    return r;
+}
+
+// lane digit d = 4 + log2(MASK): y = W[bit][0] x_lo + W[bit][1] x_hi with
+// (x_lo, x_hi) = (own, partner) when the lane's bit is 0, else (partner, own)
+template <int MASK, typename C>
+__device__ __forceinline__ void lane_digit(C (&v)[16], const C (&w)[4], uint32_t lane, bool h2) {
+    const bool hi = (lane & MASK) != 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const C p = lane_xor<MASK>(v[r]);
+        const C lo_v = hi ? p : v[r];
+        const C hi_v = hi ? v[r] : p;
+        if constexpr (std::is_same<C, uint32_t>::value) {
+            if (h2) {  // integer Hadamard: add / subtract
+                v[r] = hi ? lo_v - hi_v : lo_v + hi_v;
+                continue;
+            }
+        }
+        v[r] = hi ? cmac(cmul(w[2], lo_v), w[3], hi_v) : cmac(cmul(w[0], lo_v), w[1], hi_v);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gtt_pass_wave2_kernel(PassArgs a) {
+    using C = typename Tr<T>::C;
+    C w[4];
+    load_w<C, 2>(w, a);
+    bool h2 = false;
+    if constexpr (std::is_same<C, uint32_t>::value)
+        h2 = w[0] == 1u && w[1] == 1u && w[2] == 1u && w[3] == 0xffffffffu;
+    const int64_t E = a.ntiles * (int64_t)a.P * (int64_t)a.G;
+    const T* in = static_cast<const T*>(a.in);
+    T* out = static_cast<T*>(a.out);
+    const uint32_t lane = threadIdx.x & 63;
+    constexpr int V = Vec16<T>::V;  // storage elements per 16-byte vector
+    constexpr int NV = 16 / V;       // vectors per lane
+    const int64_t nwaves = (E + 1023) / 1024;
+    for (int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); wv < nwaves;
+         wv += (int64_t)gridDim.x * (kThreads / 64)) {
+        const int64_t e0 = wv * 1024 + (int64_t)lane * 16;  // whole blocks: valid or not as a block
+        const bool valid = e0 < E;
+        C v[16];
+        if (valid) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                T vals[V];
+                *reinterpret_cast<uint4*>(vals) = gload16<true>(in + e0 + q * V);
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[q * V + e] = to_c(vals[e]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = czero<C>();
+        }
+        // register digits 0..3 (k >= 5: all four exist)
+        if constexpr (std::is_same<C, uint32_t>::value) {
+            if (h2)
+                BlockAllH2<C, 4, 0>::run(v);
+            else
+                BlockAll<C, 2, 4, 0>::run(v, w);
+        } else {
+            BlockAll<C, 2, 4, 0>::run(v, w);
+        }
+        // lane digits 4..k-1 (the same k for every lane: no divergence)
+        const int kl = a.k - 4;
+        if (kl > 0) lane_digit<1>(v, w, lane, h2);
+        if (kl > 1) lane_digit<2>(v, w, lane, h2);
+        if (kl > 2) lane_digit<4>(v, w, lane, h2);
+        if (kl > 3) lane_digit<8>(v, w, lane, h2);
+        if (kl > 4) lane_digit<16>(v, w, lane, h2);
+        if (kl > 5) lane_digit<32>(v, w, lane, h2);
+        if (valid) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                T vals[V];
+#pragma unroll
+                for (int e = 0; e < V; ++e) vals[e] = from_c<T>(v[q * V + e]);
+                gstore16<true>(out + e0 + q * V, *reinterpret_cast<const uint4*>(vals));
+            }
+        }
+    }
+}
+
+// the wave form applies: radix 2, digits 0..k-1 of contiguous 16-byte-vector
+// tiles (groups starting at digit 0), 5 <= k <= 10, no filter mask, 16
+// elements a lane in whole 16-byte vectors
+template <typename T>
+__host__ __device__ inline bool wave2_ok(const PassArgs& a) {
+    return a.mode == kContigVec && a.logC == 0 && a.S == 1 && a.k >= 5 && a.k <= 10 && a.cut < 0 &&
+           (16 * sizeof(T)) % 16 == 0 && sizeof(T) <= 16;
+}
+
 }  // namespace gtt
 
 namespace gtt {

@@ -278,3 +278,21 @@ def test_strided_or_conjugate_views_are_refused():
         plan.forward(W.conj(), x)
     with pytest.raises(ValueError):
         plan.forward(W, x.t().contiguous().t())      # column-major (2, N)
+
+
+# radix 2 with at most ten digits in the group that starts at digit 0: the
+# wavefront form (digits 0-3 in registers, 4..k-1 across lanes by DPP /
+# ds_bpermute, no LDS); batches whose element count is not a multiple of
+# the 1024 elements one wave covers, forward and inverse
+@pytest.mark.parametrize("dtype", FLOAT_DTYPES, ids=str)
+@pytest.mark.parametrize("n,batch", [(5, 3), (6, 1), (7, 5), (8, 2), (9, 3), (10, 1), (10, 6)])
+def test_radix2_wavefront_digits(n, batch, dtype):
+    say(f"radix-2 wavefront n={n} batch={batch} dtype={dtype}")
+    x, W, x64, W64 = make_inputs(2, n, batch, dtype, seed=1700 + n + batch)
+    plan = G.Plan(2, n, batch, dtype)
+    y = plan.forward(W, x)
+    xr = plan.inverse(W, y)
+    torch.cuda.synchronize()
+    ref = O.staged(W64, x64, n)
+    assert rel_err(host64(y), ref) < TOL[dtype]
+    assert rel_err(host64(xr), O.adjoint(W64, ref, n)) < TOL[dtype]
