@@ -675,32 +675,59 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 template <int MASK>
 __device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
-    if constexpr (MASK == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
-    else if constexpr (MASK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
-    else return (uint32_t)__shfl_xor((int)v, MASK, 64);
-}
-template <int MASK, typename C>
-__device__ __forceinline__ C lane_xor(C v) {
-    static_assert(sizeof(C) % 4 == 0, "32-bit words");
-    uint32_t w[sizeof(C) / 4];
-    __builtin_memcpy(w, &v, sizeof(C));
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(C) / 4); ++i) w[i] = lane_xor32<MASK>(w[i]);
-    C r;
-    __builtin_memcpy(&r, w, sizeof(C));
-    return r;
+    static_assert(MASK == 1 || MASK == 2 || MASK == 4 || MASK == 8, "DPP lane exchange");
+    if constexpr (MASK == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+    if constexpr (MASK == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    if constexpr (MASK == 4) {  // half-row mirror (lane ^ 7), then quad [3,2,1,0] (lane ^ 3)
+        const int t = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);
+    }
+    // MASK 8: row mirror (lane ^ 15), then half-row mirror (lane ^ 7)
+    const int t = __builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false);
 }
 
-// lane digit d = 4 + log2(MASK): y = W[bit][0] x_lo + W[bit][1] x_hi with
-// (x_lo, x_hi) = (own, partner) when the lane's bit is 0, else (partner, own)
+// The pair (x_lo, x_hi) of the butterfly across lane bit log2(MASK): the
+// values of the lane with that bit clear and of the lane with it set.  Lane
+// bits 0-3 move data with DPP (the partner's value, then a select); bits 4
+// and 5 with the permlane swaps, which hand every lane both halves at once
+// (a swap of a register with a copy of itself leaves the low row or half in
+// the first result and the high one in the second).  All VALU: no LDS.
+template <int MASK, typename C>
+__device__ __forceinline__ void lane_pair(const C& v, bool hi, C& lo_v, C& hi_v) {
+    static_assert(sizeof(C) % 4 == 0, "32-bit words");
+    constexpr int NW = (int)(sizeof(C) / 4);
+    uint32_t w[NW], lo[NW], hw[NW];
+    __builtin_memcpy(w, &v, sizeof(C));
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        if constexpr (MASK == 16) {
+            const auto r = __builtin_amdgcn_permlane16_swap(w[i], w[i], false, false);
+            lo[i] = r[0];
+            hw[i] = r[1];
+        } else if constexpr (MASK == 32) {
+            const auto r = __builtin_amdgcn_permlane32_swap(w[i], w[i], false, false);
+            lo[i] = r[0];
+            hw[i] = r[1];
+        } else {
+            const uint32_t p = lane_xor32<MASK>(w[i]);
+            lo[i] = hi ? p : w[i];
+            hw[i] = hi ? w[i] : p;
+        }
+    }
+    __builtin_memcpy(&lo_v, lo, sizeof(C));
+    __builtin_memcpy(&hi_v, hw, sizeof(C));
+}
+
+// one digit held across lane bit log2(MASK): the lane with the bit clear keeps
+// W[0][0] x_lo + W[0][1] x_hi, the lane with it set W[1][0] x_lo + W[1][1] x_hi
 template <int MASK, typename C>
 __device__ __forceinline__ void lane_digit(C (&v)[16], const C (&w)[4], uint32_t lane, bool h2) {
     const bool hi = (lane & MASK) != 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const C p = lane_xor<MASK>(v[r]);
-        const C lo_v = hi ? p : v[r];
-        const C hi_v = hi ? v[r] : p;
+        C lo_v, hi_v;
+        lane_pair<MASK>(v[r], hi, lo_v, hi_v);
         if constexpr (std::is_same<C, uint32_t>::value) {
             if (h2) {  // integer Hadamard: add / subtract
                 v[r] = hi ? lo_v - hi_v : lo_v + hi_v;
@@ -711,6 +738,28 @@ __device__ __forceinline__ void lane_digit(C (&v)[16], const C (&w)[4], uint32_t
     }
 }
 
+// register digit D of a 16-register block (both the general and the integer
+// Hadamard form)
+template <typename C, int D>
+__device__ __forceinline__ void reg_digit(C (&v)[16], const C (&w)[4], bool h2) {
+    if constexpr (std::is_same<C, uint32_t>::value) {
+        if (h2) {
+            block_digit_h2<C, 4, D>(v);
+            return;
+        }
+    }
+    block_digit<C, 2, 4, D>(v, w);
+}
+
+// Radix 2 with no LDS and no barrier: one wave holds 1024 elements, 16 per
+// lane.  Element i of the wave's block sits in register e + V q of lane l
+// where i = e + V (l + 64 q) (V elements per 16-byte vector, e < V): every
+// load or store instruction of the wave covers 1 KiB of contiguous memory.
+// Digit d of i (the factors act digit by digit, in any order, Eq. (1)) is
+// thus register bit d for d < log2 V, lane bit d - log2 V up to log2 V + 5,
+// and register bit d - 6 above; the register digits of a k-digit group are
+// the low max(log2 V, k - 6) register bits, the lane digits the low
+// min(k - log2 V, 6) lane bits.  The grid loops over blocks.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gtt_pass_wave2_kernel(PassArgs a) {
     using C = typename Tr<T>::C;
@@ -724,49 +773,51 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_wave2_kernel(PassArgs a) {
     T* out = static_cast<T*>(a.out);
     const uint32_t lane = threadIdx.x & 63;
     constexpr int V = Vec16<T>::V;  // storage elements per 16-byte vector
-    constexpr int NV = 16 / V;       // vectors per lane
+    constexpr int LV = V == 1 ? 0 : V == 2 ? 1 : V == 4 ? 2 : 3;
+    constexpr int NV = 16 / V;  // vectors per lane
+    static_assert((1 << LV) == V && NV * V == 16, "16 elements a lane in whole 16-byte vectors");
+    const int rd = a.k - 6 > LV ? a.k - 6 : LV;  // register digits
+    const int nl = a.k - LV < 6 ? a.k - LV : 6;  // lane digits
     const int64_t nwaves = (E + 1023) / 1024;
     for (int64_t wv = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); wv < nwaves;
          wv += (int64_t)gridDim.x * (kThreads / 64)) {
-        const int64_t e0 = wv * 1024 + (int64_t)lane * 16;  // whole blocks: valid or not as a block
-        const bool valid = e0 < E;
+        // E is a multiple of 2^k >= 32 elements: a 16-byte vector is wholly
+        // inside or wholly past the end, and a transform vector too (its
+        // zero-filled lanes mix only with each other and are not stored)
+        const int64_t base = wv * 1024 + (int64_t)lane * V;
         C v[16];
-        if (valid) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
+        for (int q = 0; q < NV; ++q) {
+            const int64_t e0 = base + (int64_t)q * 64 * V;
+            if (e0 < E) {
                 T vals[V];
-                *reinterpret_cast<uint4*>(vals) = gload16<true>(in + e0 + q * V);
+                *reinterpret_cast<uint4*>(vals) = gload16<true>(in + e0);
 #pragma unroll
                 for (int e = 0; e < V; ++e) v[q * V + e] = to_c(vals[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[q * V + e] = czero<C>();
             }
-        } else {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = czero<C>();
         }
-        // register digits 0..3 (k >= 5: all four exist)
-        if constexpr (std::is_same<C, uint32_t>::value) {
-            if (h2)
-                BlockAllH2<C, 4, 0>::run(v);
-            else
-                BlockAll<C, 2, 4, 0>::run(v, w);
-        } else {
-            BlockAll<C, 2, 4, 0>::run(v, w);
-        }
-        // lane digits 4..k-1 (the same k for every lane: no divergence)
-        const int kl = a.k - 4;
-        if (kl > 0) lane_digit<1>(v, w, lane, h2);
-        if (kl > 1) lane_digit<2>(v, w, lane, h2);
-        if (kl > 2) lane_digit<4>(v, w, lane, h2);
-        if (kl > 3) lane_digit<8>(v, w, lane, h2);
-        if (kl > 4) lane_digit<16>(v, w, lane, h2);
-        if (kl > 5) lane_digit<32>(v, w, lane, h2);
-        if (valid) {
+        // register digits (the same rd and nl in every lane: no divergence)
+        if (0 < rd) reg_digit<C, 0>(v, w, h2);
+        if (1 < rd) reg_digit<C, 1>(v, w, h2);
+        if (2 < rd) reg_digit<C, 2>(v, w, h2);
+        if (3 < rd) reg_digit<C, 3>(v, w, h2);
+        if (0 < nl) lane_digit<1>(v, w, lane, h2);
+        if (1 < nl) lane_digit<2>(v, w, lane, h2);
+        if (2 < nl) lane_digit<4>(v, w, lane, h2);
+        if (3 < nl) lane_digit<8>(v, w, lane, h2);
+        if (4 < nl) lane_digit<16>(v, w, lane, h2);
+        if (5 < nl) lane_digit<32>(v, w, lane, h2);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
+        for (int q = 0; q < NV; ++q) {
+            const int64_t e0 = base + (int64_t)q * 64 * V;
+            if (e0 < E) {
                 T vals[V];
 #pragma unroll
                 for (int e = 0; e < V; ++e) vals[e] = from_c<T>(v[q * V + e]);
-                gstore16<true>(out + e0 + q * V, *reinterpret_cast<const uint4*>(vals));
+                gstore16<true>(out + e0, *reinterpret_cast<const uint4*>(vals));
             }
         }
     }
