@@ -156,7 +156,15 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _stream():
+# the current stream's raw handle for the device of `t` (torch's C-level
+# query; torch.cuda.current_stream() builds a Stream object, a few
+# microseconds, which at one 1024-element vector is a third of a call)
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream(t: Optional[torch.Tensor] = None):
+    if t is not None and _raw_stream is not None:
+        return ctypes.c_void_p(_raw_stream(t.device.index))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -178,6 +186,7 @@ class Plan:
         L = lib()
         self.dtype = dtype
         self.flags = flags
+        self._wsz = None
         if _handle is not None:
             self._h = _handle
             return
@@ -225,10 +234,14 @@ class Plan:
         return self._h
 
     def workspace_size(self):
-        f, b, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib().gtt_workspace_size(self._h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(s)),
-               "gtt_workspace_size")
-        return f.value, b.value, s.value
+        """(forward, backward, saved) workspace bytes: fixed when the plan is
+        made, so asked once."""
+        if self._wsz is None:
+            f, b, s = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+            _check(lib().gtt_workspace_size(self._h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(s)),
+                   "gtt_workspace_size")
+            self._wsz = (f.value, b.value, s.value)
+        return self._wsz
 
     def describe(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
@@ -267,7 +280,7 @@ class Plan:
             y = torch.empty_like(x)
         fwd, _, _ = self.workspace_size()
         ws = self._ws(fwd, x.device)
-        _check(lib().gtt_forward(self._h, _ptr(W), _ptr(x), _ptr(y), _ptr(saved), _ptr(ws), fwd, _stream()),
+        _check(lib().gtt_forward(self._h, _ptr(W), _ptr(x), _ptr(y), _ptr(saved), _ptr(ws), fwd, _stream(x)),
                "gtt_forward")
         return y
 
@@ -276,7 +289,7 @@ class Plan:
             x = torch.empty_like(y)
         fwd, _, _ = self.workspace_size()
         ws = self._ws(fwd, y.device)
-        _check(lib().gtt_inverse(self._h, _ptr(W), _ptr(y), _ptr(x), _ptr(ws), fwd, _stream()), "gtt_inverse")
+        _check(lib().gtt_inverse(self._h, _ptr(W), _ptr(y), _ptr(x), _ptr(ws), fwd, _stream(y)), "gtt_inverse")
         return x
 
     def backward(self, W: torch.Tensor, x: torch.Tensor, gy: torch.Tensor, saved: Optional[torch.Tensor] = None,
@@ -291,7 +304,7 @@ class Plan:
         ws = self._ws(need, x.device)
         _check(lib().gtt_backward(self._h, _ptr(W), _ptr(x), _ptr(saved), _ptr(gy),
                                   _ptr(gx) if want_gx else None, _ptr(gW) if want_gW else None,
-                                  _ptr(ws), need, _stream()), "gtt_backward")
+                                  _ptr(ws), need, _stream(x)), "gtt_backward")
         return (gx if want_gx else None), (gW if want_gW else None)
 
     def filter(self, W: torch.Tensor, x: torch.Tensor, cutoff: int, low=True, high=True):
@@ -301,7 +314,7 @@ class Plan:
         need = fwd + x.numel() * x.element_size()
         ws = self._ws(need, x.device)
         _check(lib().gtt_filter(self._h, _ptr(W), _ptr(x), int(cutoff), _ptr(lo), _ptr(hi), _ptr(ws), need,
-                                _stream()), "gtt_filter")
+                                _stream(x)), "gtt_filter")
         return lo, hi
 
 
@@ -316,7 +329,7 @@ def _compress(self, W: torch.Tensor, x: torch.Tensor, k: int, reconstruct: bool 
     need = fwd + x.numel() * x.element_size()
     ws = self._ws(need, x.device)
     _check(lib().gtt_compress(self._h, _ptr(W), _ptr(x), int(k), _ptr(idx), _ptr(val), _ptr(recon), _ptr(ws), need,
-                              _stream()), "gtt_compress")
+                              _stream(x)), "gtt_compress")
     return idx, val, recon
 
 
