@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -93,15 +94,28 @@ def dominant(timing: dict):
     return name, t, achieved
 
 
+# C/C++ tokens that matter for stripping comments: string and character
+# literals (kept whole, so a "//" inside one is not a comment), comments
+_CXX_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def _code_only(src: str) -> str:
+    """C++ source without comments and with runs of blank space collapsed."""
+    body = _CXX_TOKENS.sub(lambda m: " " if m.group(0)[0] == "/" else m.group(0), src)
+    return " ".join(body.split())
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the HIP/C++ sources of libgtt.so (sorted by name)."""
+    """SHA-256 over the code of libgtt.so's HIP/C++ sources (sorted by name;
+    comments and layout do not count: a counter table stays valid across a
+    comment edit, and goes stale with any change to the code)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2507_02420_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp", ".cpp")):
             h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+            h.update(_code_only(open(os.path.join(d, f), encoding="utf-8").read()).encode())
     return h.hexdigest()
 
 

@@ -666,12 +666,9 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
 
 // ---------------------------------------------------------------------------
 // Radix 2, digits 0..k-1 (5 <= k <= 10) of blocks of 2^k contiguous elements
-// on wavefronts alone: lane l of a block holds its elements 16 l .. 16 l + 15
-// in registers, so digits 0-3 are register digits (applied as in a
-// super-stage) and digits 4..k-1 are lane digits: the partner of lane l for
-// digit d is lane l ^ 2^(d-4), reached by a cross-lane move (a DPP quad
-// permute for d = 4, 5, a ds_bpermute otherwise).  No LDS, no barriers; one
-// wave covers 1024 elements (64 >> (k-4) blocks).
+// on wavefronts alone: a wave holds 1024 elements (2^(10-k) blocks), 16 a
+// lane; every digit is either a butterfly between two registers of a lane or
+// one between two lanes (a cross-lane move).  No LDS, no barriers.
 // ---------------------------------------------------------------------------
 template <int MASK>
 __device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
