@@ -202,6 +202,15 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         gr->mode = kRowVec;
     } else {
         gr->mode = kRowScalar;
+        // element-wise rows: at most one work-group's threads wide, so a
+        // thread keeps its column over the tile (the kernels' address walk)
+        if (gr->C > kThreads) {
+            gr->C = kThreads;
+            gr->logC = ilog2_floor((uint64_t)gr->C);
+            gr->L = (gr->S + gr->C - 1) / gr->C;
+            gr->ntiles = (hi_total / gr->P) * gr->L;
+            gr->tileE = (int64_t)gr->P * gr->G * gr->C;
+        }
     }
     (void)V;
     gr->kind = kind;
@@ -248,10 +257,11 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
         int64_t wtot = 0;
         for (int j = 0; j < k; ++j) wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
         gr->wtotal = (int)wtot;
-        gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * tileE) * csize;
+        gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * gr->tileE) * csize;
         gr->pad_shift = kNoPad;
     } else {
-        const int64_t phys = lds16 ? 2 * lds_tile_elems_host((tileE + 1) / 2, pad) : lds_tile_elems_host(tileE, pad);
+        const int64_t phys =
+            lds16 ? 2 * lds_tile_elems_host((gr->tileE + 1) / 2, pad) : lds_tile_elems_host(gr->tileE, pad);
         gr->wtotal = 0;
         gr->lds_bytes = (size_t)phys * csize;
     }

@@ -342,8 +342,55 @@ __device__ __forceinline__ VecWalk vec_walk(const PassArgs& a, int64_t t, uint32
     return w;
 }
 
-// NT: threads of the work-group (every thread takes part)
-template <typename T, typename C, int NT = kThreads>
+// Scalar tiles as an address walk (NT = kThreads threads): element
+// i = tid + m * NT of tile t lies at global element g0 + m * gstep and at
+// LDS element l0 + m * lstep, and a thread's elements are all inside the
+// tile's valid columns or all outside (valid).  This holds for contiguous
+// tiles, and for row tiles of one hi block (P == 1) whose rows have at most
+// NT columns (a thread keeps its column; the planner caps scalar rows at NT
+// columns); on the LDS side when every pad period divides NT
+// (scalar_walk_ok checks all of it).  The walk replaces a 64-bit row offset
+// (with its divisions) per element by one add.
+struct ScalarWalk {
+    int64_t g0, gstep;
+    uint32_t l0, lstep;
+    bool valid;
+};
+__device__ __forceinline__ bool scalar_walk_ok(const PassArgs& a) {
+    constexpr int lim = __builtin_ctz(kThreads);
+    for (int k = 0; k < 3; ++k) {
+        const int sh = (a.pad_shift >> (8 * k)) & 31;
+        if (sh != 31 && sh > lim) return false;
+    }
+    if (a.mode == kContigScalar) return true;
+    return a.mode == kRowScalar && a.P == 1 && a.logC <= lim;
+}
+__device__ __forceinline__ ScalarWalk scalar_walk(const PassArgs& a, int64_t t, uint32_t tid) {
+    ScalarWalk w;
+    const uint32_t tileE = ((uint32_t)a.P * (uint32_t)a.G) << a.logC;
+    if (a.mode == kContigScalar) {
+        w.g0 = t * (int64_t)tileE + tid;
+        w.gstep = kThreads;
+        w.valid = true;
+    } else {
+        // row r = tid >> logC (+ m * NT >> logC), column c = tid & (C - 1)
+        const int64_t hb = tile_hb(a, t);
+        const int64_t l = t - hb * a.L;
+        const uint32_t c = tid & ((1u << a.logC) - 1u);
+        w.valid = (int64_t)c < a.S - (l << a.logC);
+        w.g0 = hb * ((int64_t)a.G * a.S) + (int64_t)(tid >> a.logC) * a.S + (l << a.logC) + c;
+        w.gstep = (int64_t)(kThreads >> a.logC) * a.S;
+    }
+    w.l0 = lds_phys(tid, a.pad_shift);
+    w.lstep = lds_phys(kThreads, a.pad_shift);
+    return w;
+}
+
+// NT: threads of the work-group (every thread takes part); SWALK: scalar
+// tiles take their addresses from a ScalarWalk where scalar_walk_ok allows
+// it (the walk costs registers beside the general path, so only kernels
+// whose tiles are mostly scalar enable it)
+template <typename T, typename C, int NT = kThreads, bool SWALK = false>
 __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __restrict__ in, int64_t t,
                                           uint32_t rows) {
     constexpr int V = Vec16<T>::V;
@@ -381,6 +428,22 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
                 }
             }
         }
+    } else if (SWALK && a.cut < 0 && scalar_walk_ok(a)) {
+        static_assert(!SWALK || NT == kThreads, "the scalar walk steps by kThreads");
+        const ScalarWalk w = scalar_walk(a, t, threadIdx.x);
+        for (uint32_t i0 = 0, m0 = 0; i0 < tileE; i0 += kLoadBatch * NT, m0 += kLoadBatch) {
+            T buf[kLoadBatch];
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * NT;
+                if (i < tileE) buf[v] = w.valid ? in[w.g0 + (int64_t)(m0 + v) * w.gstep] : from_c<T>(czero<C>());
+            }
+#pragma unroll
+            for (int v = 0; v < kLoadBatch; ++v) {
+                const uint32_t i = i0 + threadIdx.x + v * NT;
+                if (i < tileE) lds[w.l0 + (m0 + v) * w.lstep] = to_c(buf[v]);
+            }
+        }
     } else {
         for (uint32_t i0 = 0; i0 < tileE; i0 += kLoadBatch * NT) {
             T buf[kLoadBatch];
@@ -404,7 +467,7 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
     }
 }
 
-template <typename T, typename C, bool WALK = false, int NT = kThreads>
+template <typename T, typename C, bool WALK = false, int NT = kThreads, bool SWALK = false>
 __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* __restrict__ out, int64_t t,
                                            uint32_t rows) {
     constexpr int V = Vec16<T>::V;
@@ -433,6 +496,14 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
 #pragma unroll
             for (int e = 0; e < V; ++e) vals[e] = from_c<T>(lds[ph + e]);
             gstore16<true>(out + vec_offset<T>(a, t, i, hb, l, tileE), *reinterpret_cast<const uint4*>(vals));
+        }
+    } else if (SWALK && scalar_walk_ok(a)) {
+        static_assert(!SWALK || NT == kThreads, "the scalar walk steps by kThreads");
+        const ScalarWalk w = scalar_walk(a, t, threadIdx.x);
+        if (w.valid) {
+            uint32_t m = 0;
+            for (uint32_t i = threadIdx.x; i < tileE; i += NT, ++m)
+                out[w.g0 + (int64_t)m * w.gstep] = from_c<T>(lds[w.l0 + m * w.lstep]);
         }
     } else {
         for (uint32_t i = threadIdx.x; i < tileE; i += NT) {
@@ -504,6 +575,23 @@ __device__ __forceinline__ void pf_fetch_scalar(uint4 (&r)[kPfVec], const PassAr
     }
 }
 template <typename T, typename C, int M = 0>
+__device__ __forceinline__ void pf_fetch_scalar_walk(uint4 (&r)[kPfVec], const T* __restrict__ in, const ScalarWalk& w,
+                                                     uint32_t tid, uint32_t tileE) {
+    if constexpr (M < PfScalar<T>::N) {
+        if (tid + M * kThreads < tileE)
+            pf_set<T, M>(r, w.valid ? in[w.g0 + (int64_t)M * w.gstep] : from_c<T>(czero<C>()));
+        pf_fetch_scalar_walk<T, C, M + 1>(r, in, w, tid, tileE);
+    }
+}
+template <typename T, typename C, int M = 0>
+__device__ __forceinline__ void pf_commit_scalar_walk(C* lds, const uint4 (&r)[kPfVec], uint32_t l0, uint32_t lstep,
+                                                      uint32_t tid, uint32_t tileE) {
+    if constexpr (M < PfScalar<T>::N) {
+        if (tid + M * kThreads < tileE) lds[l0 + M * lstep] = to_c(pf_get<T, M>(r));
+        pf_commit_scalar_walk<T, C, M + 1>(lds, r, l0, lstep, tid, tileE);
+    }
+}
+template <typename T, typename C, int M = 0>
 __device__ __forceinline__ void pf_commit_scalar(C* lds, const uint4 (&r)[kPfVec], const PassArgs& a, uint32_t tid,
                                                  uint32_t tileE) {
     if constexpr (M < PfScalar<T>::N) {
@@ -521,7 +609,7 @@ __device__ __forceinline__ void pf_commit_scalar(C* lds, const uint4 (&r)[kPfVec
 // from LDS, so HBM stays busy through the LDS phases.  WALK: vector tiles
 // take their addresses from a VecWalk where vec_walk_ok allows it (costs
 // registers in every mode, so only kernels that meet vector tiles enable it).
-template <typename T, typename C, bool PF = false, bool WALK = false, typename Stages>
+template <typename T, typename C, bool PF = false, bool WALK = false, bool SWALK = false, typename Stages>
 __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& stages) {
     constexpr int V = Vec16<T>::V;
     const uint32_t rows = (uint32_t)a.P * (uint32_t)a.G;
@@ -539,6 +627,7 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
     }
     [[maybe_unused]] uint4 r[PF ? kPfVec : 1];
     [[maybe_unused]] const bool walk = WALK && vec && vec_walk_ok<T>(a);
+    [[maybe_unused]] const bool swalk = SWALK && !vec && scalar_walk_ok(a);
     // the per-item offsets are recomputed for every tile (an opaque thread
     // index): hoisted out of the tile loop they would hold registers per item
     auto fetch = [&](int64_t t) {
@@ -560,6 +649,8 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
                     const uint32_t i = tid + v * kThreads;
                     if (i < tileE / V) r[v] = gload16<true>(in + vec_offset<T>(a, t, i, hb, l, tileE));
                 }
+            } else if (swalk) {
+                pf_fetch_scalar_walk<T, C>(r, in, scalar_walk(a, t, tid), tid, tileE);
             } else {
                 pf_fetch_scalar<T, C>(r, a, in, t, tid, hb, l, tileE);
             }
@@ -583,6 +674,9 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
                         for (int e = 0; e < V; ++e) lds[ph + e] = to_c(vals[e]);
                     }
                 }
+            } else if (swalk) {
+                pf_commit_scalar_walk<T, C>(lds, r, lds_phys(tid, a.pad_shift), lds_phys(kThreads, a.pad_shift), tid,
+                                            tileE);
             } else {
                 pf_commit_scalar<T, C>(lds, r, a, tid, tileE);
             }
@@ -594,10 +688,10 @@ __device__ __forceinline__ void tile_loop(C* lds, const PassArgs& a, Stages&& st
         if (pf)
             commit();
         else
-            tile_load<T, C>(lds, a, in, t, rows);
+            tile_load<T, C, kThreads, SWALK>(lds, a, in, t, rows);
         __syncthreads();
         if (pf && t + gridDim.x < a.ntiles) fetch(t + gridDim.x);
-        if (!stages(lds, rows, t)) tile_store<T, C, WALK>(lds, a, out, t, rows);
+        if (!stages(lds, rows, t)) tile_store<T, C, WALK, kThreads, SWALK>(lds, a, out, t, rows);
         __syncthreads();
     }
 }
@@ -647,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_kernel(PassArgs a) {
         (a.mode == kContigVec ||
          (a.mode == kRowVec && a.P == 1 && (int64_t)a.G * a.S * (int64_t)sizeof(C) < (int64_t(1) << 31))) &&
         (int64_t)a.P * a.G * ((int64_t)sizeof(C) << a.logC) < (int64_t(1) << 31);
-    tile_loop<T, C, pass_prefetches<C, B>(), kPow2>(lds, a, [&](C* t, uint32_t rows, int64_t tile) {
+    tile_loop<T, C, pass_prefetches<C, B>(), kPow2, !kPow2>(lds, a, [&](C* t, uint32_t rows, int64_t tile) {
         if constexpr (kDirect) {
             if (direct) {
                 int64_t gt0 = tile * (int64_t)(rows << a.logC);

@@ -41,6 +41,30 @@ def test_forward_matches_oracle(b, n, dtype):
     assert err < TOL[dtype], (b, n, dtype, err, plan.describe())
 
 
+# odd and non-power-of-two radices: scalar tiles (16-byte vectors do not
+# fit b^k elements) take their addresses from a walk -- contiguous tiles and
+# row tiles (at most 256 columns, so a thread keeps its column; shapes whose
+# rows the planner would make wider are among these), with a partial last
+# column block, through the single-tile load and the prefetching persistent
+# loop (more tiles than the resident grid)
+@pytest.mark.parametrize("b,n,batch,dtype", [
+    (3, 9, 3, torch.float64), (3, 12, 8, torch.float32), (6, 6, 5, torch.float32), (6, 6, 64, torch.float32),
+    (7, 5, 16, torch.complex64), (7, 5, 64, torch.float32), (6, 5, 16, torch.float64), (5, 8, 8, torch.float32),
+    (3, 11, 16, torch.bfloat16), (3, 12, 24, torch.float32), (7, 5, 512, torch.float32)], ids=str)
+def test_scalar_tile_walks(b, n, batch, dtype):
+    say(f"scalar walk b={b} n={n} batch={batch} dtype={dtype}")
+    plan = G.Plan(b, n, batch, dtype)
+    groups = plan.describe()["groups"]
+    assert any(g["mode"] in (1, 3) for g in groups), groups  # a scalar tile mode is exercised
+    assert all(g["C"] <= 256 for g in groups if g["mode"] == 3), groups
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=5000 + 31 * b + n)
+    y = plan.forward(W, x)
+    xi = plan.inverse(W, x)
+    torch.cuda.synchronize()
+    assert rel_err(host64(y), O.staged(W64, x64, n)) < TOL[dtype], (b, n, batch, dtype, plan.describe())
+    assert rel_err(host64(xi), O.adjoint(W64, x64, n)) < TOL[dtype], (b, n, batch, dtype)
+
+
 # complex radix 8: every (digits, tile) variant of the matrix-core pass with
 # per-lane addresses (1-4 digits, 2048 / 4096 element tiles, contiguous and
 # strided groups) and the general kernel (8192 element tiles)
