@@ -544,9 +544,11 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
 #pragma unroll
     for (int e = 0; e < B * B; ++e) acc[e] = acc_zero(Acc{});
     C* Ct = slot(1);
+    // odd radices: element-wise tiles, addresses from the scalar walk
+    constexpr bool kScalarWalk = (B & (B - 1)) != 0;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C, NT>(slot(0), a, static_cast<const T*>(a.in), t, rows);
-        tile_load<T, C, NT>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
+        tile_load<T, C, NT, kScalarWalk>(slot(0), a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, C, NT, kScalarWalk>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
         __syncthreads();
         for (int o = 0; o < ba.nops; ++o) {
             const int op = ba.ops[o];
@@ -574,7 +576,7 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
         done:
             __syncthreads();
         }
-        if (a.out) tile_store<T, C, false, NT>(Ct, a, static_cast<T*>(a.out), t, rows);
+        if (a.out) tile_store<T, C, false, NT, kScalarWalk>(Ct, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
     // work-group total, fixed order: lanes by a shuffle tree, then waves

@@ -342,7 +342,7 @@ __device__ __forceinline__ VecWalk vec_walk(const PassArgs& a, int64_t t, uint32
     return w;
 }
 
-// Scalar tiles as an address walk (NT = kThreads threads): element
+// Scalar tiles as an address walk (NT threads): element
 // i = tid + m * NT of tile t lies at global element g0 + m * gstep and at
 // LDS element l0 + m * lstep, and a thread's elements are all inside the
 // tile's valid columns or all outside (valid).  This holds for contiguous
@@ -356,8 +356,9 @@ struct ScalarWalk {
     uint32_t l0, lstep;
     bool valid;
 };
+template <int NT = kThreads>
 __device__ __forceinline__ bool scalar_walk_ok(const PassArgs& a) {
-    constexpr int lim = __builtin_ctz(kThreads);
+    constexpr int lim = __builtin_ctz(NT);
     for (int k = 0; k < 3; ++k) {
         const int sh = (a.pad_shift >> (8 * k)) & 31;
         if (sh != 31 && sh > lim) return false;
@@ -365,12 +366,13 @@ __device__ __forceinline__ bool scalar_walk_ok(const PassArgs& a) {
     if (a.mode == kContigScalar) return true;
     return a.mode == kRowScalar && a.P == 1 && a.logC <= lim;
 }
+template <int NT = kThreads>
 __device__ __forceinline__ ScalarWalk scalar_walk(const PassArgs& a, int64_t t, uint32_t tid) {
     ScalarWalk w;
     const uint32_t tileE = ((uint32_t)a.P * (uint32_t)a.G) << a.logC;
     if (a.mode == kContigScalar) {
         w.g0 = t * (int64_t)tileE + tid;
-        w.gstep = kThreads;
+        w.gstep = NT;
         w.valid = true;
     } else {
         // row r = tid >> logC (+ m * NT >> logC), column c = tid & (C - 1)
@@ -379,10 +381,10 @@ __device__ __forceinline__ ScalarWalk scalar_walk(const PassArgs& a, int64_t t, 
         const uint32_t c = tid & ((1u << a.logC) - 1u);
         w.valid = (int64_t)c < a.S - (l << a.logC);
         w.g0 = hb * ((int64_t)a.G * a.S) + (int64_t)(tid >> a.logC) * a.S + (l << a.logC) + c;
-        w.gstep = (int64_t)(kThreads >> a.logC) * a.S;
+        w.gstep = (int64_t)(NT >> a.logC) * a.S;
     }
     w.l0 = lds_phys(tid, a.pad_shift);
-    w.lstep = lds_phys(kThreads, a.pad_shift);
+    w.lstep = lds_phys(NT, a.pad_shift);
     return w;
 }
 
@@ -428,9 +430,8 @@ __device__ __forceinline__ void tile_load(C* lds, const PassArgs& a, const T* __
                 }
             }
         }
-    } else if (SWALK && a.cut < 0 && scalar_walk_ok(a)) {
-        static_assert(!SWALK || NT == kThreads, "the scalar walk steps by kThreads");
-        const ScalarWalk w = scalar_walk(a, t, threadIdx.x);
+    } else if (SWALK && a.cut < 0 && scalar_walk_ok<NT>(a)) {
+        const ScalarWalk w = scalar_walk<NT>(a, t, threadIdx.x);
         for (uint32_t i0 = 0, m0 = 0; i0 < tileE; i0 += kLoadBatch * NT, m0 += kLoadBatch) {
             T buf[kLoadBatch];
 #pragma unroll
@@ -497,9 +498,8 @@ __device__ __forceinline__ void tile_store(const C* lds, const PassArgs& a, T* _
             for (int e = 0; e < V; ++e) vals[e] = from_c<T>(lds[ph + e]);
             gstore16<true>(out + vec_offset<T>(a, t, i, hb, l, tileE), *reinterpret_cast<const uint4*>(vals));
         }
-    } else if (SWALK && scalar_walk_ok(a)) {
-        static_assert(!SWALK || NT == kThreads, "the scalar walk steps by kThreads");
-        const ScalarWalk w = scalar_walk(a, t, threadIdx.x);
+    } else if (SWALK && scalar_walk_ok<NT>(a)) {
+        const ScalarWalk w = scalar_walk<NT>(a, t, threadIdx.x);
         if (w.valid) {
             uint32_t m = 0;
             for (uint32_t i = threadIdx.x; i < tileE; i += NT, ++m)
