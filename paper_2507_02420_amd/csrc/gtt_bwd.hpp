@@ -226,8 +226,9 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
     __syncthreads();
     C* Ct = slot(1);
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(slot(0), a, static_cast<const T*>(a.in), t, rows);
-        tile_load<T, C>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
+        // run-time radices: element-wise tiles take the scalar address walk
+        tile_load<T, C, kThreads, true>(slot(0), a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, C, kThreads, true>(Ct, a, static_cast<const T*>(ba.c_out), t, rows);
         __syncthreads();
         for (int o = 0; o < ba.nops; ++o) {
             const int op = ba.ops[o];
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
                 __syncthreads();
             }
         }
-        if (a.out) tile_store<T, C>(Ct, a, static_cast<T*>(a.out), t, rows);
+        if (a.out) tile_store<T, C, false, kThreads, true>(Ct, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
     // this work-group's partial vector in the W table's layout (zero outside
