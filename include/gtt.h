@@ -58,7 +58,7 @@ typedef enum gtt_status {
     GTT_ERR_DTYPE = 3,         /* unknown dtype */
     GTT_ERR_ALIGNMENT = 4,     /* a data pointer is not 16-byte aligned */
     GTT_ERR_WORKSPACE = 5,     /* ws_bytes smaller than the call needs */
-    GTT_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement */
+    GTT_ERR_UNSUPPORTED = 6,   /* valid request the library does not implement */
     GTT_ERR_HIP = 7,           /* a HIP runtime call or kernel launch failed */
     GTT_ERR_INTERNAL = 8,
     GTT_ERR_TIMEOUT = 9        /* a persistent ragged launch gave up waiting at a

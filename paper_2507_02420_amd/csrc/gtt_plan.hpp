@@ -45,7 +45,7 @@ struct Group {
     int bwd_rd = 0;      // > 0: register-block kernel, schedule over blocks of bwd_rd digits
     int bwd_maxb = 0;
     int bwd_wloc = 0;
-    bool bwd_ok = true;  // false: this build has no backward for the group
+    bool bwd_ok = true;  // false: no backward kernel covers the group
     std::vector<uint16_t> bwd_ops;
 };
 
