@@ -11,7 +11,8 @@ from paper_2507_02420_amd.inputs import hadamard2, int_uniform
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,batch", [(1, 3), (5, 2), (13, 2), (16, 3), (20, 2)])
+# n = 5..10 run the wave form (digits in registers and across lanes)
+@pytest.mark.parametrize("n,batch", [(1, 3), (5, 2), (6, 5), (8, 3), (9, 1), (10, 7), (13, 2), (16, 3), (20, 2)])
 def test_hadamard_int32_bit_exact(n, batch):
     say(f"int32 hadamard n={n} batch={batch}")
     H = hadamard2(False).astype(np.int64)
@@ -27,7 +28,7 @@ def test_hadamard_int32_bit_exact(n, batch):
     assert np.array_equal(back.cpu().numpy().astype(np.int64), x * (1 << n))
 
 
-@pytest.mark.parametrize("b,n", [(3, 7), (4, 6), (5, 4), (7, 4), (11, 3)])
+@pytest.mark.parametrize("b,n", [(2, 7), (2, 10), (3, 7), (4, 6), (5, 4), (7, 4), (11, 3)])
 def test_general_int32_wraparound(b, n):
     say(f"int32 general b={b} n={n}")
     rng = np.random.default_rng(b * 100 + n)
