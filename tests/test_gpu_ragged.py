@@ -50,6 +50,27 @@ SMALL = [(2, 11), (4, 3), (16, 2), (32, 2), (3, 4), (2, 0), (8, 3), (16, 3), (4,
          (16, 4), (2, 1), (4, 5), (5, 3), (32, 3), (2, 17), (3, 1), (6, 3)]
 
 
+# odd and mixed-parity radices large enough for a strided second digit group
+# (element-wise row tiles, at most 256 columns wide)
+ODD = [(7, 5), (6, 6), (3, 10), (5, 7), (3, 9), (2, 12), (7, 4)]
+
+
+@pytest.mark.parametrize("mode", list(MODES), ids=str)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64], ids=str)
+def test_ragged_odd_radix_strided_groups(mode, dtype):
+    say(f"ragged odd radices {mode} {dtype}")
+    xt, Wt, W64, widx, offs = _ragged_inputs(ODD, dtype, seed=900)
+    plan = G.Plan([b for b, _ in ODD], [n for _, n in ODD], 1, dtype, flags=MODES[mode])
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    x64, y64, xi64 = host64(xt), host64(y), host64(xi)
+    for t, ((b, n), o) in enumerate(zip(ODD, offs)):
+        N = b ** n
+        assert rel_err(y64[o:o + N], O.staged(W64[widx[t]], x64[o:o + N], n)) < TOL[dtype], (t, b, n)
+        assert rel_err(xi64[o:o + N], O.adjoint(W64[widx[t]], y64[o:o + N], n)) < TOL[dtype], (t, b, n)
+
+
 @pytest.mark.parametrize("mode", list(MODES), ids=str)
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, torch.complex64], ids=str)
 def test_ragged_forward_inverse(mode, dtype):
