@@ -7,14 +7,17 @@ digit groups) + gtt_backward, inputs resident in HBM.  value = elements per
 second of that step.
 
 The JSON line also carries:
-  roofline     -- the kernel with the largest share of the timed region: its
-                  algorithmic HBM bytes and matrix-core flops per launch over
-                  its HIP-event duration, against the 8 TB/s HBM peak and the
-                  157.3 TFLOP/s FP32 MFMA peak; "bound" is the resource whose
-                  time at peak is the larger (the roofline that binds), and
-                  both views are kept;
+  roofline     -- the kernel with the largest share of a step (found in a
+                  few steps with every launch timed, just before the timed
+                  region): its algorithmic HBM bytes and matrix-core flops per
+                  launch over its HIP-event duration inside the timed region
+                  (where only its launches carry events), against the 8 TB/s
+                  HBM peak and the 157.3 TFLOP/s FP32 MFMA peak; "bound" is
+                  the resource whose time at peak is the larger (the roofline
+                  that binds), and both views are kept;
   directions   -- forward and backward HBM rates (algorithmic bytes of all
-                  their launches over their summed durations);
+                  their launches over their summed durations, from those
+                  fully timed steps);
   cpu_baseline -- the FP64 oracle (numpy, one core) on a bounded sample of the
                   same workload, and the GPU error against it on that sample;
   workloads    -- the other configurations (single FP64 vector, complex64
@@ -172,7 +175,18 @@ def headline(steps, warmup):
     for _ in range(warmup):
         step()
     _sync()
+    # per-kernel breakdown, before the timed region: every launch bracketed
+    # by HIP events (the directions' rates and the dominant kernel's name)
+    nb = max(1, min(steps, 10))
     plan.timing(True)
+    for _ in range(nb):
+        step()
+    _sync()
+    breakdown = plan.timing_read()
+    dom_name = max(breakdown, key=lambda k: breakdown[k]["total_ms"])
+    # the timed region: events only around the dominant kernel's launches
+    # (events around every launch cost about 2 % of a step)
+    plan.timing_filter(dom_name)
     _sync()
     marks = [_events()[0] for _ in range(steps + 1)]
     t0 = time.perf_counter()
@@ -183,13 +197,15 @@ def headline(steps, warmup):
     _sync()
     wall = time.perf_counter() - t0
     plan.timing(False)
+    plan.timing_filter(None)
     per_step = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
     ms = marks[0].elapsed_time(marks[-1]) / steps
     timing = plan.timing_read()
     name, t, achieved = dominant(timing)
     q = lambda f: per_step[min(steps - 1, int(f * steps))]
     out = {
-        "E": E, "ms_per_step": ms, "wall_s": wall, "timing": timing, "plan": plan.describe(),
+        "E": E, "ms_per_step": ms, "wall_s": wall, "timing": timing, "breakdown": breakdown, "breakdown_steps": nb,
+        "plan": plan.describe(),
         "step_ms_p10_p50_p90": [q(0.1), q(0.5), q(0.9)],
         "dominant": name, "achieved_GBs": achieved, "bytes_per_launch": t["bytes_per_launch"],
         "tensors": (x, g, W, y, gx, gW),
@@ -664,12 +680,13 @@ def main():
             "hbm_view": hbm_view, "mfma_view": mfma_view,
             "round_trips_measured_over_algorithmic": (traffic / h["bytes_per_launch"]) if traffic else None,
             "copy_ceiling_GBs": copy_ceiling_gbs()}
+    # directions: kernel times of the breakdown steps (every launch timed)
     directions = {}
     for d, pref in (("forward", "pass"), ("backward", "bwd")):
-        ks = [v for k, v in h["timing"].items() if k.startswith(pref) or (d == "backward" and k.startswith("reduce"))]
+        ks = [v for k, v in h["breakdown"].items() if k.startswith(pref) or (d == "backward" and k.startswith("reduce"))]
         by = sum(v["bytes_per_launch"] * v["launches"] for v in ks)
         ms_ = sum(v["total_ms"] for v in ks)
-        directions[d] = {"ms": ms_ / args.steps, "GBs": by / (ms_ * 1e-3) / 1e9,
+        directions[d] = {"ms": ms_ / h["breakdown_steps"], "GBs": by / (ms_ * 1e-3) / 1e9,
                          "frac_of_hbm_peak": by / (ms_ * 1e-3) / 1e9 / HBM_PEAK_GBS}
     cpu = None
     if not args.no_cpu:
@@ -687,7 +704,9 @@ def main():
                    "b": 8, "n": 6, "batch": 256, "elements": E, "parallelism": "single GPU"},
         "roofline": roof, "directions": directions, "cpu_baseline": cpu,
         "kernels": {k: {kk: round(vv, 6) if isinstance(vv, float) else vv for kk, vv in v.items()}
-                    for k, v in h["timing"].items()},
+                    for k, v in h["breakdown"].items()},
+        "kernels_note": ("per-kernel HIP-event times of separate steps before the timed region; "
+                         "in the timed region only the dominant kernel carries events"),
         "workloads": extra,
     }
     print(json.dumps(line), flush=True)

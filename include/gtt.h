@@ -300,6 +300,14 @@ gtt_status gtt_plan_timing(gtt_plan_t p, int32_t enable);
 gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len);
 
 /*
+ * gtt_plan_timing_filter -- instrumentation: with timing enabled, bracket
+ * only the launches whose name (as gtt_plan_timing_read reports it) starts
+ * with `prefix`; the other launches record no events and cost nothing.
+ * NULL or "" times every launch again.  The string is copied.
+ */
+gtt_status gtt_plan_timing_filter(gtt_plan_t p, const char* prefix);
+
+/*
  * gtt_set_tuning -- override the launch heuristics for plans created after
  * this call, for radix b, digit count n (0: every n without an entry of its
  * own) and storage dtype (used by the autotuner; uniform plans and each

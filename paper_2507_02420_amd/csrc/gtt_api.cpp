@@ -535,7 +535,16 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     // with per-lane addresses, two 1024-thread work-groups per compute unit
     // looping over tiles with a register prefetch
     const int fast_ni = cut < 0 ? g.fast_ni : 0;
-    timing_begin(tp, s);
+    std::string nm;
+    if (tp && tp->timing.enabled) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "pass %s b=%d%s s0=%d k=%d%s", dt_name(dt), rad[g.s0],
+                      g.kind == kKindGeneric ? " generic" : g.kind == kKindMfma ? " mfma"
+                                                   : g.kind == kKindCMfma ? " cmfma" : "",
+                      g.s0, g.k, adjoint ? " adjoint" : "");
+        nm = buf;
+    }
+    timing_begin(tp, s, nm);
     hipError_t e;
     if (fast_ni) {
         grid = (unsigned)std::min<int64_t>(g.ntiles, 2 * 256);
@@ -543,14 +552,7 @@ static gtt_status launch_group(gtt_plan_s* tp, gtt_dtype dt, const Group& g, con
     } else {
         e = launch_pass(to_dt(dt), rad[g.s0], g.kind, a, grid, g.lds_bytes, s);
     }
-    if (tp && tp->timing.enabled) {
-        char nm[128];
-        std::snprintf(nm, sizeof nm, "pass %s b=%d%s s0=%d k=%d%s", dt_name(dt), rad[g.s0],
-                      g.kind == kKindGeneric ? " generic" : g.kind == kKindMfma ? " mfma"
-                                                   : g.kind == kKindCMfma ? " cmfma" : "",
-                      g.s0, g.k, adjoint ? " adjoint" : "");
-        timing_end(tp, s, nm, 2.0 * (double)g.elems * (double)storage_size(dt));
-    }
+    if (tp && tp->timing.enabled) timing_end(tp, s, nm, 2.0 * (double)g.elems * (double)storage_size(dt));
     return e == hipSuccess ? GTT_OK : GTT_ERR_HIP;
 }
 
@@ -845,6 +847,13 @@ gtt_status gtt_plan_timing(gtt_plan_t p, int32_t enable) {
     return GTT_OK;
 }
 
+gtt_status gtt_plan_timing_filter(gtt_plan_t p, const char* prefix) {
+    if (!p) return GTT_ERR_INVALID_VALUE;
+    p->timing.filter = prefix ? prefix : "";
+    if (p->inner) p->inner->timing.filter = p->timing.filter;
+    return GTT_OK;
+}
+
 gtt_status gtt_plan_timing_read(gtt_plan_t p, char* buf, size_t len) {
     if (!p || !buf || len == 0) return GTT_ERR_INVALID_VALUE;
     std::string s = timing_read(p);
@@ -1006,9 +1015,10 @@ extern "C" gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, i
     char* coef = static_cast<char*>(ws) + f;
     gtt_status st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, coef, nullptr, E, s);
     if (st != GTT_OK) return st;
-    timing_begin(p, s);
+    const std::string tnm = std::string("topk ") + dt_name(p->dtype);
+    timing_begin(p, s, tnm);
     if (launch_topk(to_dt(p->dtype), coef, p->N, p->batch, k, idx, val, recon, s) != hipSuccess) return GTT_ERR_HIP;
-    timing_end(p, s, std::string("topk ") + dt_name(p->dtype), (double)E * (double)p->esize * 5.0);
+    timing_end(p, s, tnm, (double)E * (double)p->esize * 5.0);
     if (recon)
         return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, recon, recon, nullptr, E, s);
     return GTT_OK;

@@ -154,7 +154,8 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
         pa.out = c_in;
         const unsigned grid = bwd_grid(G);
         int threads = 0;  // work-group size of a general-kernel launch
-        timing_begin(tp, s);
+        std::string nm;   // timing label (the general kernels' labels carry the work-group size)
+        const bool timed = tp && tp->timing.enabled;
         if (G.kind == kKindCMfma) {
             CBwdArgs ca;
             std::memset(&ca, 0, sizeof ca);
@@ -163,6 +164,12 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
             ca.partials = part;
             const int ni = G.fast_ni;
             const size_t lds = bwd_lds_bytes(G, dt);
+            if (timed) {
+                char buf[96];
+                std::snprintf(buf, sizeof buf, "bwd %s b=%d cmfma s0=%d k=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k);
+                nm = buf;
+            }
+            timing_begin(tp, s, nm);
             const hipError_t e = ni ? launch_cbwd8_fast(G.k, ni, ca, grid, lds, s) : launch_cbwd8(ca, grid, lds, s);
             if (e != hipSuccess) return GTT_ERR_HIP;
         } else {
@@ -203,19 +210,17 @@ static gtt_status bwd_run(gtt_plan_s* tp, gtt_dtype dt, const std::vector<Group>
             if (!shared_w && G.bwd_rd > 0) return GTT_ERR_INTERNAL;
             const size_t lds = bwd_lds_bytes(G, dt);
             threads = launch_bwd_threads(to_dt(dt), radix, lds);
+            if (timed) {
+                char buf[96];
+                std::snprintf(buf, sizeof buf, "bwd %s b=%d s0=%d k=%d wg=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k,
+                              threads);
+                nm = buf;
+            }
+            timing_begin(tp, s, nm);
             if (launch_bwd(to_dt(dt), ba, G.bwd_maxb, radix, grid, threads, lds, s) != hipSuccess)
                 return GTT_ERR_HIP;
         }
-        if (tp && tp->timing.enabled) {
-            // the general kernels' labels carry the work-group size
-            char nm[96];
-            if (G.kind == kKindCMfma)
-                std::snprintf(nm, sizeof nm, "bwd %s b=%d cmfma s0=%d k=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k);
-            else
-                std::snprintf(nm, sizeof nm, "bwd %s b=%d s0=%d k=%d wg=%d", kDtName[(int)dt], rad[G.s0], G.s0, G.k,
-                              threads);
-            timing_end(tp, s, nm, 3.0 * (double)G.elems * (double)es);
-        }
+        if (timed) timing_end(tp, s, nm, 3.0 * (double)G.elems * (double)es);
         part += (size_t)grid * wslot * as;
         c_out = c_in;
     }
@@ -314,9 +319,10 @@ gtt_status backward_impl(gtt_plan_s* p, const void* W, const void* x, const void
             if (R == 0) {
                 if (launch_zero(gW, (size_t)wslot * cs, s) != hipSuccess) return GTT_ERR_HIP;
             } else {
-                timing_begin(p, s);
+                const std::string rnm = std::string("reduce ") + kDtName[(int)p->dtype];
+                timing_begin(p, s, rnm);
                 if (launch_reduce(dt, partials, nparts, wslot, gW, s) != hipSuccess) return GTT_ERR_HIP;
-                timing_end(p, s, std::string("reduce ") + kDtName[(int)p->dtype], (double)nparts * wslot * as);
+                timing_end(p, s, rnm, (double)nparts * wslot * as);
             }
         }
         return GTT_OK;

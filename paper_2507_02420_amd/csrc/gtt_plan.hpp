@@ -85,6 +85,7 @@ struct TimedLaunch {
 };
 struct Timing {
     bool enabled = false;
+    std::string filter;  // time only launches whose name starts with it (empty: all)
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> pool;
 };
@@ -167,7 +168,7 @@ size_t backward_ws_need(const gtt_plan_s* p, bool have_saved, bool cb_in_gx);
 size_t f32_buf_bytes(const gtt_plan_s* p);
 std::string describe_plan(const gtt_plan_s* p);
 // bracket a launch with events when timing is enabled (no-ops otherwise)
-void timing_begin(gtt_plan_s* p, hipStream_t s);
+void timing_begin(gtt_plan_s* p, hipStream_t s, const std::string& name);
 void timing_end(gtt_plan_s* p, hipStream_t s, const std::string& name, double bytes);
 void timing_release(gtt_plan_s* p);
 std::string timing_read(gtt_plan_s* p);

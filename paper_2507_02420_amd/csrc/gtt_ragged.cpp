@@ -320,10 +320,10 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rs->grid_persistent, most));
         a.persistent = 1;
         if (launch_barrier_reset(rs->d_bar, s) != hipSuccess) return GTT_ERR_HIP;
-        timing_begin(p, s);
+        const std::string nm = std::string("ragged persistent ") + dn[(int)p->dtype];
+        timing_begin(p, s, nm);
         if (launch_ragged(dt, a, grid, rs->lds_max, s) != hipSuccess) return GTT_ERR_HIP;
-        timing_end(p, s, std::string("ragged persistent ") + dn[(int)p->dtype],
-                   2.0 * (double)p->total_elems * (double)p->esize * (double)a.nphases);
+        timing_end(p, s, nm, 2.0 * (double)p->total_elems * (double)p->esize * (double)a.nphases);
         return GTT_OK;
     }
     // one launch per run of one item class in a phase, in order on the
@@ -336,12 +336,13 @@ gtt_status ragged_apply(gtt_plan_s* p, const void* W, const void* in, void* out,
         a.phase_start[0] = sg.start;
         a.phase_start[1] = sg.end;
         const unsigned grid = (unsigned)std::min<int64_t>(sg.end - sg.start, (int64_t)0x7fffffff);
-        timing_begin(p, s);
+        std::string nm;
+        if (p->timing.enabled)
+            nm = std::string("ragged phase ") + std::to_string(sg.phase) + " " + dn[(int)p->dtype] +
+                 (sg.cls == kClsGeneric ? " generic" : (sg.cls >= 16 ? " mfma b=" : " b=") + std::to_string(sg.cls));
+        timing_begin(p, s, nm);
         if (launch_ragged_cls(dt, sg.cls, a, grid, sg.lds, s) != hipSuccess) return GTT_ERR_HIP;
-        timing_end(p, s,
-                   std::string("ragged phase ") + std::to_string(sg.phase) + " " + dn[(int)p->dtype] +
-                       (sg.cls == kClsGeneric ? " generic" : (sg.cls >= 16 ? " mfma b=" : " b=") + std::to_string(sg.cls)),
-                   sg.bytes);
+        timing_end(p, s, nm, sg.bytes);
     }
     return GTT_OK;
 }
@@ -421,8 +422,11 @@ static hipEvent_t pool_get(Timing& t) {
 
 static thread_local hipEvent_t t_open = nullptr;
 
-void timing_begin(gtt_plan_s* p, hipStream_t s) {
+void timing_begin(gtt_plan_s* p, hipStream_t s, const std::string& name) {
+    t_open = nullptr;
     if (!p || !p->timing.enabled) return;
+    const std::string& f = p->timing.filter;
+    if (!f.empty() && name.compare(0, f.size(), f) != 0) return;
     t_open = pool_get(p->timing);
     if (t_open) (void)hipEventRecord(t_open, s);
 }

@@ -41,7 +41,7 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 # every symbol declared in include/gtt.h
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
            "gtt_backward", "gtt_filter", "gtt_compress", "gtt_plan_destroy", "gtt_status_string",
-           "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_set_tuning",
+           "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_plan_timing_filter", "gtt_set_tuning",
            "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit", "gtt_backward_noalloc"]
 
 
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.gtt_plan_timing.argtypes = [vp, i32]
     L.gtt_plan_timing_read.argtypes = [vp, ctypes.c_char_p, sz]
+    L.gtt_plan_timing_filter.argtypes = [vp, ctypes.c_char_p]
     L.gtt_set_tuning.argtypes = [i32, i32, ctypes.c_int, i32, i32, i32, i32]
     L.gtt_selftest.argtypes = []
     L.gtt_plan_check.argtypes = [vp, vp]
@@ -251,6 +252,11 @@ class Plan:
     def timing(self, enable: bool = True):
         """Bracket every kernel launch of this plan with HIP events."""
         _check(lib().gtt_plan_timing(self._h, 1 if enable else 0), "gtt_plan_timing")
+
+    def timing_filter(self, prefix: Optional[str] = None):
+        """Time only the launches whose name starts with prefix (None: all)."""
+        _check(lib().gtt_plan_timing_filter(self._h, None if not prefix else prefix.encode()),
+               "gtt_plan_timing_filter")
 
     def timing_read(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
