@@ -331,11 +331,13 @@ def _flusher():
 
 
 def _timed_plan(p, fn, iters, flush=None):
-    """Median ms of fn() and the plan's per-kernel timing over the calls."""
+    """Median ms of fn() without instrumentation, and the plan's per-kernel
+    timing (HIP events around every launch) over as many further calls."""
     fn()
     _sync()
-    p.timing(True)
     ms, _ = time_calls(fn, iters, flush=flush)
+    p.timing(True)
+    time_calls(fn, iters, flush=flush)
     tm = p.timing_read()
     p.timing(False)
     return ms, tm
