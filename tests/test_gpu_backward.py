@@ -194,6 +194,32 @@ def test_full_size_differentiation_workload():
     assert err < 1e-5
 
 
+def test_full_size_complex_radix4_backward():
+    # 64 x c64, b=4, n=10 (the complex64 radix-4 workload; matrix-core
+    # gradient sums): the cotangent is nonzero on 8 instances spread over
+    # the batch, so gW is the oracle's sum over those 8, gx matches the
+    # oracle there and is exactly zero elsewhere
+    b, n, batch, dtype = 4, 10, 64, torch.complex64
+    say("full-size backward 64 x 4^10 c64")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=61)
+    live = [0, 9, 17, 30, 31, 44, 58, 63]
+    g = np.zeros((batch, b ** n), dtype=np.complex64)
+    g[live] = gaussian((len(live), b ** n), seed=63, complex_=True).astype(np.complex64)
+    plan = G.Plan(b, n, batch, dtype)
+    gt = torch.from_numpy(g).cuda()
+    gx, gW = plan.backward(W, x, gt)
+    torch.cuda.synchronize()
+    gx64 = host64(gx)
+    dead = [i for i in range(batch) if i not in live]
+    assert not np.any(gx64[dead]), "gx of zero cotangents"
+    rgx, rgW = O.grad(W64, x64[live], g[live].astype(np.complex128), n)
+    for j, i in enumerate(live):
+        assert rel_err(gx64[i], rgx[j]) < 1e-5, i
+    err = rel_err(host64(gW), rgW)
+    say(f"  gW rel err {err:.3e}")
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64, torch.complex128], ids=str)
 @pytest.mark.parametrize("radices,batch", [([2, 3, 4, 5], 3), ([3, 8, 2, 7, 4], 2), ([16, 2, 9], 2),
                                            ([32, 4], 3), ([5, 5, 5, 5, 5, 5, 5], 2), ([2] * 14 + [3], 1)])
