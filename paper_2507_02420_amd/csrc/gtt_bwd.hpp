@@ -511,10 +511,11 @@ __device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B
     }
 }
 
-// Complex radix 4, one digit per block: the gradient sums of a digit on
-// the FP32 matrix cores, the adjoint on the VALU.  The sum over fibres of
-// c a^H is a contraction over the fibre index: with c and a as real
-// 8-vectors (four real parts, then four imaginary parts), one 16x16x4 MFMA
+// Complex radix B = 3 or 4, one digit per block: the gradient sums of a
+// digit on the FP32 matrix cores, the adjoint on the VALU.  The sum over
+// fibres of c a^H is a contraction over the fibre index: with c and a as
+// real 8-vectors (B real parts, then B imaginary parts, each part padded with
+// zeros to four), one 16x16x4 MFMA
 // takes four fibres each of two sets (rows / columns 0-7: set 0, 8-15: set 1;
 // lane (m, k) supplies component m % 8 of fibre 4 (m / 8) + k of the set
 // group, for the cotangent (A) and the activation (B) alike), and the two
@@ -523,13 +524,18 @@ __device__ __forceinline__ void block_gw_adj(C* Ct, const C* act, const C (&w)[B
 // the operands from LDS at the fibre positions its lanes computed (a lane
 // shuffle) before any lane writes its adjoint back.  Each digit's FP32
 // chain over the tile is added into the lane's FP64 sums Md.
-__device__ __forceinline__ void block_gw_adj_c4_mfma(cf* Ct, const cf* act, const cf (&w)[16], double (&Md)[4],
-                                                     const PassArgs& a, int j, uint32_t rows, bool store, int nt) {
-    const BlockGeom<4, 1> g(a, j, rows);
+template <int B>
+__device__ __forceinline__ void block_gw_adj_cmfma(cf* Ct, const cf* act, const cf (&w)[B * B], double (&Md)[4],
+                                                   const PassArgs& a, int j, uint32_t rows, bool store, int nt) {
+    static_assert(B == 3 || B == 4, "complex radix 3 or 4");
+    const BlockGeom<B, 1> g(a, j, rows);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t m = lane & 15u, kk = lane >> 4;
     const uint32_t comp = (m >> 2) & 1u, r = m & 3u;
-    const uint32_t offr = r == 0 ? g.off[0] : r == 1 ? g.off[1] : r == 2 ? g.off[2] : g.off[3];
+    const bool rlive = r < (uint32_t)B;  // radix 3: component rows 3 and 7 are zero padding
+    uint32_t offr = g.off[0];
+#pragma unroll
+    for (int e = 1; e < B; ++e) offr = r == (uint32_t)e ? g.off[e] : offr;
     const uint32_t eidx = 2u * offr + comp;  // float index of the operand inside its fibre
     const float* Ctf = reinterpret_cast<const float*>(Ct);
     const float* actf = reinterpret_cast<const float*>(act);
@@ -544,19 +550,19 @@ __device__ __forceinline__ void block_gw_adj_c4_mfma(cf* Ct, const cf* act, cons
         for (int u = 0; u < 8; ++u) {
             const uint32_t p = (uint32_t)__shfl((int)ph0, 8 * u + srcbase, 64);
             float cvf = 0.f, avf = 0.f;
-            if (p != 0xffffffffu) {
+            if (p != 0xffffffffu && rlive) {
                 cvf = Ctf[2u * p + eidx];
                 avf = actf[2u * p + eidx];
             }
             D = __builtin_amdgcn_mfma_f32_16x16x4f32(cvf, avf, D, 0, 0, 0);
         }
         if (valid && store) {
-            cf cv[4];
+            cf cv[B];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) cv[e] = Ct[ph0 + g.off[e]];
-            block_digit_adj<cf, 4, 1, 0>(cv, w);
+            for (int e = 0; e < B; ++e) cv[e] = Ct[ph0 + g.off[e]];
+            block_digit_adj<cf, B, 1, 0>(cv, w);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Ct[ph0 + g.off[e]] = cv[e];
+            for (int e = 0; e < B; ++e) Ct[ph0 + g.off[e]] = cv[e];
         }
     }
 #pragma unroll
@@ -593,9 +599,9 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
     C w[B * B];
 #pragma unroll
     for (int e = 0; e < B * B; ++e) w[e] = Wg[e];
-    // complex radix 4: gradient sums on the matrix cores (FP64 sums of the
-    // 16x16 FP32 blocks per lane); otherwise per-thread FP64 accumulators
-    constexpr bool kMfmaGw = std::is_same<C, cf>::value && B == 4 && RD == 1;
+    // complex radix 3 and 4: gradient sums on the matrix cores (FP64 sums of
+    // the 16x16 FP32 blocks per lane); otherwise per-thread FP64 accumulators
+    constexpr bool kMfmaGw = std::is_same<C, cf>::value && (B == 3 || B == 4) && RD == 1;
     Acc acc[kMfmaGw ? 1 : B * B];
 #pragma unroll
     for (int e = 0; e < (kMfmaGw ? 1 : B * B); ++e) acc[e] = acc_zero(Acc{});
@@ -627,7 +633,7 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
                 if constexpr (RD >= 3) { if (r == 3) { block_gw_adj<C, Acc, B, 3, NT>(Ct, slot(src), w, acc, a, j0, rows, store); goto done; } }
                 if constexpr (RD >= 2) { if (r == 2) { block_gw_adj<C, Acc, B, 2, NT>(Ct, slot(src), w, acc, a, j0, rows, store); goto done; } }
                 if constexpr (kMfmaGw)
-                    block_gw_adj_c4_mfma(Ct, slot(src), w, Md, a, j0, rows, store, NT);
+                    block_gw_adj_cmfma<B>(Ct, slot(src), w, Md, a, j0, rows, store, NT);
                 else
                     block_gw_adj<C, Acc, B, 1, NT>(Ct, slot(src), w, acc, a, j0, rows, store);
             }
@@ -643,9 +649,10 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if constexpr (kMfmaGw) {
         // lane l holds D[4 (l / 16) + v][l % 16]: fold set 1's diagonal block
-        // (lane l + 40) onto set 0's, then lane q < 4 forms gradient entry
-        // (v, q): real part G[v][q] + G[4 + v][4 + q] (lanes q, 20 + q),
-        // imaginary part G[4 + v][q] - G[v][4 + q] (lanes 16 + q, 4 + q)
+        // (lane l + 40) onto set 0's, then lane q < B forms gradient entry
+        // (v, q), v < B: real part G[v][q] + G[4 + v][4 + q] (lanes q,
+        // 20 + q), imaginary part G[4 + v][q] - G[v][4 + q] (lanes 16 + q,
+        // 4 + q)
         double G8[4], re[4], im[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) G8[v] = Md[v] + __shfl_down(Md[v], 40, 64);
@@ -654,9 +661,9 @@ __global__ __launch_bounds__(NT) void gtt_bwd_block_kernel(BwdArgs ba) {
             re[v] = G8[v] + __shfl_down(G8[v], 20, 64);
             im[v] = __shfl_down(G8[v], 16, 64) - __shfl_down(G8[v], 4, 64);
         }
-        if (lane < 4) {
+        if (lane < B) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wave * (B * B) + v * B + lane] = cd{re[v], im[v]};
+            for (int v = 0; v < B; ++v) red[wave * (B * B) + v * B + lane] = cd{re[v], im[v]};
         }
     } else {
 #pragma unroll
