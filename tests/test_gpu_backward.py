@@ -220,6 +220,30 @@ def test_full_size_complex_radix4_backward():
     assert err < 1e-5
 
 
+def test_full_size_float32_radix3_backward():
+    # 16 x f32, b=3, n=13 (the odd-radix workload: register-block backward
+    # with element-wise tiles and the scalar address walk): cotangent on 4
+    # spread instances; gW against the oracle's sum over them, gx against the
+    # oracle there and exactly zero elsewhere
+    b, n, batch, dtype = 3, 13, 16, torch.float32
+    say("full-size backward 16 x 3^13 f32")
+    x, W, x64, W64 = make_inputs(b, n, batch, dtype, seed=71)
+    live = [0, 6, 11, 15]
+    g = np.zeros((batch, b ** n), dtype=np.float32)
+    g[live] = gaussian((len(live), b ** n), seed=73).astype(np.float32)
+    plan = G.Plan(b, n, batch, dtype)
+    gx, gW = plan.backward(W, x, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    gx64 = host64(gx)
+    assert not np.any(gx64[[i for i in range(batch) if i not in live]]), "gx of zero cotangents"
+    rgx, rgW = O.grad(W64, x64[live], g[live].astype(np.float64), n)
+    for j, i in enumerate(live):
+        assert rel_err(gx64[i], rgx[j]) < 1e-5, i
+    err = rel_err(host64(gW), rgW)
+    say(f"  gW rel err {err:.3e}")
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64, torch.complex128], ids=str)
 @pytest.mark.parametrize("radices,batch", [([2, 3, 4, 5], 3), ([3, 8, 2, 7, 4], 2), ([16, 2, 9], 2),
                                            ([32, 4], 3), ([5, 5, 5, 5, 5, 5, 5], 2), ([2] * 14 + [3], 1)])
