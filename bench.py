@@ -365,7 +365,7 @@ def _dominant_entry(tm, E, flops_per_elem_digit=None):
     return e
 
 
-def _backward_entry(p, W, x, iters=10, seed=7):
+def _backward_entry(p, W, x, iters=10, seed=7, alu=True):
     """Forward keeping the activations between digit groups, then the
     backward (gx and gW) of the same plan, timed alone: elements/s and HBM
     rate of the algorithmic bytes (read gy and x, write gx: 3 E s)."""
@@ -386,7 +386,8 @@ def _backward_entry(p, W, x, iters=10, seed=7):
     return {"ms": ms, "elements_per_s": E / (ms * 1e-3), "algorithmic_bytes": alg,
             "algorithmic_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "round_trips": len(p.describe()["bwd_groups"]),
-            **_dominant_entry(bw, E, (16 if x.is_complex() else 4) * p.describe()["b"]), "kernels": tm}
+            **_dominant_entry(bw, E, (16 if x.is_complex() else 4) * p.describe()["b"] if alu else None),
+            "kernels": tm}
 
 
 def wl_c1(iters=50, cpu=True):
@@ -614,9 +615,163 @@ def wl_c5(iters=5, cpu=True):
     return e
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3a": wl_c3a, "c3b": wl_c3b, "c5": wl_c5}
+def wl_mixed(iters=10, cpu=True):
+    """Distinct factors W_0 kron ... kron W_5 (remark on distinct tensor
+    factors after Def. 2.4), radices 8, 3, 4, 5, 2, 7 (N = 6720), 4096 x
+    complex64: forward then inverse, and the backward (gx and every
+    factor's gradient)."""
+    import re as _re
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+    radices, batch = [8, 3, 4, 5, 2, 7], 4096
+    N = int(np.prod(radices))
+    xn = gaussian((batch, N), seed=81, complex_=True).astype(np.complex64)
+    x = torch.from_numpy(xn).to(_gpu())
+    Ws = [haar_unitary(r, 82 + i).astype(np.complex64) for i, r in enumerate(radices)]
+    W = torch.cat([torch.from_numpy(w).reshape(-1) for w in Ws]).to(_gpu())
+    p = G.Plan.mixed(radices, batch, torch.complex64)
+    y = torch.empty_like(x)
+    xr = torch.empty_like(x)
+    ms, tm = _timed_plan(p, lambda: (p.forward(W, x, y), p.inverse(W, y, xr)), iters)
+    E = batch * N
+    err = float((torch.linalg.vector_norm(xr - x) / torch.linalg.vector_norm(x)).item())
+    e = {"radices": radices, "ms": ms, "elements_per_s": E / (ms * 1e-3), "roundtrip_rel_err": err,
+         **_dominant_entry(tm, E), "kernels": tm}
+    # ALU view of the dominant group: 8 b_j real flops per element and digit
+    # j of the group (digit j has the radix of factor m-1-j)
+    m_ = _re.search(r"s0=(\d+) k=(\d+)", e["dominant"])
+    if m_:
+        s0, k = int(m_.group(1)), int(m_.group(2))
+        rd = radices[::-1]
+        flops = 8.0 * E * sum(rd[s0:s0 + k])
+        e["alu_flops_per_launch"] = flops
+        e["alu_frac"] = flops / (e["dominant_avg_ms"] * 1e-3) / 1e12 / VALU_PEAK_TFLOPS
+    e["backward"] = _backward_entry(p, W, x, alu=False)
+    _with_copy(e, size_matched_copy(x, xr))
+    if cpu:
+        from oracle import gtt_oracle as O
+        Ws64 = [w.astype(np.complex128) for w in Ws]
+        x0 = xn[:4].astype(np.complex128)
+        r = oracle_rate(lambda: O.staged_mixed(Ws64, x0), 4 * N)
+        ref = r.pop("result")
+        r["sample"] = "instances 0-3 (4 x 6720), numpy staged forward with distinct factors"
+        e["cpu_oracle"] = r
+        e["rel_err_fwd_instances0_3_vs_oracle"] = float(np.linalg.norm(y[:4].cpu().numpy() - ref) /
+                                                        np.linalg.norm(ref))
+    return e
+
+
+def wl_filter(iters=10, cpu=True):
+    """Natural-order filter (classical form of Alg. 3): 64 x complex64,
+    b=4, n=10, cutoff N/2 -- forward, the coefficients split at the cut-off
+    (mask fused into the inverse's tile loads), both parts back."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+    b, n, batch = 4, 10, 64
+    N = b ** n
+    xn = gaussian((batch, N), seed=91, complex_=True).astype(np.complex64)
+    x = torch.from_numpy(xn).to(_gpu())
+    W = torch.from_numpy(haar_unitary(4, 92).astype(np.complex64)).to(_gpu())
+    p = G.Plan(b, n, batch, torch.complex64)
+    out = {}
+    ms, tm = _timed_plan(p, lambda: out.update(zip(("lo", "hi"), p.filter(W, x, N // 2))), iters)
+    E = batch * N
+    lo, hi = out["lo"], out["hi"]
+    split_err = float((torch.linalg.vector_norm(lo + hi - x) / torch.linalg.vector_norm(x)).item())
+    e = {"cutoff": N // 2, "ms": ms, "elements_per_s": E / (ms * 1e-3), "low_plus_high_vs_x_rel_err": split_err,
+         **_dominant_entry(tm, E, 8 * b), "kernels": tm}
+    if cpu:
+        from oracle import gtt_oracle as O
+        W64 = W.cpu().to(torch.complex128).numpy()
+        x0 = xn[0].astype(np.complex128)
+        r = oracle_rate(lambda: O.natural_filter(W64, x0, n, N // 2), N)
+        rlo, rhi = r.pop("result")
+        r["sample"] = "instance 0 (N=1048576), numpy forward, split, two inverses"
+        e["cpu_oracle"] = r
+        e["rel_err_low_instance0_vs_oracle"] = float(np.linalg.norm(lo[0].cpu().numpy() - rlo) / np.linalg.norm(rlo))
+        e["rel_err_high_instance0_vs_oracle"] = float(np.linalg.norm(hi[0].cpu().numpy() - rhi) / np.linalg.norm(rhi))
+    return e
+
+
+def wl_compress(iters=10, cpu=True):
+    """State transmission (§4.1.1): 16 x float32, b=2, n=20, the k = N/64
+    coefficients of largest magnitude per instance (radix select, ascending
+    indices) and the reconstruction from them."""
+    import torch
+    from paper_2507_02420_amd import gtt as G
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+    b, n, batch = 2, 20, 16
+    N = b ** n
+    k = N // 64
+    xn = gaussian((batch, N), seed=101).astype(np.float32)
+    x = torch.from_numpy(xn).to(_gpu())
+    W = torch.from_numpy(haar_unitary(2, 102, complex_=False).astype(np.float32)).to(_gpu())
+    p = G.Plan(b, n, batch, torch.float32)
+    out = {}
+    ms, tm = _timed_plan(p, lambda: out.update(zip(("idx", "val", "recon"), p.compress(W, x, k))), iters)
+    E = batch * N
+    e = {"k": k, "ms": ms, "elements_per_s": E / (ms * 1e-3), **_dominant_entry(tm, E), "kernels": tm}
+    if cpu:
+        from oracle import gtt_oracle as O
+        W64 = W.cpu().to(torch.float64).numpy()
+        x0 = xn[0].astype(np.float64)
+        r = oracle_rate(lambda: O.topk_compress(W64, x0, n, k), N)
+        ridx, rval, rrec = r.pop("result")
+        r["sample"] = "instance 0 (N=1048576), numpy forward, top-k, inverse"
+        e["cpu_oracle"] = r
+        e["instance0_indices_equal_oracle"] = bool(np.array_equal(out["idx"][0].cpu().numpy(), ridx))
+        e["rel_err_recon_instance0_vs_oracle"] = float(np.linalg.norm(out["recon"][0].cpu().numpy() - rrec) /
+                                                       np.linalg.norm(rrec))
+    return e
+
+
+def wl_wtune(steps=10, cpu=True):
+    """Gradient-based tuning of W (§4.2): 256 x complex64, b=8, n=4, k=64
+    kept coefficients; one step = top-k selection + backward (gW only) +
+    Cayley retraction, with the host reading the kept energy each step."""
+    import torch
+    from paper_2507_02420_amd import wtune
+    from paper_2507_02420_amd.inputs import gaussian, haar_unitary
+    b, n, batch, k = 8, 4, 256, 64
+    N = b ** n
+    xn = gaussian((batch, N), seed=111, complex_=True).astype(np.complex64)
+    x = torch.from_numpy(xn).to(_gpu())
+    W0 = torch.from_numpy(haar_unitary(8, 112).astype(np.complex64)).to(_gpu())
+    wtune.tune(x, W0, b, n, k, steps=2, backtrack=False)  # warm-up (plan, kernels)
+    _sync()
+    t0 = time.perf_counter()
+    res = wtune.tune(x, W0, b, n, k, steps=steps, backtrack=False)
+    _sync()
+    dt = (time.perf_counter() - t0) / steps
+    E = batch * N
+    e = {"k": k, "steps": steps, "ms_per_step": dt * 1e3, "elements_per_s": E / dt,
+         "kept_fraction_first_last": [res.kept_fraction[0], res.kept_fraction[-1]]}
+    if cpu:
+        from oracle import gtt_oracle as O
+        W64 = W0.cpu().to(torch.complex128).numpy()
+        x0 = xn[0].astype(np.complex128)
+
+        def one():
+            idx, val, _ = O.topk_compress(W64, x0, n, k)
+            g = np.zeros(N, dtype=np.complex128)
+            g[idx] = 2 * val
+            return O.grad(W64, x0, g, n)
+        r = oracle_rate(one, N)
+        r.pop("result")
+        r["sample"] = "instance 0 (N=4096): numpy forward, top-k and gradient (one step's transform work)"
+        e["cpu_oracle"] = r
+    return e
+
+
 WL_NAMES = {"c1": "f64_b2_n10", "c2": "c64_b4_n10_x64_fwd_inv", "c3a": "f32_b3_n13_x16_fwd",
-            "c3b": "i32_hadamard_b2_n20_x16_fwd", "c5": "ragged_bf16_1024"}
+            "c3b": "i32_hadamard_b2_n20_x16_fwd", "c5": "ragged_bf16_1024",
+            "mixed": "c64_mixed_8_3_4_5_2_7_x4096_fwd_inv", "filter": "c64_b4_n10_x64_filter",
+            "compress": "f32_b2_n20_x16_topk_n64", "wtune": "c64_b8_n4_x256_wtune_k64"}
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3a": wl_c3a, "c3b": wl_c3b, "c5": wl_c5,
+             "mixed": wl_mixed, "filter": wl_filter, "compress": wl_compress, "wtune": wl_wtune}
 
 
 def secondary(cpu=True, only=None):

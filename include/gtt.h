@@ -243,11 +243,20 @@ gtt_status gtt_filter(gtt_plan_t p, const void* W, const void* x, int64_t cutoff
  * written as idx[t][j] (int64, ascending) and val[t][j] (storage dtype),
  * t < batch, j < k; if recon != NULL also recon = G_N^dagger applied to the
  * vector that keeps only those k coefficients (the receiver's
- * reconstruction).  1 <= k <= N.  Uniform plans.  Needs gtt_workspace_size's
- * fwd bytes plus N*batch elements of the storage dtype in `ws`.
+ * reconstruction).  1 <= k <= N.  Uniform plans.  Needs
+ * gtt_compress_workspace_size bytes in `ws` (the coefficients, and for few
+ * large instances the selection's state, histograms and per-chunk counts);
+ * GTT_ERR_WORKSPACE when ws_bytes is smaller.
  */
 gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, int64_t k, int64_t* idx, void* val,
                         void* recon, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gtt_compress_workspace_size -- bytes of `ws` gtt_compress needs for this
+ * plan (independent of k).  GTT_ERR_UNSUPPORTED for plans gtt_compress
+ * refuses.
+ */
+gtt_status gtt_compress_workspace_size(gtt_plan_t p, size_t* bytes);
 
 /*
  * gtt_plan_check -- waits for the work enqueued on `stream`, then reports

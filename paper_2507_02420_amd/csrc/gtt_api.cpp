@@ -999,6 +999,16 @@ gtt_status filter_impl(gtt_plan_s* p, const void* W, const void* x, int64_t cuto
 }
 }  // namespace gtt
 
+extern "C" gtt_status gtt_compress_workspace_size(gtt_plan_t p, size_t* bytes) {
+    if (!p || !bytes) return GTT_ERR_INVALID_VALUE;
+    if (p->kind != PlanKind::Uniform || p->inner) return GTT_ERR_UNSUPPORTED;
+    size_t f = 0, bw = 0, sv = 0;
+    workspace_sizes(p, &f, &bw, &sv);
+    const size_t E = (size_t)p->total_elems;
+    *bytes = f + ((E * p->esize + 255) & ~(size_t)255) + topk_meta_bytes(p->N, p->batch);
+    return GTT_OK;
+}
+
 extern "C" gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, int64_t k, int64_t* idx, void* val,
                                    void* recon, void* ws, size_t ws_bytes, void* stream) {
     if (!p || !W || !x || !idx || !val) return GTT_ERR_INVALID_VALUE;
@@ -1007,17 +1017,21 @@ extern "C" gtt_status gtt_compress(gtt_plan_t p, const void* W, const void* x, i
         return GTT_ERR_ALIGNMENT;
     if (p->kind != PlanKind::Uniform || p->inner) return GTT_ERR_UNSUPPORTED;
     if (k < 1 || k > p->N) return GTT_ERR_INVALID_VALUE;
+    size_t need = 0;
+    gtt_compress_workspace_size(p, &need);
+    if (!ws || ws_bytes < need) return GTT_ERR_WORKSPACE;
     size_t f = 0, bw = 0, sv = 0;
     workspace_sizes(p, &f, &bw, &sv);
     const size_t E = (size_t)p->total_elems;
-    if (!ws || ws_bytes < f + E * p->esize) return GTT_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* coef = static_cast<char*>(ws) + f;
+    char* meta = coef + ((E * p->esize + 255) & ~(size_t)255);
     gtt_status st = run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, false, x, coef, nullptr, E, s);
     if (st != GTT_OK) return st;
     const std::string tnm = std::string("topk ") + dt_name(p->dtype);
     timing_begin(p, s, tnm);
-    if (launch_topk(to_dt(p->dtype), coef, p->N, p->batch, k, idx, val, recon, s) != hipSuccess) return GTT_ERR_HIP;
+    if (launch_topk(to_dt(p->dtype), coef, p->N, p->batch, k, idx, val, recon, meta, s) != hipSuccess)
+        return GTT_ERR_HIP;
     timing_end(p, s, tnm, (double)E * (double)p->esize * 5.0);
     if (recon)
         return run_groups(p, p->dtype, p->groups, p->rad, p->wofs, p->N, W, true, recon, recon, nullptr, E, s);

@@ -101,8 +101,11 @@ hipError_t launch_cbwd8_fast(int k, int ni, const CBwdArgs& a, unsigned grid, si
 // k dominant coefficients of every instance (ascending indices, ties to the
 // lower index); with recon != NULL also the zero-filled sparse coefficient
 // vector (the caller then applies the inverse transform in place)
+// (few large instances: many work-groups per instance, with `meta` bytes
+// of workspace from topk_meta_bytes; otherwise one work-group per instance)
 hipError_t launch_topk(DT dt, const void* coef, int64_t N, int64_t batch, int64_t k, int64_t* idx, void* val,
-                       void* recon, hipStream_t s);
+                       void* recon, void* meta, hipStream_t s);
+size_t topk_meta_bytes(int64_t N, int64_t batch);
 
 // elementwise storage conversion bf16/f16 <-> float32 (RNE to 16 bits)
 hipError_t launch_convert(DT from, DT to, const void* in, void* out, int64_t n, hipStream_t s);

@@ -46,8 +46,9 @@ __device__ __forceinline__ uint64_t topk_key(cd v) {
     return (uint64_t)__double_as_longlong(__builtin_fma(v.re, v.re, v.im * v.im));
 }
 
-// exclusive prefix count of flag over the work-group (in thread order) and
-// the total; wsum: kTopkThreads/64 ints of LDS
+// exclusive prefix count of flag over the work-group of NT threads (in
+// thread order) and the total; wsum: NT/64 ints of LDS
+template <int NT = kTopkThreads>
 __device__ __forceinline__ uint32_t block_excl_count(bool flag, uint32_t* wsum, uint32_t* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t m = __ballot(flag);
@@ -55,7 +56,7 @@ __device__ __forceinline__ uint32_t block_excl_count(bool flag, uint32_t* wsum, 
     if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
     __syncthreads();
     uint32_t before = 0, tot = 0;
-    for (int w = 0; w < kTopkThreads / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         const uint32_t c = wsum[w];
         if (w < wave) before += c;
         tot += c;
@@ -118,10 +119,10 @@ __global__ __launch_bounds__(kTopkThreads) void gtt_topk_kernel(const T* __restr
         const bool gt = in && key > thr;
         const bool eq = in && key == thr;
         uint32_t eq_tot;
-        const uint32_t eq_rank = block_excl_count(eq, wsum, &eq_tot);
+        const uint32_t eq_rank = block_excl_count<>(eq, wsum, &eq_tot);
         const bool take = gt || (eq && eq_seen + (int64_t)eq_rank < need_eq);
         uint32_t take_tot;
-        const uint32_t pos = block_excl_count(take, wsum, &take_tot);
+        const uint32_t pos = block_excl_count<>(take, wsum, &take_tot);
         if (take) {
             oi[out_seen + pos] = i;
             ov[out_seen + pos] = c[i];
@@ -130,6 +131,202 @@ __global__ __launch_bounds__(kTopkThreads) void gtt_topk_kernel(const T* __restr
         out_seen += take_tot;
         if (out_seen >= k) break;  // uniform: every thread sees the same totals
     }
+}
+
+// ---------------------------------------------------------------------------
+// The same selection spread over many work-groups per instance (few large
+// instances: one work-group each would leave most compute units idle).  An
+// instance is cut into chunks of kTopkChunk elements, one work-group each:
+//   per 8-bit digit of the key (most significant first): every chunk adds its
+//   histogram of the keys that match the prefix chosen so far into the
+//   instance's global histogram (atomics), then one work-group per instance
+//   picks the digit holding the k-th largest key and clears the histogram;
+//   ordered compaction: every chunk counts its keys above and equal to the
+//   threshold, one work-group per instance turns the counts into each
+//   chunk's output offset (chunks in index order: the elements above the
+//   threshold before the chunk, plus min(equal elements before it, equal
+//   elements needed)), and every chunk writes its elements in index order.
+// The state, histograms and per-chunk counts live in the caller's workspace.
+// ---------------------------------------------------------------------------
+constexpr int kTopkChunkThreads = 256;
+constexpr int kTopkChunk = kTopkChunkThreads * 16;
+
+struct TopkState {
+    uint64_t prefix, pmask;
+    int64_t remaining;
+    int64_t pad;
+};
+
+template <typename K>
+__global__ __launch_bounds__(256) void gtt_topk_init_kernel(TopkState* st, uint32_t* ghist, int64_t batch, int64_t k) {
+    const int64_t t = blockIdx.x;
+    if (t >= batch) return;
+    if (threadIdx.x == 0) st[t] = TopkState{0, 0, k, 0};
+    ghist[t * 256 + threadIdx.x] = 0u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_hist_kernel(const T* __restrict__ coef, int64_t N,
+                                                                          const TopkState* __restrict__ st,
+                                                                          uint32_t* __restrict__ ghist, int shift) {
+    using K = typename TopkKey<T>::K;
+    __shared__ uint32_t hist[256];
+    const int64_t t = blockIdx.y;
+    const int64_t c0 = (int64_t)blockIdx.x * kTopkChunk;
+    const int64_t c1 = c0 + kTopkChunk < N ? c0 + kTopkChunk : N;
+    hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const K prefix = (K)st[t].prefix, pmask = (K)st[t].pmask;
+    const T* c = coef + t * N;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kTopkChunkThreads) {
+        const K key = topk_key(c[i]);
+        if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t h = hist[threadIdx.x];
+    if (h) atomicAdd(&ghist[t * 256 + threadIdx.x], h);
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void gtt_topk_select_kernel(TopkState* st, uint32_t* ghist, int shift) {
+    const int64_t t = blockIdx.x;
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = ghist[t * 256 + threadIdx.x];
+    ghist[t * 256 + threadIdx.x] = 0u;  // clean for the next digit
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t remaining = st[t].remaining;
+        int64_t cum = 0;
+        int sel = 0;
+        for (int d = 255; d >= 0; --d) {
+            if (cum + (int64_t)h[d] >= remaining) {
+                sel = d;
+                break;
+            }
+            cum += h[d];
+        }
+        st[t].prefix = (uint64_t)((K)st[t].prefix | ((K)sel << shift));
+        st[t].pmask = (uint64_t)((K)st[t].pmask | ((K)255 << shift));
+        st[t].remaining = remaining - cum;
+    }
+}
+
+// per chunk: keys above and equal to the threshold (the final prefix)
+template <typename T>
+__global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_count_kernel(const T* __restrict__ coef, int64_t N,
+                                                                           int64_t nch, const TopkState* __restrict__ st,
+                                                                           uint32_t* __restrict__ cnt) {
+    using K = typename TopkKey<T>::K;
+    __shared__ uint32_t red[2];
+    const int64_t t = blockIdx.y;
+    const int64_t c0 = (int64_t)blockIdx.x * kTopkChunk;
+    const int64_t c1 = c0 + kTopkChunk < N ? c0 + kTopkChunk : N;
+    if (threadIdx.x < 2) red[threadIdx.x] = 0u;
+    __syncthreads();
+    const K thr = (K)st[t].prefix;
+    const T* c = coef + t * N;
+    uint32_t gt = 0, eq = 0;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kTopkChunkThreads) {
+        const K key = topk_key(c[i]);
+        gt += key > thr;
+        eq += key == thr;
+    }
+    if (gt) atomicAdd(&red[0], gt);
+    if (eq) atomicAdd(&red[1], eq);
+    __syncthreads();
+    if (threadIdx.x < 2) cnt[(t * nch + blockIdx.x) * 2 + threadIdx.x] = red[threadIdx.x];
+}
+
+// per instance: each chunk's output offset and the equal keys before it
+__global__ __launch_bounds__(256) void gtt_topk_scan_kernel(const TopkState* __restrict__ st,
+                                                            const uint32_t* __restrict__ cnt,
+                                                            int64_t* __restrict__ off, int64_t nch) {
+    __shared__ int64_t sg[256], se[256];
+    const int64_t t = blockIdx.x;
+    const int64_t per = (nch + 255) / 256;
+    const int64_t a = (int64_t)threadIdx.x * per;
+    const int64_t b = a + per < nch ? a + per : nch;
+    const uint32_t* ct = cnt + t * nch * 2;
+    int64_t g = 0, e = 0;
+    for (int64_t c = a; c < b; ++c) {
+        g += ct[2 * c];
+        e += ct[2 * c + 1];
+    }
+    sg[threadIdx.x] = g;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive scan of the 256 ranges, in order
+        int64_t rg = 0, re = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int64_t vg = sg[i], ve = se[i];
+            sg[i] = rg;
+            se[i] = re;
+            rg += vg;
+            re += ve;
+        }
+    }
+    __syncthreads();
+    const int64_t need_eq = st[t].remaining;
+    g = sg[threadIdx.x];
+    e = se[threadIdx.x];
+    int64_t* ot = off + t * nch * 2;
+    for (int64_t c = a; c < b; ++c) {
+        ot[2 * c] = g + (e < need_eq ? e : need_eq);  // output position of the chunk's first element
+        ot[2 * c + 1] = e;                            // equal keys before the chunk
+        g += ct[2 * c];
+        e += ct[2 * c + 1];
+    }
+}
+
+// per chunk: its elements above the threshold and the equal ones still
+// needed, in index order, at the chunk's output offset
+template <typename T>
+__global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_write_kernel(
+    const T* __restrict__ coef, int64_t N, int64_t nch, const TopkState* __restrict__ st,
+    const int64_t* __restrict__ off, int64_t k, int64_t* __restrict__ idx, T* __restrict__ val) {
+    using K = typename TopkKey<T>::K;
+    __shared__ uint32_t wsum[kTopkChunkThreads / 64];
+    const int64_t t = blockIdx.y;
+    const int64_t c0 = (int64_t)blockIdx.x * kTopkChunk;
+    const int64_t c1 = c0 + kTopkChunk < N ? c0 + kTopkChunk : N;
+    const K thr = (K)st[t].prefix;
+    const int64_t need_eq = st[t].remaining;
+    const T* c = coef + t * N;
+    int64_t out = off[(t * nch + blockIdx.x) * 2];
+    int64_t eq_seen = off[(t * nch + blockIdx.x) * 2 + 1];
+    int64_t* oi = idx + t * k;
+    T* ov = val + t * k;
+    for (int64_t base = c0; base < c1; base += kTopkChunkThreads) {  // uniform loop
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < c1;
+        const K key = in ? topk_key(c[i]) : (K)0;
+        const bool gt = in && key > thr;
+        const bool eq = in && key == thr;
+        uint32_t eq_tot;
+        const uint32_t eq_rank = block_excl_count<kTopkChunkThreads>(eq, wsum, &eq_tot);
+        const bool take = gt || (eq && eq_seen + (int64_t)eq_rank < need_eq);
+        uint32_t take_tot;
+        const uint32_t pos = block_excl_count<kTopkChunkThreads>(take, wsum, &take_tot);
+        if (take) {
+            oi[out + pos] = i;
+            ov[out + pos] = c[i];
+        }
+        eq_seen += eq_tot;
+        out += take_tot;
+    }
+}
+
+// chunked form: few instances, large N
+__host__ __device__ inline bool topk_chunked(int64_t N, int64_t batch) {
+    return batch < 512 && N >= 4 * (int64_t)kTopkChunk;
+}
+// workspace bytes of the chunked form (0 otherwise), in 256-byte sections
+__host__ __device__ inline size_t topk_ws_bytes(int64_t N, int64_t batch) {
+    if (!topk_chunked(N, batch)) return 0;
+    const int64_t nch = (N + kTopkChunk - 1) / kTopkChunk;
+    auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return r((size_t)batch * sizeof(TopkState)) + r((size_t)batch * 256 * 4) + r((size_t)(batch * nch) * 8) +
+           r((size_t)(batch * nch) * 16);
 }
 
 // recon[inst][idx[inst][j]] = val[inst][j] over a zeroed buffer

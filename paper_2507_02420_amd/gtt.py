@@ -40,7 +40,8 @@ W_DTYPE = {torch.float64: torch.float64, torch.float32: torch.float32,
 
 # every symbol declared in include/gtt.h
 EXPORTS = ["gtt_plan", "gtt_plan_mixed", "gtt_workspace_size", "gtt_forward", "gtt_inverse",
-           "gtt_backward", "gtt_filter", "gtt_compress", "gtt_plan_destroy", "gtt_status_string",
+           "gtt_backward", "gtt_filter", "gtt_compress", "gtt_compress_workspace_size", "gtt_plan_destroy",
+           "gtt_status_string",
            "gtt_plan_describe", "gtt_plan_timing", "gtt_plan_timing_read", "gtt_plan_timing_filter", "gtt_set_tuning",
            "gtt_selftest", "gtt_plan_check", "gtt_plan_barrier_limit", "gtt_backward_noalloc"]
 
@@ -90,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.gtt_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.gtt_filter.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
     L.gtt_compress.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    L.gtt_compress_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     L.gtt_plan_destroy.argtypes = [vp]
     L.gtt_status_string.argtypes = [ctypes.c_int]
     L.gtt_status_string.restype = ctypes.c_char_p
@@ -331,8 +333,9 @@ def _compress(self, W: torch.Tensor, x: torch.Tensor, k: int, reconstruct: bool 
     idx = torch.empty(batch, k, dtype=torch.int64, device=x.device)
     val = torch.empty(batch, k, dtype=x.dtype, device=x.device)
     recon = torch.empty_like(x) if reconstruct else None
-    fwd, _, _ = self.workspace_size()
-    need = fwd + x.numel() * x.element_size()
+    nb = ctypes.c_size_t()
+    _check(lib().gtt_compress_workspace_size(self._h, ctypes.byref(nb)), "gtt_compress_workspace_size")
+    need = nb.value
     ws = self._ws(need, x.device)
     _check(lib().gtt_compress(self._h, _ptr(W), _ptr(x), int(k), _ptr(idx), _ptr(val), _ptr(recon), _ptr(ws), need,
                               _stream(x)), "gtt_compress")
