@@ -254,11 +254,21 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
                     : mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize), (int)(16 / esize), false);
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
+        // radices <= 16 run in place on one tile buffer padded every 32
+        // elements (fibre strides that are multiples of 32 elements would
+        // otherwise meet in one bank); a larger radix needs a second buffer
+        // and then no pad
         int64_t wtot = 0;
-        for (int j = 0; j < k; ++j) wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
+        int maxr = 0;
+        for (int j = 0; j < k; ++j) {
+            wtot += (int64_t)rad[s0 + j] * rad[s0 + j];
+            maxr = std::max(maxr, rad[s0 + j]);
+        }
+        const bool inplace = maxr <= kGenericInplaceMax;
+        gr->pad_shift = inplace ? (5 | (31 << 8) | (31 << 16)) : kNoPad;
+        const int64_t phys = lds_tile_elems_host(gr->tileE, gr->pad_shift);
         gr->wtotal = (int)wtot;
-        gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + 2 * gr->tileE) * csize;
-        gr->pad_shift = kNoPad;
+        gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + (inplace ? 1 : 2) * phys) * csize;
     } else {
         const int64_t phys =
             lds16 ? 2 * lds_tile_elems_host((gr->tileE + 1) / 2, pad) : lds_tile_elems_host(gr->tileE, pad);
@@ -336,6 +346,7 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
             for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
                 Group c;
                 fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
+                if (c.kind == kKindGeneric) c.pad_shift = kNoPad;  // (the forward's in-place pad)
                 const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
                 if (over + 3 * tb > cap) break;  // tiles only grow with T
                 // the register-block kernel addresses a block as one padded
@@ -377,6 +388,7 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
         // no backward for this group: keep the forward geometry for the
         // plan's description
         fill_group(out, rad, s0, k, total, Tmax, es, cs, kind, cmin);
+        if (out->kind == kKindGeneric) out->pad_shift = kNoPad;
         out->bwd_ok = false;
         out->bwd_maxb = maxb;
         return;
@@ -421,13 +433,18 @@ gtt_status plan_groups(const std::vector<int>& rad, int64_t batch, gtt_dtype dt,
     }
     const int64_t min_row_bytes = tr > 0 ? tr : 128;
     int64_t N = 1;
-    for (int r : rad) N *= r;
+    int maxrad = 0;
+    for (int r : rad) {
+        N *= r;
+        maxrad = std::max(maxrad, r);
+    }
     const int64_t total = N * batch;
     for (int64_t relax_row = min_row_bytes; relax_row >= (int64_t)es; relax_row /= 2) {
         for (int R = 1; R <= n; ++R) {
             for (int64_t bud : budgets) {
                 int64_t T = bud / (int64_t)cs_fwd;
-                if (!small_b) T /= 2;  // the runtime-radix kernel double-buffers
+                // the runtime-radix kernel double-buffers for radices above 16
+                if (!small_b && maxrad > kGenericInplaceMax) T /= 2;
                 const int64_t cmin = std::max<int64_t>(1, relax_row / (int64_t)es);
                 std::vector<int> ks;
                 // a group's positions must fit three times in LDS for backward

@@ -95,12 +95,67 @@ __device__ __forceinline__ double acc_to(double v, double*) { return v; }
 __device__ __forceinline__ cf acc_to(cd v, cf*) { return cf{(float)v.re, (float)v.im}; }
 __device__ __forceinline__ cd acc_to(cd v, cd*) { return v; }
 
-// dst = (W or W^H along digit j) src, runtime radix b <= MAXB; a thread owns
-// whole fibres: it reads all b values of a fibre into registers before it
-// writes any, so dst may equal src.
+// dst = (W or W^H along digit j) src, radix B compiled in; a thread owns
+// whole fibres: it reads all B values of a fibre into registers before it
+// writes any, so dst may equal src.  LIN: an unpadded tile (linear LDS
+// positions).
+template <typename C, int B, bool LIN>
+__device__ __forceinline__ void digit_apply_b(const C* src, C* dst, const C* Wl, const PassArgs& a, int j,
+                                              uint32_t rows) {
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t F = (rows << a.logC) / (uint32_t)B;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t bj1 = (uint32_t)a.bpow[j + 1];
+    const uint32_t step = bj << a.logC;
+    auto phys = [&](uint32_t x) { return LIN ? x : lds_phys(x, a.pad_shift); };
+    for (uint32_t f = threadIdx.x; f < F; f += kThreads) {
+        const uint32_t c = f & Cm;
+        const uint32_t f1 = f >> a.logC;
+        const uint32_t Q = fdiv(f1, a.divb[j]);
+        const uint32_t glo = f1 - Q * bj;
+        const uint32_t lam0 = ((Q * bj1 + glo) << a.logC) | c;
+        C v[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) v[q] = src[phys(lam0 + (uint32_t)q * step)];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            C acc = cmul(Wl[r * B], v[0]);
+#pragma unroll
+            for (int q = 1; q < B; ++q) acc = cmac(acc, Wl[r * B + q], v[q]);
+            dst[phys(lam0 + (uint32_t)r * step)] = acc;
+        }
+    }
+}
+
+#define GTT_DA_CASE(B)                                                   \
+    case B:                                                              \
+        if constexpr (B <= LIM) digit_apply_b<C, B, LIN>(src, dst, Wl, a, j, rows); \
+        break;
+template <typename C, bool LIN, int LIM>
+__device__ __forceinline__ void digit_apply_sw(const C* src, C* dst, const C* Wl, const PassArgs& a, int b, int j,
+                                               uint32_t rows) {
+    switch (b) {
+        GTT_DA_CASE(2) GTT_DA_CASE(3) GTT_DA_CASE(4) GTT_DA_CASE(5) GTT_DA_CASE(6) GTT_DA_CASE(7)
+        GTT_DA_CASE(8) GTT_DA_CASE(9) GTT_DA_CASE(10) GTT_DA_CASE(11) GTT_DA_CASE(12) GTT_DA_CASE(13)
+        GTT_DA_CASE(14) GTT_DA_CASE(15) GTT_DA_CASE(16)
+        default: break;
+    }
+}
+#undef GTT_DA_CASE
+
+// the same for a runtime radix b <= MAXB: radices up to 8 take the
+// compiled-in form, larger ones a loop over b with run-time bounds (compiled
+// in, their matrices would be held in registers across the fibre loop and
+// spill)
 template <typename C, int MAXB>
 __device__ __forceinline__ void digit_apply(const C* src, C* dst, const C* Wl, const PassArgs& a, int b, int j,
                                             uint32_t rows) {
+    constexpr int LIM = MAXB < 8 ? MAXB : 8;
+    if (b <= LIM) {
+        if (a.pad_shift == kPadNone) digit_apply_sw<C, true, LIM>(src, dst, Wl, a, b, j, rows);
+        else digit_apply_sw<C, false, LIM>(src, dst, Wl, a, b, j, rows);
+        return;
+    }
     const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t F = (rows << a.logC) / (uint32_t)b;
     const uint32_t bj = (uint32_t)a.bpow[j];
@@ -184,6 +239,86 @@ __device__ __forceinline__ void gw_sweep(const C* Ct, const C* Tt, Acc* red, Acc
     __syncthreads();
 }
 
+__device__ __forceinline__ double acc_shfl_down(double v, int d) { return __shfl_down(v, d, 64); }
+__device__ __forceinline__ cd acc_shfl_down(cd v, int d) {
+    return cd{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
+}
+
+// The same sums for b <= 8 (4 b*b <= kThreads), a row of the gradient per
+// lane: a wave's lanes are (sub, r) pairs, r = lane % b, sub = lane / b
+// (64 / b of them), and lane (sub, r) of wave w takes fibres
+// f = w * subs + sub + i * 4 * subs: it reads Ct[r] once and Tt[0..b-1] of
+// each and keeps the b sums of row r in registers.  The sums are folded over
+// sub inside the wave by shuffles (a fixed tree), then the four waves' rows
+// are added in wave order into acc.
+template <typename C, typename Acc, int B, bool LIN>
+__device__ __forceinline__ void gw_rows(const C* Ct, const C* Tt, Acc* red, Acc* acc, const PassArgs& a, int j,
+                                        uint32_t rows) {
+    constexpr int MB = B;
+    constexpr int b = B;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t F = (rows << a.logC) / (uint32_t)b;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t bj1 = (uint32_t)a.bpow[j + 1];
+    const uint32_t step = bj << a.logC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int subs = 64 / b;
+    const int sub = lane / b, r = lane - sub * b;
+    auto phys = [&](uint32_t x) { return LIN ? x : lds_phys(x, a.pad_shift); };
+    Acc s[MB];
+#pragma unroll
+    for (int q = 0; q < MB; ++q) s[q] = acc_zero(Acc{});
+    if (sub < subs) {
+        for (uint32_t f = (uint32_t)(wave * subs + sub); f < F; f += (uint32_t)(4 * subs)) {
+            const uint32_t c = f & Cm;
+            const uint32_t f1 = f >> a.logC;
+            const uint32_t Q = fdiv(f1, a.divb[j]);
+            const uint32_t glo = f1 - Q * bj;
+            const uint32_t lam0 = ((Q * bj1 + glo) << a.logC) | c;
+            const C cr = Ct[phys(lam0 + (uint32_t)r * step)];
+#pragma unroll
+            for (int q = 0; q < MB; ++q) s[q] = acc_mac_conj(s[q], cr, Tt[phys(lam0 + (uint32_t)q * step)]);
+        }
+    }
+    for (int h = 1; h < subs; h <<= 1) {
+        const bool take = (sub & (2 * h - 1)) == 0 && sub + h < subs;
+#pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            const Acc o = acc_shfl_down(s[q], h * b);
+            if (take) s[q] = acc_add(s[q], o);
+        }
+    }
+    const int bb = b * b;
+    if (sub == 0) {
+#pragma unroll
+        for (int q = 0; q < MB; ++q) red[wave * bb + r * b + q] = s[q];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < bb) {
+        Acc tot = acc[t];
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) tot = acc_add(tot, red[w * bb + t]);
+        acc[t] = tot;
+    }
+    __syncthreads();
+}
+
+template <typename C, typename Acc, bool LIN>
+__device__ __forceinline__ void gw_rows_sw(const C* Ct, const C* Tt, Acc* red, Acc* acc, const PassArgs& a, int b,
+                                           int j, uint32_t rows) {
+    switch (b) {
+        case 2: gw_rows<C, Acc, 2, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 3: gw_rows<C, Acc, 3, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 4: gw_rows<C, Acc, 4, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 5: gw_rows<C, Acc, 5, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 6: gw_rows<C, Acc, 6, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 7: gw_rows<C, Acc, 7, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        case 8: gw_rows<C, Acc, 8, LIN>(Ct, Tt, red, acc, a, j, rows); break;
+        default: break;
+    }
+}
+
 __host__ __device__ constexpr size_t bwd_align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 template <typename T, int MAXB>
@@ -238,7 +373,12 @@ __global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
                 digit_apply<C, MAXB>(slot(src), slot(dst), sW + ba.lofs[j], a, b, j, rows);
                 __syncthreads();
             } else if (kind == kOpGw) {
-                gw_sweep<C, Acc>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
+                if (b <= 8 && a.pad_shift == kPadNone)
+                    gw_rows_sw<C, Acc, true>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
+                else if (b <= 8)
+                    gw_rows_sw<C, Acc, false>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
+                else
+                    gw_sweep<C, Acc>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
             } else if (j != 0 || a.out) {
                 // (the cotangent at the input of digit 0 is needed only when
                 // it is stored: out is null for the first digit group when
@@ -384,11 +524,6 @@ __host__ __device__ constexpr int bwd_block_digits(int b) {
     if (std::is_same<C, cf>::value) return b == 2 ? 3 : (b == 3 || b == 4) ? 1 : 0;
     if (std::is_same<C, cd>::value) return b == 2 ? 2 : (b == 3 || b == 4) ? 1 : 0;
     return 0;
-}
-
-__device__ __forceinline__ double acc_shfl_down(double v, int d) { return __shfl_down(v, d, 64); }
-__device__ __forceinline__ cd acc_shfl_down(cd v, int d) {
-    return cd{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
 }
 
 // The B^R positions of block f of a group whose first block digit is j:

@@ -57,6 +57,7 @@ inline unsigned resident_grid(K kernel, int threads, size_t lds, unsigned tiles)
 // kernel families of a digit-group pass
 constexpr int kKindValu = 0;     // radix 2..8, register super-stages on the VALU
 constexpr int kKindGeneric = 1;  // any radix <= 64 and mixed radices, LDS sweeps
+constexpr int kGenericInplaceMax = 16;  // the runtime-radix kernel: radices up to this run in place
 constexpr int kKindMfma = 2;     // radix 16 / 32, bf16 / f16 storage, matrix cores
 constexpr int kKindCMfma = 3;    // complex64, radix 8, FP32 matrix cores
 

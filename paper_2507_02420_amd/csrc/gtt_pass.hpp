@@ -930,9 +930,97 @@ namespace gtt {
 // ---------------------------------------------------------------------------
 // Runtime-radix group pass (any radix up to 64, mixed radices allowed): used
 // for radices without a specialised kernel and for heterogeneous transforms
-// (§2.6, remark on distinct factors).  One digit per LDS sweep, out of place
-// between two LDS buffers; W matrices are staged in LDS.
+// (§2.6, remark on distinct factors).  W matrices are staged in LDS.  A
+// digit of radix <= 16 runs in place on the tile: a thread owns whole
+// fibres, reads the B values of one into registers and writes the B results
+// back (code compiled per radix, W read from LDS by all lanes at one
+// address); the LDS tile takes one pad element every 2^p elements (p = the
+// low pad field, lds_phys).  A larger radix goes out of place, element by
+// element, into a second tile buffer that the planner adds (and then no pad).
 // ---------------------------------------------------------------------------
+template <typename C, int B>
+__device__ __forceinline__ void fibre_digit(C* buf, const C* Wj, const PassArgs& a, int j, uint32_t tileE) {
+    const uint32_t F = tileE / (uint32_t)B;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t pv = (uint32_t)a.bpow[j];
+    const uint32_t step = pv << a.logC;
+    const uint32_t ps = (uint32_t)(a.pad_shift & 31);
+    for (uint32_t f = threadIdx.x; f < F; f += kThreads) {
+        const uint32_t c = f & Cm;
+        const uint32_t f1 = f >> a.logC;
+        const uint32_t Q = fdiv(f1, a.divb[j]);  // f1 / pv
+        const uint32_t lo = f1 - Q * pv;
+        const uint32_t lam0 = ((Q * pv * (uint32_t)B + lo) << a.logC) | c;
+        C v[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const uint32_t lam = lam0 + (uint32_t)q * step;
+            v[q] = buf[lam + (lam >> ps)];
+        }
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            C acc = cmul(Wj[r * B], v[0]);
+#pragma unroll
+            for (int q = 1; q < B; ++q) acc = cmac(acc, Wj[r * B + q], v[q]);
+            const uint32_t lam = lam0 + (uint32_t)r * step;
+            buf[lam + (lam >> ps)] = acc;
+        }
+    }
+}
+
+// the group's digits on a tile in LDS (buf0 holds it on entry); returns the
+// buffer holding the result
+template <typename C>
+__device__ C* generic_digits(C* buf0, C* buf1, const C* Wl, const PassArgs& a, uint32_t rows) {
+    const uint32_t tileE = rows << a.logC;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    C* src = buf0;
+    C* dst = buf1;
+    int woff = 0;
+    for (int j = 0; j < a.k; ++j) {
+        const int bj = a.rad[j];
+        const C* Wj = Wl + woff;
+        switch (bj) {
+            case 2: fibre_digit<C, 2>(src, Wj, a, j, tileE); break;
+            case 3: fibre_digit<C, 3>(src, Wj, a, j, tileE); break;
+            case 4: fibre_digit<C, 4>(src, Wj, a, j, tileE); break;
+            case 5: fibre_digit<C, 5>(src, Wj, a, j, tileE); break;
+            case 6: fibre_digit<C, 6>(src, Wj, a, j, tileE); break;
+            case 7: fibre_digit<C, 7>(src, Wj, a, j, tileE); break;
+            case 8: fibre_digit<C, 8>(src, Wj, a, j, tileE); break;
+            case 9: fibre_digit<C, 9>(src, Wj, a, j, tileE); break;
+            case 10: fibre_digit<C, 10>(src, Wj, a, j, tileE); break;
+            case 11: fibre_digit<C, 11>(src, Wj, a, j, tileE); break;
+            case 12: fibre_digit<C, 12>(src, Wj, a, j, tileE); break;
+            case 13: fibre_digit<C, 13>(src, Wj, a, j, tileE); break;
+            case 14: fibre_digit<C, 14>(src, Wj, a, j, tileE); break;
+            case 15: fibre_digit<C, 15>(src, Wj, a, j, tileE); break;
+            case 16: fibre_digit<C, 16>(src, Wj, a, j, tileE); break;
+            default: {
+                const uint32_t b = (uint32_t)bj;
+                const uint32_t pv = (uint32_t)a.bpow[j];
+                for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
+                    const uint32_t c = i & Cm;
+                    const uint32_t r = i >> a.logC;
+                    const uint32_t hi = fdiv(r, a.divb[j]);              // r / pv
+                    const uint32_t d = hi - fdiv(hi, a.divrad[j]) * b;  // digit j of r
+                    const uint32_t r0 = r - d * pv;
+                    C acc = czero<C>();
+                    for (uint32_t q = 0; q < b; ++q)
+                        acc = cmac(acc, Wj[d * b + q], src[((r0 + q * pv) << a.logC) | c]);
+                    dst[i] = acc;
+                }
+                C* tmp = src;
+                src = dst;
+                dst = tmp;
+            }
+        }
+        __syncthreads();
+        woff += bj * bj;
+    }
+    return src;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) {
     using C = typename Tr<T>::C;
@@ -942,7 +1030,7 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) 
     const uint32_t tileE = rows << a.logC;
     const uint32_t wpad = ((uint32_t)a.wtotal + 15u) & ~15u;
     C* buf0 = Wl + wpad;
-    C* buf1 = buf0 + tileE;
+    C* buf1 = buf0 + lds_tile_elems(tileE, a.pad_shift);  // only for radices above 16
     {
         const C* __restrict__ Wg = static_cast<const C*>(a.W);
         for (int j = 0, done = 0; j < a.k; ++j) {
@@ -955,33 +1043,12 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) 
             done += bj * bj;
         }
     }
-    const uint32_t Cm = (1u << a.logC) - 1u;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        tile_load<T, C>(buf0, a, static_cast<const T*>(a.in), t, rows);
+        // (element-wise tiles take the scalar address walk)
+        tile_load<T, C, kThreads, true>(buf0, a, static_cast<const T*>(a.in), t, rows);
         __syncthreads();
-        C* src = buf0;
-        C* dst = buf1;
-        int woff = 0;
-        for (int j = 0; j < a.k; ++j) {
-            const uint32_t bj = (uint32_t)a.rad[j];
-            const uint32_t pv = (uint32_t)a.bpow[j];
-            const C* Wj = Wl + woff;
-            for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
-                const uint32_t c = i & Cm;
-                const uint32_t r = i >> a.logC;
-                const uint32_t hi = fdiv(r, a.divb[j]);      // r / pv
-                const uint32_t d = hi - fdiv(hi, a.divrad[j]) * bj;  // digit j of r
-                const uint32_t r0 = r - d * pv;
-                C acc = czero<C>();
-                for (uint32_t q = 0; q < bj; ++q)
-                    acc = cmac(acc, Wj[d * bj + q], src[((r0 + q * pv) << a.logC) | c]);
-                dst[i] = acc;
-            }
-            __syncthreads();
-            C* tmp = src; src = dst; dst = tmp;
-            woff += (int)(bj * bj);
-        }
-        tile_store<T, C>(src, a, static_cast<T*>(a.out), t, rows);
+        const C* res = generic_digits<C>(buf0, buf1, Wl, a, rows);
+        tile_store<T, C, false, kThreads, true>(res, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
 }

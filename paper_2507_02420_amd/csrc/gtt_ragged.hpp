@@ -150,7 +150,7 @@ __device__ __forceinline__ void ragged_tile_generic(unsigned char* smem, const P
     const uint32_t tileE = rows << a.logC;
     const uint32_t wpad = ((uint32_t)a.wtotal + 15u) & ~15u;
     C* buf0 = Wl + wpad;
-    C* buf1 = buf0 + tileE;
+    C* buf1 = buf0 + lds_tile_elems(tileE, a.pad_shift);  // only for radices above 16
     for (int j = 0, done = 0; j < a.k; ++j) {
         const int bj = a.rad[j];
         for (int e = threadIdx.x; e < bj * bj; e += kThreads) {
@@ -161,31 +161,8 @@ __device__ __forceinline__ void ragged_tile_generic(unsigned char* smem, const P
     }
     tile_load<T, C>(buf0, a, in, t, rows);
     __syncthreads();
-    const uint32_t Cm = (1u << a.logC) - 1u;
-    C* src = buf0;
-    C* dst = buf1;
-    int woff = 0;
-    for (int j = 0; j < a.k; ++j) {
-        const uint32_t bj = (uint32_t)a.rad[j];
-        const uint32_t pv = (uint32_t)a.bpow[j];
-        const C* Wj = Wl + woff;
-        for (uint32_t i = threadIdx.x; i < tileE; i += kThreads) {
-            const uint32_t c = i & Cm;
-            const uint32_t r = i >> a.logC;
-            const uint32_t hi = fdiv(r, a.divb[j]);
-            const uint32_t d = hi - fdiv(hi, a.divrad[j]) * bj;
-            const uint32_t r0 = r - d * pv;
-            C acc = czero<C>();
-            for (uint32_t q = 0; q < bj; ++q) acc = cmac(acc, Wj[d * bj + q], src[((r0 + q * pv) << a.logC) | c]);
-            dst[i] = acc;
-        }
-        __syncthreads();
-        C* tmp = src;
-        src = dst;
-        dst = tmp;
-        woff += (int)(bj * bj);
-    }
-    tile_store<T, C>(src, a, out, t, rows);
+    const C* res = generic_digits<C>(buf0, buf1, Wl, a, rows);
+    tile_store<T, C>(res, a, out, t, rows);
     __syncthreads();
 }
 

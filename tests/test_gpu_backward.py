@@ -246,7 +246,8 @@ def test_full_size_float32_radix3_backward():
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.float32, torch.float64, torch.complex128], ids=str)
 @pytest.mark.parametrize("radices,batch", [([2, 3, 4, 5], 3), ([3, 8, 2, 7, 4], 2), ([16, 2, 9], 2),
-                                           ([32, 4], 3), ([5, 5, 5, 5, 5, 5, 5], 2), ([2] * 14 + [3], 1)])
+                                           ([32, 4], 3), ([5, 5, 5, 5, 5, 5, 5], 2), ([2] * 14 + [3], 1),
+                                           ([8, 3, 4, 5, 2, 7], 8)])
 def test_mixed_radix_backward(radices, batch, dtype):
     # distinct factors W_0 kron ... kron W_{m-1}: gx and every factor's
     # gradient against the oracle (gW comes back in the W table's layout)

@@ -226,6 +226,36 @@ def test_mixed_radix_matches_kron(dtype):
     assert rel_err(host64(xi), x64) < 3 * TOL[dtype]
 
 
+# the runtime-radix kernel over many tiles and two digit groups (one strided,
+# with a partial last column block): radices up to 16 in place, a radix above
+# 16 out of place in the same group, contiguous tiles of several instances
+@pytest.mark.parametrize("radices,batch,dtype", [
+    ([8, 3, 4, 5, 2, 7], 64, torch.complex64), ([17, 3, 20, 2, 5], 5, torch.complex64),
+    ([16, 9, 13, 6], 4, torch.float32), ([12, 11, 10, 15, 14], 2, torch.float64),
+    ([7, 2, 5, 3, 8, 4], 10, torch.complex128), ([3, 5, 7, 9, 11], 6, torch.bfloat16)], ids=str)
+def test_mixed_radix_tiles(radices, batch, dtype):
+    Ns = int(np.prod(radices))
+    say(f"mixed radix tiles {radices} batch={batch} dtype={dtype}")
+    cplx = dtype in COMPLEX
+    from paper_2507_02420_amd.inputs import haar_unitary
+    Ws = [haar_unitary(r, 70 + i, complex_=cplx) for i, r in enumerate(radices)]
+    x = gaussian((batch, Ns), seed=80 + len(radices), complex_=cplx)
+    wdt = G.W_DTYPE[dtype]
+    Wt = torch.cat([torch.from_numpy(w).to(wdt).reshape(-1) for w in Ws]).cuda()
+    xt = torch.from_numpy(x).to(dtype).cuda()
+    plan = G.Plan.mixed(radices, batch, dtype)
+    groups = plan.describe()["groups"]
+    assert len(groups) >= 2 and any(g["S"] > 1 for g in groups), groups
+    assert sum(g["tiles"] for g in groups) > 2 * len(groups), groups
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    Ws64 = [torch.from_numpy(w).to(wdt).to(torch.complex128).numpy() for w in Ws]
+    x64 = host64(xt)
+    assert rel_err(host64(y), O.staged_mixed(Ws64, x64)) < TOL[dtype], (radices, dtype, groups)
+    assert rel_err(host64(xi), x64) < 3 * TOL[dtype], (radices, dtype)
+
+
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=str)
 @pytest.mark.parametrize("b,n,batch", [(16, 1, 5), (16, 2, 3), (16, 3, 2), (16, 5, 1), (32, 1, 7), (32, 2, 3),
                                        (32, 3, 1), (32, 4, 1)])
