@@ -321,8 +321,16 @@ __device__ __forceinline__ void gw_rows_sw(const C* Ct, const C* Tt, Acc* red, A
 
 __host__ __device__ constexpr size_t bwd_align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-template <typename T, int MAXB>
-__global__ __launch_bounds__(kThreads) void gtt_bwd_kernel(BwdArgs ba) {
+// W4: the form compiled for four waves per SIMD (at most 128 VGPRs); the
+// launch takes it where it fits more work-groups than the unconstrained one
+template <bool W4>
+struct BwdMinWaves {
+    static constexpr int value = W4 ? 4 : 1;
+};
+
+template <typename T, int MAXB, bool W4 = false>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(BwdMinWaves<W4>::value))) void gtt_bwd_kernel(
+    BwdArgs ba) {
     using C = typename Tr<T>::C;
     using Acc = typename AccOf<C>::type;
     const PassArgs& a = ba.p;
@@ -893,6 +901,19 @@ inline int bwd_resident_waves(K kernel, int nt, size_t lds) {
     return blocks * nt / 64;
 }
 
+// the runtime-radix backward: the four-wave form (32-bit compute lanes, radix
+// <= 16; where it does not spill) when more of its work-groups are resident at
+// this LDS size, else the unconstrained one
+template <typename T, int MAXB>
+inline hipError_t launch_bwd_general(const BwdArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    if constexpr (sizeof(typename Tr<T>::C) <= 8) {
+        if (bwd_resident_waves(gtt_bwd_kernel<T, MAXB, true>, kThreads, lds) >
+            bwd_resident_waves(gtt_bwd_kernel<T, MAXB, false>, kThreads, lds))
+            return bwd_launch_one(gtt_bwd_kernel<T, MAXB, true>, a, grid, kThreads, lds, s);
+    }
+    return bwd_launch_one(gtt_bwd_kernel<T, MAXB, false>, a, grid, kThreads, lds, s);
+}
+
 // The register-block kernels of radix B at 256, 512 and 1024 threads (1024
 // only where the per-wave sums fit the reduction area)
 template <typename T, int B, int RD>
@@ -942,8 +963,8 @@ hipError_t launch_bwd_t(const BwdArgs& a, int maxb, int radix, unsigned grid, in
         }
         return hipErrorInvalidValue;
     }
-    if (maxb <= 8) return bwd_launch_one(gtt_bwd_kernel<T, 8>, a, grid, kThreads, lds, s);
-    if (maxb <= 16) return bwd_launch_one(gtt_bwd_kernel<T, 16>, a, grid, kThreads, lds, s);
+    if (maxb <= 8) return launch_bwd_general<T, 8>(a, grid, lds, s);
+    if (maxb <= 16) return launch_bwd_general<T, 16>(a, grid, lds, s);
     if (maxb <= 32) return bwd_launch_one(gtt_bwd_kernel<T, 32>, a, grid, kThreads, lds, s);
     return hipErrorInvalidValue;
 }
