@@ -65,9 +65,18 @@ inline hipError_t launch_mfma(const PassArgs& a, unsigned grid, size_t lds, hipS
     return hipGetLastError();
 }
 
+// runtime-radix pass: the form with the scalar address walk for element-wise
+// tiles
+template <typename T>
+inline hipError_t launch_generic(const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
+    if (a.mode == kContigScalar || a.mode == kRowScalar)
+        return launch_tiles(gtt_pass_generic_kernel<T, true>, a, grid, lds, s);
+    return launch_tiles(gtt_pass_generic_kernel<T, false>, a, grid, lds, s);
+}
+
 template <typename T>
 hipError_t launch_pass_t(int b, int kind, const PassArgs& a, unsigned grid, size_t lds, hipStream_t s) {
-    if (kind == kKindGeneric) return launch_tiles(gtt_pass_generic_kernel<T>, a, grid, lds, s);
+    if (kind == kKindGeneric) return launch_generic<T>(a, grid, lds, s);
     if (kind == kKindMfma) {
         if constexpr (has_mfma_pass<T>()) {
             if (b == 16) return launch_mfma<T, 16>(a, grid, lds, s);
@@ -101,7 +110,7 @@ hipError_t launch_pass_t(int b, int kind, const PassArgs& a, unsigned grid, size
         case 8: if constexpr (mx >= 8) return launch_valu<T, mx >= 8 ? 8 : 2>(a, grid, lds, s); break;
         default: break;
     }
-    return launch_tiles(gtt_pass_generic_kernel<T>, a, grid, lds, s);
+    return launch_generic<T>(a, grid, lds, s);
 }
 
 // ---- ragged batches --------------------------------------------------------

@@ -971,7 +971,7 @@ __device__ __forceinline__ void fibre_digit(C* buf, const C* Wj, const PassArgs&
 // the group's digits on a tile in LDS (buf0 holds it on entry); returns the
 // buffer holding the result
 template <typename C>
-__device__ C* generic_digits(C* buf0, C* buf1, const C* Wl, const PassArgs& a, uint32_t rows) {
+__device__ __forceinline__ C* generic_digits(C* buf0, C* buf1, const C* Wl, const PassArgs& a, uint32_t rows) {
     const uint32_t tileE = rows << a.logC;
     const uint32_t Cm = (1u << a.logC) - 1u;
     C* src = buf0;
@@ -1021,7 +1021,9 @@ __device__ C* generic_digits(C* buf0, C* buf1, const C* Wl, const PassArgs& a, u
     return src;
 }
 
-template <typename T>
+// SW: element-wise tiles take the scalar address walk (costs registers: the
+// launch uses this form only for groups whose tiles are element-wise)
+template <typename T, bool SW>
 __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) {
     using C = typename Tr<T>::C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1044,11 +1046,10 @@ __global__ __launch_bounds__(kThreads) void gtt_pass_generic_kernel(PassArgs a) 
         }
     }
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        // (element-wise tiles take the scalar address walk)
-        tile_load<T, C, kThreads, true>(buf0, a, static_cast<const T*>(a.in), t, rows);
+        tile_load<T, C, kThreads, SW>(buf0, a, static_cast<const T*>(a.in), t, rows);
         __syncthreads();
         const C* res = generic_digits<C>(buf0, buf1, Wl, a, rows);
-        tile_store<T, C, false, kThreads, true>(res, a, static_cast<T*>(a.out), t, rows);
+        tile_store<T, C, false, kThreads, SW>(res, a, static_cast<T*>(a.out), t, rows);
         __syncthreads();
     }
 }
