@@ -254,10 +254,10 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
                     : mfma_pad(rad[s0], k, gr->logC, gr->tileE, ilog2_floor(16 / esize), (int)(16 / esize), false);
     gr->pad_shift = pad;
     if (gr->kind == kKindGeneric) {
-        // radices <= 16 run in place on one tile buffer padded every 32
-        // elements (fibre strides that are multiples of 32 elements would
-        // otherwise meet in one bank); a larger radix needs a second buffer
-        // and then no pad
+        // radices <= 16 run in place on one tile buffer; a larger radix needs
+        // a second buffer.  Unpadded (the kernel is bound by its VALU work,
+        // and the pad's address arithmetic cost more than the bank conflicts
+        // it removed)
         int64_t wtot = 0;
         int maxr = 0;
         for (int j = 0; j < k; ++j) {
@@ -265,7 +265,7 @@ static void fill_group(Group* gr, const std::vector<int>& rad, int s0, int k, in
             maxr = std::max(maxr, rad[s0 + j]);
         }
         const bool inplace = maxr <= kGenericInplaceMax;
-        gr->pad_shift = inplace ? (5 | (31 << 8) | (31 << 16)) : kNoPad;
+        gr->pad_shift = kNoPad;
         const int64_t phys = lds_tile_elems_host(gr->tileE, gr->pad_shift);
         gr->wtotal = (int)wtot;
         gr->lds_bytes = (size_t)(((wtot + 15) & ~15LL) + (inplace ? 1 : 2) * phys) * csize;
@@ -346,7 +346,6 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
             for (int64_t T = G; T <= Tmax && radix_ok; T *= 2) {
                 Group c;
                 fill_group(&c, rad, s0, k, total, T, es, cs, kind, cmin);
-                if (c.kind == kKindGeneric) c.pad_shift = kNoPad;  // (the forward's in-place pad)
                 const size_t tb = (size_t)lds_tile_elems_host(c.tileE, c.pad_shift) * cs;
                 if (over + 3 * tb > cap) break;  // tiles only grow with T
                 // the register-block kernel addresses a block as one padded
@@ -388,7 +387,6 @@ static void plan_bwd_general(Group* out, const std::vector<int>& rad, int s0, in
         // no backward for this group: keep the forward geometry for the
         // plan's description
         fill_group(out, rad, s0, k, total, Tmax, es, cs, kind, cmin);
-        if (out->kind == kKindGeneric) out->pad_shift = kNoPad;
         out->bwd_ok = false;
         out->bwd_maxb = maxb;
         return;

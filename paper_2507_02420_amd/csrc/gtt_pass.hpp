@@ -930,13 +930,12 @@ namespace gtt {
 // ---------------------------------------------------------------------------
 // Runtime-radix group pass (any radix up to 64, mixed radices allowed): used
 // for radices without a specialised kernel and for heterogeneous transforms
-// (§2.6, remark on distinct factors).  W matrices are staged in LDS.  A
-// digit of radix <= 16 runs in place on the tile: a thread owns whole
-// fibres, reads the B values of one into registers and writes the B results
-// back (code compiled per radix, W read from LDS by all lanes at one
-// address); the LDS tile takes one pad element every 2^p elements (p = the
-// low pad field, lds_phys).  A larger radix goes out of place, element by
-// element, into a second tile buffer that the planner adds (and then no pad).
+// (§2.6, remark on distinct factors).  W matrices are staged in LDS; tiles
+// are unpadded (positions linear).  A digit of radix <= 16 runs in place on
+// the tile: a thread owns whole fibres, reads the B values of one into
+// registers and writes the B results back (code compiled per radix, W read
+// from LDS by all lanes at one address).  A larger radix goes out of place,
+// element by element, into a second tile buffer that the planner adds.
 // ---------------------------------------------------------------------------
 template <typename C, int B>
 __device__ __forceinline__ void fibre_digit(C* buf, const C* Wj, const PassArgs& a, int j, uint32_t tileE) {
@@ -944,26 +943,22 @@ __device__ __forceinline__ void fibre_digit(C* buf, const C* Wj, const PassArgs&
     const uint32_t Cm = (1u << a.logC) - 1u;
     const uint32_t pv = (uint32_t)a.bpow[j];
     const uint32_t step = pv << a.logC;
-    const uint32_t ps = (uint32_t)(a.pad_shift & 31);
     for (uint32_t f = threadIdx.x; f < F; f += kThreads) {
         const uint32_t c = f & Cm;
         const uint32_t f1 = f >> a.logC;
         const uint32_t Q = fdiv(f1, a.divb[j]);  // f1 / pv
         const uint32_t lo = f1 - Q * pv;
         const uint32_t lam0 = ((Q * pv * (uint32_t)B + lo) << a.logC) | c;
+        C* fb = buf + lam0;
         C v[B];
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            const uint32_t lam = lam0 + (uint32_t)q * step;
-            v[q] = buf[lam + (lam >> ps)];
-        }
+        for (int q = 0; q < B; ++q) v[q] = fb[q * step];
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             C acc = cmul(Wj[r * B], v[0]);
 #pragma unroll
             for (int q = 1; q < B; ++q) acc = cmac(acc, Wj[r * B + q], v[q]);
-            const uint32_t lam = lam0 + (uint32_t)r * step;
-            buf[lam + (lam >> ps)] = acc;
+            fb[r * step] = acc;
         }
     }
 }
