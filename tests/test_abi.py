@@ -494,3 +494,28 @@ def test_plan_destruction_is_deferred_during_graph_capture(monkeypatch):
     q = G.Plan(2, 4, 1, torch.float32)  # a new plan frees the deferred ones first
     assert not G._DEFERRED
     del q
+
+
+@pytest.mark.parametrize("radices,batch,dtype", [
+    ([8, 3, 4, 5, 2, 7], 4096, torch.complex64), ([17, 3, 20, 2, 5], 5, torch.complex64),
+    ([16, 9, 13, 6], 4, torch.float32), ([7, 2, 5, 3, 8, 4], 10, torch.complex128),
+    ([33, 40], 3, torch.float64), ([11, 11, 11, 11], 256, torch.bfloat16)], ids=str)
+def test_runtime_radix_lds_contract(radices, batch, dtype):
+    # the runtime-radix pass stages every digit's W (rounded up to 16 entries)
+    # and works in place on one unpadded tile when every radix of the group
+    # is at most 16; a larger radix runs out of place into a second buffer.
+    # The kernel places that buffer one element past the tile, so the plan's
+    # LDS is (W + (tile + 1) per buffer) compute elements.
+    plan = G.Plan.mixed(radices, batch, dtype)
+    rad = radices[::-1]  # digit d is factor m-1-d
+    csize = {torch.complex64: 8, torch.complex128: 16, torch.float32: 4, torch.float64: 8, torch.bfloat16: 4}[dtype]
+    no_pad = 31 | (31 << 8) | (31 << 16)
+    groups = plan.describe()["groups"]
+    assert sum(g["k"] for g in groups) == len(radices)
+    for g in groups:
+        assert g["kind"] == "generic" and g["pad_shift"] == no_pad, g
+        digits = rad[g["s0"]:g["s0"] + g["k"]]
+        w = sum(r * r for r in digits)
+        nbuf = 1 if max(digits) <= 16 else 2
+        assert g["lds_bytes"] == (((w + 15) // 16) * 16 + nbuf * (g["tile_elems"] + 1)) * csize, (g, digits)
+        assert g["lds_bytes"] <= 160 * 1024
