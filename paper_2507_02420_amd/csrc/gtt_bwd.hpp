@@ -304,6 +304,61 @@ __device__ __forceinline__ void gw_rows(const C* Ct, const C* Tt, Acc* red, Acc*
     __syncthreads();
 }
 
+// The row-wise sums for a radix b in 9..16 given at run time, one body for
+// all of them (compiled per radix, several bodies in one kernel pushed it
+// into scratch): columns q0 .. q0 + qn - 1 (qn <= 8) of each lane's row, the
+// waves' rows added into acc one after another in wave order.  The caller
+// covers a row in two calls (two passes over the fibres: columns 0..7 and
+// 8..b-1, measured faster than an even split).
+template <typename C, typename Acc, bool LIN>
+__device__ __forceinline__ void gw_rows_rt(const C* Ct, const C* Tt, Acc* acc, const PassArgs& a, int b, int q0,
+                                           int qn, int j, uint32_t rows) {
+    constexpr int MB = 8;
+    const uint32_t Cm = (1u << a.logC) - 1u;
+    const uint32_t F = (rows << a.logC) / (uint32_t)b;
+    const uint32_t bj = (uint32_t)a.bpow[j];
+    const uint32_t bj1 = (uint32_t)a.bpow[j + 1];
+    const uint32_t step = bj << a.logC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int subs = 64 / b;
+    const int sub = lane / b, r = lane - sub * b;
+    auto phys = [&](uint32_t x) { return LIN ? x : lds_phys(x, a.pad_shift); };
+    Acc s[MB];
+#pragma unroll
+    for (int q = 0; q < MB; ++q) s[q] = acc_zero(Acc{});
+    if (sub < subs) {
+        for (uint32_t f = (uint32_t)(wave * subs + sub); f < F; f += (uint32_t)(4 * subs)) {
+            const uint32_t c = f & Cm;
+            const uint32_t f1 = f >> a.logC;
+            const uint32_t Q = fdiv(f1, a.divb[j]);
+            const uint32_t glo = f1 - Q * bj;
+            const uint32_t lam0 = ((Q * bj1 + glo) << a.logC) | c;
+            const C cr = Ct[phys(lam0 + (uint32_t)r * step)];
+#pragma unroll
+            for (int q = 0; q < MB; ++q)
+                if (q < qn) s[q] = acc_mac_conj(s[q], cr, Tt[phys(lam0 + (uint32_t)(q0 + q) * step)]);
+        }
+    }
+    for (int h = 1; h < subs; h <<= 1) {
+        const bool take = (sub & (2 * h - 1)) == 0 && sub + h < subs;
+#pragma unroll
+        for (int q = 0; q < MB; ++q) {
+            if (q < qn) {
+                const Acc o = acc_shfl_down(s[q], h * b);
+                if (take) s[q] = acc_add(s[q], o);
+            }
+        }
+    }
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (wave == w && sub == 0) {
+#pragma unroll
+            for (int q = 0; q < MB; ++q)
+                if (q < qn) acc[r * b + q0 + q] = acc_add(acc[r * b + q0 + q], s[q]);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename C, typename Acc, bool LIN>
 __device__ __forceinline__ void gw_rows_sw(const C* Ct, const C* Tt, Acc* red, Acc* acc, const PassArgs& a, int b,
                                            int j, uint32_t rows) {
@@ -368,6 +423,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(BwdMin
     }
     __syncthreads();
     C* Ct = slot(1);
+    // radices from which the run-time row sums beat the pair sweep (complex
+    // data: measured slower at 9 and 11, faster at 16)
+    constexpr int kRowsRtMin = (std::is_same<C, cf>::value || std::is_same<C, cd>::value) ? 12 : 9;
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         // run-time radices: element-wise tiles take the scalar address walk
         tile_load<T, C, kThreads, true>(slot(0), a, static_cast<const T*>(a.in), t, rows);
@@ -385,7 +443,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(BwdMin
                     gw_rows_sw<C, Acc, true>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
                 else if (b <= 8)
                     gw_rows_sw<C, Acc, false>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
-                else
+                else if (MAXB > 8 && b <= 16 && b >= kRowsRtMin && a.pad_shift == kPadNone) {
+                    if constexpr (MAXB > 8) {
+                        // two passes over the fibres: columns 0..7, then 8..b-1
+                        gw_rows_rt<C, Acc, true>(Ct, slot(src), acc + ba.lofs[j], a, b, 0, 8, j, rows);
+                        gw_rows_rt<C, Acc, true>(Ct, slot(src), acc + ba.lofs[j], a, b, 8, b - 8, j, rows);
+                    }
+                } else
                     gw_sweep<C, Acc>(Ct, slot(src), red, acc + ba.lofs[j], a, b, j, rows);
             } else if (j != 0 || a.out) {
                 // (the cotangent at the input of digit 0 is needed only when
