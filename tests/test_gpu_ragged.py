@@ -55,6 +55,28 @@ SMALL = [(2, 11), (4, 3), (16, 2), (32, 2), (3, 4), (2, 0), (8, 3), (16, 3), (4,
 ODD = [(7, 5), (6, 6), (3, 10), (5, 7), (3, 9), (2, 12), (7, 4)]
 
 
+# radices without a specialised kernel: in place up to 16, out of place
+# above (17, 20, 21), beside small ones; two digit groups where an
+# instance exceeds one tile; both launch modes
+GENERIC = [(17, 3), (9, 4), (20, 3), (12, 3), (2, 5), (21, 1), (11, 3)]
+
+
+@pytest.mark.parametrize("mode", list(MODES), ids=str)
+@pytest.mark.parametrize("dtype", [torch.float32, torch.complex64], ids=str)
+def test_ragged_runtime_radix_items(mode, dtype):
+    say(f"ragged runtime radices {mode} {dtype}")
+    xt, Wt, W64, widx, offs = _ragged_inputs(GENERIC, dtype, seed=950)
+    plan = G.Plan([b for b, _ in GENERIC], [n for _, n in GENERIC], 1, dtype, flags=MODES[mode])
+    y = plan.forward(Wt, xt)
+    xi = plan.inverse(Wt, y)
+    torch.cuda.synchronize()
+    x64, y64, xi64 = host64(xt), host64(y), host64(xi)
+    for t, ((b, n), o) in enumerate(zip(GENERIC, offs)):
+        N = b ** n
+        assert rel_err(y64[o:o + N], O.staged(W64[widx[t]], x64[o:o + N], n)) < TOL[dtype], (t, b, n)
+        assert rel_err(xi64[o:o + N], O.adjoint(W64[widx[t]], y64[o:o + N], n)) < TOL[dtype], (t, b, n)
+
+
 @pytest.mark.parametrize("mode", list(MODES), ids=str)
 @pytest.mark.parametrize("dtype", [torch.float32, torch.complex64, torch.float64], ids=str)
 def test_ragged_odd_radix_strided_groups(mode, dtype):
