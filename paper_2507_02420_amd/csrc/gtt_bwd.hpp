@@ -24,6 +24,10 @@
 // All sums run in a fixed order (deterministic).
 #pragma once
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "gtt_args.hpp"
 #include "gtt_mfma.hpp"
 #include "gtt_pass.hpp"
@@ -951,18 +955,31 @@ inline hipError_t bwd_launch_one(K kernel, const BwdArgs& a, unsigned grid, unsi
 }
 
 // Resident waves per compute unit of a kernel at NT threads and `lds` bytes
-// of LDS; 0 when it cannot run or spills to scratch.
+// of LDS; 0 when it cannot run or spills to scratch.  Asked once per
+// (kernel, NT, lds): the launches take it on every call.
 template <typename K>
 inline int bwd_resident_waves(K kernel, int nt, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, int, size_t>, int> cache;
+    const void* fp = reinterpret_cast<const void*>(kernel);
+    const auto key = std::make_tuple(fp, nt, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int waves = 0;
     hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
-    if (fa.localSizeBytes > 0 || fa.maxThreadsPerBlock < nt) return 0;
-    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return 0;
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, nt, lds) != hipSuccess) return 0;
-    return blocks * nt / 64;
+    if (hipFuncGetAttributes(&fa, fp) == hipSuccess && fa.localSizeBytes == 0 && fa.maxThreadsPerBlock >= nt &&
+        (lds <= 65536 ||
+         hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)) {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, nt, lds) == hipSuccess)
+            waves = blocks * nt / 64;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = waves;
+    return waves;
 }
 
 // the runtime-radix backward: the four-wave form (32-bit compute lanes, radix
