@@ -187,26 +187,45 @@ __global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_hist_kernel(const 
     if (h) atomicAdd(&ghist[t * 256 + threadIdx.x], h);
 }
 
+// The digit of the k-th largest key: the largest digit value d whose count
+// of keys with digit >= d reaches the keys still to be taken.  Thread i
+// holds digit 255 - i, so an inclusive scan over the threads gives every
+// digit's count from the top (P) and the count strictly above it (P - h);
+// the one thread where P first reaches `remaining` writes the state.
 template <typename K>
 __global__ __launch_bounds__(256) void gtt_topk_select_kernel(TopkState* st, uint32_t* ghist, int shift) {
     const int64_t t = blockIdx.x;
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = ghist[t * 256 + threadIdx.x];
-    ghist[t * 256 + threadIdx.x] = 0u;  // clean for the next digit
+    const int i = threadIdx.x;
+    __shared__ uint64_t sc[2][256];
+    const TopkState s0 = st[t];  // read by every thread before any write
+    const uint32_t hv = ghist[t * 256 + (255 - i)];
+    ghist[t * 256 + (255 - i)] = 0u;  // clean for the next digit
+    sc[0][i] = hv;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t remaining = st[t].remaining;
-        int64_t cum = 0;
-        int sel = 0;
-        for (int d = 255; d >= 0; --d) {
-            if (cum + (int64_t)h[d] >= remaining) {
-                sel = d;
-                break;
-            }
-            cum += h[d];
-        }
-        st[t].prefix = (uint64_t)((K)st[t].prefix | ((K)sel << shift));
-        st[t].pmask = (uint64_t)((K)st[t].pmask | ((K)255 << shift));
+    int cur = 0;
+    for (int off = 1; off < 256; off <<= 1) {
+        uint64_t v = sc[cur][i];
+        if (i >= off) v += sc[cur][i - off];
+        sc[cur ^ 1][i] = v;
+        cur ^= 1;
+        __syncthreads();
+    }
+    const int64_t P = (int64_t)sc[cur][i], above = P - (int64_t)hv;
+    const int64_t remaining = s0.remaining;
+    int sel = -1;
+    int64_t cum = 0;
+    if (P >= remaining && (i == 0 || above < remaining)) {
+        sel = 255 - i;
+        cum = above;
+    } else if (i == 255 && P < remaining) {
+        // fewer keys than still to be taken (cannot happen for k <= N):
+        // take digit 0 and everything above it
+        sel = 0;
+        cum = P;
+    }
+    if (sel >= 0) {
+        st[t].prefix = (uint64_t)((K)s0.prefix | ((K)sel << shift));
+        st[t].pmask = (uint64_t)((K)s0.pmask | ((K)255 << shift));
         st[t].remaining = remaining - cum;
     }
 }
