@@ -66,6 +66,45 @@ __device__ __forceinline__ uint32_t block_excl_count(bool flag, uint32_t* wsum, 
     return before + below;
 }
 
+// The digit of the k-th largest key: the largest digit value d whose count
+// of keys with digit >= d reaches the keys still to be taken.  Thread
+// i < 256 of the work-group holds the count hv of digit 255 - i, so an
+// inclusive scan over those threads gives every digit's count from the top
+// (P) and the count strictly above it (P - hv); the one thread where P
+// first reaches `remaining` returns true with the digit and the count above
+// it.  Fewer keys than still wanted (not possible for k <= N) take digit 0
+// and everything above it.  Every thread of the work-group calls it (it
+// holds work-group barriers); sc: 2 x 256 words of LDS.
+__device__ __forceinline__ bool topk_digit_choice(uint64_t hv, int64_t remaining, uint64_t (*sc)[256], int* sel,
+                                                  int64_t* cum) {
+    const int i = threadIdx.x;
+    if (i < 256) sc[0][i] = hv;
+    __syncthreads();
+    int cur = 0;
+    for (int o = 1; o < 256; o <<= 1) {
+        if (i < 256) {
+            uint64_t v = sc[cur][i];
+            if (i >= o) v += sc[cur][i - o];
+            sc[cur ^ 1][i] = v;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (i >= 256) return false;
+    const int64_t P = (int64_t)sc[cur][i], above = P - (int64_t)hv;
+    if (P >= remaining && (i == 0 || above < remaining)) {
+        *sel = 255 - i;
+        *cum = above;
+        return true;
+    }
+    if (i == 255 && P < remaining) {
+        *sel = 0;
+        *cum = P;
+        return true;
+    }
+    return false;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTopkThreads) void gtt_topk_kernel(const T* __restrict__ coef, int64_t N, int64_t k,
                                                                  int64_t* __restrict__ idx, T* __restrict__ val) {
@@ -73,6 +112,7 @@ __global__ __launch_bounds__(kTopkThreads) void gtt_topk_kernel(const T* __restr
     constexpr int KB = 8 * sizeof(K);
     __shared__ uint32_t hist[256];
     __shared__ uint32_t wsum[kTopkThreads / 64];
+    __shared__ uint64_t sc[2][256];
     __shared__ K s_prefix;
     __shared__ int64_t s_remaining;
     const T* c = coef + (int64_t)blockIdx.x * N;
@@ -88,16 +128,9 @@ __global__ __launch_bounds__(kTopkThreads) void gtt_topk_kernel(const T* __restr
             if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t cum = 0;
-            int sel = 0;
-            for (int d = 255; d >= 0; --d) {
-                if (cum + (int64_t)hist[d] >= remaining) {
-                    sel = d;
-                    break;
-                }
-                cum += hist[d];
-            }
+        int sel;
+        int64_t cum;
+        if (topk_digit_choice(threadIdx.x < 256 ? hist[255 - threadIdx.x] : 0u, remaining, sc, &sel, &cum)) {
             s_prefix = prefix | ((K)sel << shift);
             s_remaining = remaining - cum;
         }
@@ -187,46 +220,21 @@ __global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_hist_kernel(const 
     if (h) atomicAdd(&ghist[t * 256 + threadIdx.x], h);
 }
 
-// The digit of the k-th largest key: the largest digit value d whose count
-// of keys with digit >= d reaches the keys still to be taken.  Thread i
-// holds digit 255 - i, so an inclusive scan over the threads gives every
-// digit's count from the top (P) and the count strictly above it (P - h);
-// the one thread where P first reaches `remaining` writes the state.
+// the digit choice of one instance from its global histogram (cleared for
+// the next digit on the way)
 template <typename K>
 __global__ __launch_bounds__(256) void gtt_topk_select_kernel(TopkState* st, uint32_t* ghist, int shift) {
     const int64_t t = blockIdx.x;
-    const int i = threadIdx.x;
     __shared__ uint64_t sc[2][256];
     const TopkState s0 = st[t];  // read by every thread before any write
-    const uint32_t hv = ghist[t * 256 + (255 - i)];
-    ghist[t * 256 + (255 - i)] = 0u;  // clean for the next digit
-    sc[0][i] = hv;
-    __syncthreads();
-    int cur = 0;
-    for (int off = 1; off < 256; off <<= 1) {
-        uint64_t v = sc[cur][i];
-        if (i >= off) v += sc[cur][i - off];
-        sc[cur ^ 1][i] = v;
-        cur ^= 1;
-        __syncthreads();
-    }
-    const int64_t P = (int64_t)sc[cur][i], above = P - (int64_t)hv;
-    const int64_t remaining = s0.remaining;
-    int sel = -1;
-    int64_t cum = 0;
-    if (P >= remaining && (i == 0 || above < remaining)) {
-        sel = 255 - i;
-        cum = above;
-    } else if (i == 255 && P < remaining) {
-        // fewer keys than still to be taken (cannot happen for k <= N):
-        // take digit 0 and everything above it
-        sel = 0;
-        cum = P;
-    }
-    if (sel >= 0) {
+    const uint32_t hv = ghist[t * 256 + (255 - threadIdx.x)];
+    ghist[t * 256 + (255 - threadIdx.x)] = 0u;
+    int sel;
+    int64_t cum;
+    if (topk_digit_choice(hv, s0.remaining, sc, &sel, &cum)) {
         st[t].prefix = (uint64_t)((K)s0.prefix | ((K)sel << shift));
         st[t].pmask = (uint64_t)((K)s0.pmask | ((K)255 << shift));
-        st[t].remaining = remaining - cum;
+        st[t].remaining = s0.remaining - cum;
     }
 }
 
@@ -271,23 +279,22 @@ __global__ __launch_bounds__(256) void gtt_topk_scan_kernel(const TopkState* __r
         g += ct[2 * c];
         e += ct[2 * c + 1];
     }
-    sg[threadIdx.x] = g;
-    se[threadIdx.x] = e;
-    __syncthreads();
-    if (threadIdx.x == 0) {  // exclusive scan of the 256 ranges, in order
-        int64_t rg = 0, re = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int64_t vg = sg[i], ve = se[i];
-            sg[i] = rg;
-            se[i] = re;
-            rg += vg;
-            re += ve;
+    // exclusive scan of the 256 ranges, in order: an inclusive scan over the
+    // threads, then each range's own counts taken off
+    const int64_t g0 = g, e0 = e;
+    for (int o = 1; o < 256; o <<= 1) {
+        sg[threadIdx.x] = g;
+        se[threadIdx.x] = e;
+        __syncthreads();
+        if ((int)threadIdx.x >= o) {
+            g += sg[threadIdx.x - o];
+            e += se[threadIdx.x - o];
         }
+        __syncthreads();
     }
-    __syncthreads();
     const int64_t need_eq = st[t].remaining;
-    g = sg[threadIdx.x];
-    e = se[threadIdx.x];
+    g -= g0;
+    e -= e0;
     int64_t* ot = off + t * nch * 2;
     for (int64_t c = a; c < b; ++c) {
         ot[2 * c] = g + (e < need_eq ? e : need_eq);  // output position of the chunk's first element
