@@ -305,11 +305,14 @@ __global__ __launch_bounds__(256) void gtt_topk_scan_kernel(const TopkState* __r
 }
 
 // per chunk: its elements above the threshold and the equal ones still
-// needed, in index order, at the chunk's output offset
+// needed, in index order, at the chunk's output offset; with rec, also the
+// chunk of the dense sparse vector (kept values, zeros elsewhere), which
+// replaces a zero fill and a scatter (a chunk reads and writes only its own
+// elements, so rec may be coef)
 template <typename T>
 __global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_write_kernel(
-    const T* __restrict__ coef, int64_t N, int64_t nch, const TopkState* __restrict__ st,
-    const int64_t* __restrict__ off, int64_t k, int64_t* __restrict__ idx, T* __restrict__ val) {
+    const T* coef, int64_t N, int64_t nch, const TopkState* __restrict__ st, const int64_t* __restrict__ off,
+    int64_t k, int64_t* __restrict__ idx, T* __restrict__ val, T* rec) {
     using K = typename TopkKey<T>::K;
     __shared__ uint32_t wsum[kTopkChunkThreads / 64];
     const int64_t t = blockIdx.y;
@@ -325,7 +328,8 @@ __global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_write_kernel(
     for (int64_t base = c0; base < c1; base += kTopkChunkThreads) {  // uniform loop
         const int64_t i = base + threadIdx.x;
         const bool in = i < c1;
-        const K key = in ? topk_key(c[i]) : (K)0;
+        const T v = in ? c[i] : from_c<T>(czero<typename Tr<T>::C>());
+        const K key = in ? topk_key(v) : (K)0;
         const bool gt = in && key > thr;
         const bool eq = in && key == thr;
         uint32_t eq_tot;
@@ -335,8 +339,9 @@ __global__ __launch_bounds__(kTopkChunkThreads) void gtt_topk_write_kernel(
         const uint32_t pos = block_excl_count<kTopkChunkThreads>(take, wsum, &take_tot);
         if (take) {
             oi[out + pos] = i;
-            ov[out + pos] = c[i];
+            ov[out + pos] = v;
         }
+        if (rec && in) rec[t * N + i] = take ? v : from_c<T>(czero<typename Tr<T>::C>());
         eq_seen += eq_tot;
         out += take_tot;
     }

@@ -6,7 +6,7 @@ namespace gtt {
 
 template <typename T>
 static hipError_t topk_chunked_t(const T* coef, int64_t N, int64_t batch, int64_t k, int64_t* idx, T* val,
-                                 void* meta, hipStream_t s) {
+                                 T* recon, void* meta, hipStream_t s) {
     using K = typename TopkKey<T>::K;
     const int64_t nch = (N + kTopkChunk - 1) / kTopkChunk;
     auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -30,7 +30,7 @@ static hipError_t topk_chunked_t(const T* coef, int64_t N, int64_t batch, int64_
     hipLaunchKernelGGL(gtt_topk_scan_kernel, dim3((unsigned)batch), dim3(256), 0, s, (const TopkState*)st,
                        (const uint32_t*)cnt, off, nch);
     hipLaunchKernelGGL(gtt_topk_write_kernel<T>, grid, dim3(kTopkChunkThreads), 0, s, coef, N, nch,
-                       (const TopkState*)st, (const int64_t*)off, k, idx, val);
+                       (const TopkState*)st, (const int64_t*)off, k, idx, val, recon);
     return hipGetLastError();
 }
 
@@ -39,7 +39,9 @@ static hipError_t topk_t(const void* coef, int64_t N, int64_t batch, int64_t k, 
                          void* recon, void* meta, hipStream_t s) {
     hipError_t e;
     if (topk_chunked(N, batch)) {
-        e = topk_chunked_t<T>(static_cast<const T*>(coef), N, batch, k, idx, static_cast<T*>(val), meta, s);
+        // the ordered write also fills the dense sparse vector
+        return topk_chunked_t<T>(static_cast<const T*>(coef), N, batch, k, idx, static_cast<T*>(val),
+                                 static_cast<T*>(recon), meta, s);
     } else {
         hipLaunchKernelGGL(gtt_topk_kernel<T>, dim3((unsigned)batch), dim3(kTopkThreads), 0, s,
                            static_cast<const T*>(coef), N, k, idx, static_cast<T*>(val));
